@@ -1,0 +1,366 @@
+"""Pins of the whole oracle step against exact solutions, invariants and a textbook scheme.
+
+* uniform flow is a fixed point, bitwise (the pair-ordered sums cancel exactly);
+* with uniform p and u the step reduces to the textbook minmod (Fromm-type)
+  advection scheme, because Q of Eq. (7) vanishes and every particle moves by u dt;
+* mass, momentum and energy are conserved to round-off on a periodic box (Eq. (4)
+  is in flux form and the pair terms of Eq. (7) are antisymmetric);
+* the hydrostatic state rho = 1 - psi, p = rho^2/2 stays at rest (the well-balanced
+  claim of the abstract and Sec. 1), while an isothermal atmosphere does not;
+* Sod's tube and the gas-vacuum tube of Sec. 2.3 match the exact Riemann solution;
+* smooth advection converges at second order (the order claim of Sec. 2.3);
+* the scheme is symmetric under axis permutations and mirrors.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import exact_riemann as ER
+from paper_1912_04855_amd import problems as P
+
+from helpers import l1_rel, oracle_sim, orders
+
+
+# ---------------------------------------------------------------- exact Riemann solver
+def test_exact_riemann_sod_star_state():
+    """Toro, Riemann Solvers and Numerical Methods for Fluid Dynamics, Test 1 (Sod)."""
+    w = ER.waves((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+    assert w["p_star"] == pytest.approx(0.30313, abs=5e-6)
+    assert w["u_star"] == pytest.approx(0.92745, abs=5e-6)
+    assert w["rho_star_L"] == pytest.approx(0.42632, abs=5e-6)
+    assert w["rho_star_R"] == pytest.approx(0.26557, abs=5e-6)
+    # Rankine-Hugoniot across the right shock: mass flux continuity
+    S = w["S_R"]
+    assert 0.125 * (0.0 - S) == pytest.approx(w["rho_star_R"] * (w["u_star"] - S), rel=1e-12)
+    # the left rarefaction is isentropic
+    assert w["p_star"] / w["rho_star_L"] ** 1.4 == pytest.approx(1.0, rel=1e-12)
+
+
+def test_exact_riemann_vacuum_closed_form():
+    g = 5.0 / 3.0
+    cl = math.sqrt(g)
+    r, u, p = ER.sample((1.0, 0.0, 1.0), (0.0, 0.0, 0.0), g, np.array([0.0, -cl - 1e-9, 3 * cl - 1e-12]))
+    assert r[0] == pytest.approx((2.0 / (g + 1.0)) ** (2.0 / (g - 1.0)), rel=1e-14)  # 0.421875
+    assert r[0] == pytest.approx(0.421875, rel=1e-14)
+    assert u[0] == pytest.approx(2.0 / (g + 1.0) * cl, rel=1e-14)
+    assert r[1] == 1.0
+    assert r[2] < 1e-20
+
+
+# ---------------------------------------------------------------- invariants
+def test_uniform_flow_is_bitwise_fixed_point():
+    pr = P.uniform_flow((8, 6, 5))
+    s = oracle_sim(pr)
+    U0 = s.conserved()
+    for _ in range(20):
+        s.step()
+    assert np.array_equal(s.conserved(), U0)
+
+
+def test_reduces_to_textbook_minmod_advection():
+    """Q = 0 exactly for uniform p and u; every particle moves by u dt, and the step
+    is the classical piecewise-linear minmod update
+       U_i - nu [(U_i + (1-nu) d_i / 2) - (U_{i-1} + (1-nu) d_{i-1} / 2)]."""
+    n = 64
+    pr = P.advected_density(n, amp=0.3, u=(0.7, 0.0, 0.0), p0=2.0)
+    s = oracle_sim(pr)
+    rho = pr.prim[0][0, 0, :].copy()
+    u, h = 0.7, pr.h
+    for _ in range(15):
+        dt = s.step()
+        nu = u * dt / h
+        a = np.roll(rho, -1) - rho
+        b = rho - np.roll(rho, 1)
+        d = np.where(a * b > 0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
+        UL = rho + 0.5 * (1 - nu) * d
+        rho = rho - nu * (UL - np.roll(UL, 1))
+    got = s.conserved()[0]
+    assert np.max(np.abs(got - rho[None, None, :])) <= 1e-13
+    assert np.max(np.abs(got - got[:1, :1, :])) == 0.0
+
+
+@pytest.mark.parametrize("potential", [False, True])
+def test_conservation_periodic(potential):
+    pr = P.random_state((12, 10, 8), seed=11, potential=potential)
+    s = oracle_sim(pr)
+    s.step()
+    T0 = s.totals()
+    for _ in range(30):
+        s.step()
+    T1 = s.totals()
+    assert abs(T1[0] - T0[0]) <= 1e-13 * abs(T0[0])
+    if not potential:  # an external force changes momentum and energy
+        scale = np.sum(np.abs(pr.prim[0] * pr.prim[1:4])) * pr.h ** 3
+        assert np.all(np.abs(T1[1:4] - T0[1:4]) <= 1e-13 * scale)
+        assert abs(T1[4] - T0[4]) <= 1e-13 * abs(T0[4])
+
+
+@pytest.mark.parametrize("gamma,steps", [(2.0, 400), (5.0 / 3.0, 100)])
+def test_well_balanced_rest(gamma, steps):
+    """rho = 1 - psi, p = rho^2/2 is the discrete equilibrium for any gamma.  With
+    gamma = 2 it is isentropic (neutrally buoyant) and is held for long runs; with
+    gamma = 5/3 the entropy falls outward, so the state is convectively unstable
+    (Schwarzschild) and round-off grows at the physical rate: a shorter run."""
+    pr = P.well_rest(20, gamma=gamma)
+    s = oracle_sim(pr)
+    U0 = s.conserved()
+    for _ in range(steps):
+        s.step()
+    W = s.primitive()
+    U = s.conserved()
+    assert np.max(np.abs(W[1:4])) <= 1e-13
+    assert np.max(np.abs(U[0] - U0[0])) <= 1e-12 * np.max(U0[0])
+    assert np.max(np.abs(U[4] - U0[4])) <= 1e-12 * np.max(U0[4])
+
+
+def test_rest_noise_is_damped():
+    """Velocity noise on a uniform gas at rest decays: the acoustic dissipation of the
+    face flux damps what the central 27-point sums and the RK2 pair leave undamped."""
+    pr = P.uniform_flow((12, 12, 12), u=(0.0, 0.0, 0.0))
+    rng = np.random.default_rng(0)
+    pr.prim[1:4] = 1e-6 * rng.standard_normal(pr.prim[1:4].shape)
+    s = oracle_sim(pr)
+    u0 = np.max(np.abs(pr.prim[1:4]))
+    for _ in range(100):
+        s.step()
+    assert np.max(np.abs(s.primitive()[1:4])) < 0.1 * u0
+
+
+def test_well_balance_control_isothermal_moves():
+    """An isothermal atmosphere is not the discrete equilibrium: it must visibly move,
+    which shows that the rest test above has teeth."""
+    pr = P.isothermal_rest(20)
+    s = oracle_sim(pr)
+    for _ in range(50):
+        s.step()
+    assert np.max(np.abs(s.primitive()[1:4])) > 1e-4
+
+
+def test_well_balanced_outflow_boundaries():
+    pr = P.well_rest(16, gamma=2.0, bc=(P.OUTFLOW,) * 6)
+    s = oracle_sim(pr)
+    for _ in range(100):
+        s.step()
+    assert np.max(np.abs(s.primitive()[1:4])) <= 1e-12
+
+
+# ---------------------------------------------------------------- shock tubes
+def _crossing(x, f, level):
+    """First x where the piecewise-linear f crosses level (f decreasing overall)."""
+    for i in range(len(f) - 1):
+        if (f[i] - level) * (f[i + 1] - level) <= 0 and f[i] != f[i + 1]:
+            return x[i] + (level - f[i]) / (f[i + 1] - f[i]) * (x[i + 1] - x[i])
+    return None
+
+
+def _sod(n):
+    pr = P.sod(n)
+    s = oracle_sim(pr)
+    s.advance(pr.t_end)
+    t, _ = s.time()
+    assert t == pr.t_end
+    return s.primitive()[:, 0, 0, :], pr
+
+
+def test_sod_wave_positions_within_one_cell():
+    n = 256
+    W, pr = _sod(n)
+    x = (np.arange(n) + 0.5) / n
+    edges = np.arange(n + 1) / n
+    r, u, p = ER.cell_average((1, 0, 1), (0.125, 0, 0.1), 1.4, edges, 0.5, 0.2)
+    # levels inside: rarefaction head region, rarefaction tail, contact, shock
+    for lev, lo, hi in [(0.9, 0.0, 0.5), (0.5, 0.3, 0.6), (0.346, 0.55, 0.8), (0.195, 0.75, 1.0)]:
+        m = (x > lo) & (x < hi)
+        xn = _crossing(x[m], W[0][m], lev)
+        xe = _crossing(x[m], r[m], lev)
+        assert xn is not None and xe is not None
+        assert abs(xn - xe) <= 1.0 / n, (lev, xn, xe)
+    # the pressure and velocity plateaus
+    star = (x > 0.72) & (x < 0.82)
+    assert np.max(np.abs(W[4][star] - 0.30313)) < 0.01
+    assert np.max(np.abs(W[1][star] - 0.92745)) < 0.02
+
+
+def test_sod_l1_converges():
+    errs = []
+    for n in (64, 128, 256):
+        W, pr = _sod(n)
+        edges = np.arange(n + 1) / n
+        r, u, p = ER.cell_average((1, 0, 1), (0.125, 0, 0.1), 1.4, edges, 0.5, 0.2)
+        errs.append(np.mean(np.abs(W[0] - r)))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 4e-3
+
+
+def test_vacuum_tube():
+    """Gas (rho = p = 1) expanding into vacuum, gamma = 5/3 (Sec. 2.3, Fig. 2 setup)."""
+    g = 5.0 / 3.0
+    errs = []
+    for n in (100, 200, 400):
+        pr = P.vacuum_tube(n, t_end=0.1)
+        s = oracle_sim(pr)
+        M0 = np.sum(pr.prim[0])
+        s.advance(pr.t_end)
+        W = s.primitive()[:, 0, 0, :]
+        assert np.min(W[0]) >= 0.0
+        # the numerical front runs ahead of the exact one (0.887 at t = 0.1) with an
+        # exponentially thin precursor; what reaches the far outflow face is < 1e-5
+        assert np.sum(s.conserved()[0][0, 0, :]) == pytest.approx(M0 / 16, rel=1e-5)
+        edges = np.arange(n + 1) / n
+        r, u, p = ER.cell_average((1, 0, 1), (0, 0, 0), g, edges, 0.5, 0.1)
+        errs.append(np.mean(np.abs(W[0] - r)))
+        x = (np.arange(n) + 0.5) / n
+        # a level inside the rarefaction fan, away from the sonic point x0
+        m = x < 0.49
+        xn, xe = _crossing(x[m], W[0][m], 0.8), _crossing(x[m], r[m], 0.8)
+        assert abs(xn - xe) <= 1.0 / n
+    assert errs[0] > errs[1] > errs[2]
+
+
+# ---------------------------------------------------------------- convergence
+def _advection_error(n, limiter):
+    pr = P.advected_density(n, t_end=0.5)
+    s = oracle_sim(pr, limiter=limiter)
+    s.advance(pr.t_end)
+    rho = s.conserved()[0][0, 0, :]
+    x = (np.arange(n) + 0.5) / n
+    h = 1.0 / n
+    exact = 1 + 0.2 * (np.cos(2 * math.pi * (x - h / 2 - 0.5)) - np.cos(2 * math.pi * (x + h / 2 - 0.5))) / (2 * math.pi * h)
+    return np.mean(np.abs(rho - exact))
+
+
+@pytest.mark.parametrize("limiter,min_order", [(O.LIM_MINMOD, 1.8), (O.LIM_MC, 1.95)])
+def test_second_order_smooth_advection(limiter, min_order):
+    errs = [_advection_error(n, limiter) for n in (32, 64, 128, 256)]
+    assert orders(errs)[-1] >= min_order, errs
+
+
+def test_acoustic_wave_converges():
+    """A right-going acoustic simple wave on a background flow: the step converges,
+    at first order (the remap of rigid particles and the displaced-kernel sum of the
+    corrector both carry O(h) terms for a compressive velocity field)."""
+    errs = []
+    for n in (32, 64, 128):
+        pr = P.acoustic_wave(n, t_end=0.25)
+        s = oracle_sim(pr)
+        s.advance(pr.t_end)
+        rho = s.conserved()[0][0, 0, :]
+        c = math.sqrt(1.4)
+        x = (np.arange(n) + 0.5) / n
+        ph = (0.5 + c) * 0.25
+        ex = 1 + 1e-6 * (np.cos(2 * math.pi * (x - 0.5 / n - ph)) - np.cos(2 * math.pi * (x + 0.5 / n - ph))) * n / (2 * math.pi)
+        errs.append(np.mean(np.abs(rho - ex)))
+    o = orders(errs)
+    assert all(k >= 0.9 for k in o), o
+
+
+# ---------------------------------------------------------------- symmetry
+def test_sod_axis_permutation_symmetry():
+    sols = []
+    for axis in range(3):
+        pr = P.sod(32, axis=axis, transverse=4)
+        s = oracle_sim(pr)
+        s.advance(pr.t_end)
+        U = s.conserved()
+        # bring the tube axis to x
+        perm = {0: (0, 1, 2), 1: (0, 2, 1), 2: (2, 1, 0)}[axis]
+        Ur = np.transpose(U, (0,) + tuple(1 + np.array(perm)))
+        mom = [1 + axis] + [1 + a for a in range(3) if a != axis]
+        sols.append((Ur[0], Ur[mom[0]], Ur[4]))
+    for k in (1, 2):
+        for a, b in zip(sols[0], sols[k]):
+            assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(sols[0][0]))
+
+
+def test_mirror_symmetry():
+    pr = P.riemann_tube(40, left=(0.125, 0.0, 0.1), right=(1.0, 0.0, 1.0))
+    prm = P.sod(40)
+    s1, s2 = oracle_sim(pr), oracle_sim(prm)
+    for _ in range(30):
+        s1.step()
+        s2.step()
+    U1, U2 = s1.conserved(), s2.conserved()
+    np.testing.assert_allclose(U1[0][..., ::-1], U2[0], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(-U1[1][..., ::-1], U2[1], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(U1[4][..., ::-1], U2[4], rtol=1e-13, atol=1e-15)
+
+
+def test_sedov_octahedral_symmetry_and_energy():
+    pr = P.sedov((16, 16, 16))
+    s = oracle_sim(pr)
+    s.step()
+    E0 = s.totals()[4]
+    for _ in range(12):
+        s.step()
+    U = s.conserved()
+    rho = U[0]
+    ref = np.max(np.abs(rho))
+    for perm in ((0, 2, 1), (1, 0, 2), (2, 1, 0)):
+        assert np.max(np.abs(np.transpose(rho, perm) - rho)) <= 1e-12 * ref
+    assert np.max(np.abs(rho[::-1] - rho)) <= 1e-12 * ref
+    assert abs(s.totals()[4] - E0) <= 1e-12 * E0
+    assert np.max(rho) > 1.2  # a compressed shell has formed
+
+
+def test_potential_well_flow_mirror_symmetric():
+    pr = P.well_flow(16)
+    s = oracle_sim(pr)
+    for _ in range(10):
+        s.step()
+    U = s.conserved()
+    ref = np.max(np.abs(U[0]))
+    # y -> -y about the well centre: the grid is symmetric about 0.5
+    np.testing.assert_allclose(U[0][:, ::-1, :], U[0], rtol=0, atol=1e-12 * ref)
+    np.testing.assert_allclose(-U[2][:, ::-1, :], U[2], rtol=0, atol=1e-12 * ref)
+    np.testing.assert_allclose(np.transpose(U[0], (1, 0, 2)), U[0], rtol=0, atol=1e-12 * ref)
+
+
+def test_cloud_keeps_vacuum_non_negative_and_mass():
+    pr = P.cloud(24, seed=3)
+    assert pr.rho_vac == 1e-6
+    s = oracle_sim(pr)
+    M0 = np.sum(pr.prim[0])
+    for _ in range(15):
+        s.step()
+    U = s.conserved()
+    assert np.min(U[0]) >= 0.0
+    assert np.sum(U[0]) == pytest.approx(M0, rel=1e-13)
+
+
+def test_advance_lands_on_t_end_and_checkpoint():
+    pr = P.sod(32)
+    a = oracle_sim(pr)
+    n = a.advance(0.05)
+    assert a.time()[0] == 0.05 and a.time()[1] == n
+    b = oracle_sim(pr)
+    b.advance(0.025)
+    c = oracle_sim(pr)
+    c.set_conserved(b.conserved())
+    c.set_time(*b.time())
+    c.advance(0.05)
+    d = oracle_sim(pr)
+    d.advance(0.025)
+    d.advance(0.05)
+    assert np.array_equal(c.conserved(), d.conserved())
+
+
+def test_error_paths():
+    pr = P.uniform_flow((4, 4, 4), u=(0, 0, 0))
+    s = oracle_sim(pr)
+    W = pr.prim.copy()
+    W[0, 0, 0, 0] = -1.0
+    with pytest.raises(O.OracleError):
+        s.set_primitive(W)
+    # a state with no signal speed needs an explicit dt
+    z = O.OracleSim((4, 4, 4), 0.25)
+    z.set_conserved(np.zeros((5, 4, 4, 4)))
+    with pytest.raises(O.OracleError):
+        z.step()
+    U = s.conserved()
+    U[4, 1, 1, 1] = np.nan
+    s.set_conserved(U)
+    with pytest.raises(O.OracleError) as e:
+        s.step(dt_max=1e-3)
+    assert e.value.code in (5,)
