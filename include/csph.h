@@ -1,0 +1,167 @@
+/*
+ * csph.h -- C ABI of the MI355X CSPH-TVD library.
+ *
+ * The library advances the 3D Euler equations of an ideal gas in a static
+ * external potential psi with the CSPH-TVD scheme of Khrapov, Khoperskov and
+ * Khoperskov (arXiv:1912.04855): a Lagrangian predictor-corrector stage that
+ * moves one particle per cell under the pressure and potential forces
+ * (Sec. 2.2, Eqs. (5)-(7)), then an Eulerian stage that remaps the particles
+ * onto the fixed grid with TVD-limited, offset-shifted reconstructions
+ * (Eqs. (8) and (4)), with a global CFL time step.
+ *
+ * Conventions shared by every call:
+ *  - All entry points return csph_status (0 = success).  No C++ exception
+ *    crosses this interface.  On failure csph_last_error() describes the cause
+ *    (thread-local text, valid until the next call on the same thread).
+ *  - Host arrays are FP64, structure of arrays, x fastest:
+ *      state  [5][nz][ny][nx]  CONSERVED (rho, rho u, rho v, rho w, E)
+ *                              or PRIMITIVE (rho, u, v, w, p), E = rho(|u|^2/2 + eps),
+ *                              p = (gamma - 1) rho eps  (Sec. 2.1)
+ *      psi    [nz][ny][nx]     cell-centred potential (force f = -grad psi, Sec. 2.1)
+ *    The caller owns host arrays; every copy is complete when the call returns.
+ *  - Device state lives in one device allocation per simulation, either owned
+ *    by the library (csph_create) or lent by the caller (csph_create_in).  The
+ *    arithmetic type of the stored state and of the kernels is desc->dtype.
+ *  - Work is issued on the HIP stream given at creation (NULL = the null
+ *    stream).  Calls that return host data synchronise that stream.
+ *  - A simulation is not thread-safe: one thread at a time per csph_sim.
+ */
+#ifndef CSPH_H
+#define CSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t csph_status;
+enum {
+  CSPH_OK = 0,
+  CSPH_ERR_ARG = 1,          /* invalid argument (message says which)              */
+  CSPH_ERR_NOMEM = 2,        /* device allocation failed                            */
+  CSPH_ERR_DEVICE = 3,       /* a HIP runtime call failed                           */
+  CSPH_ERR_STATE = 4,        /* the simulation holds a sticky error; set_state clears it */
+  CSPH_ERR_NONFINITE = 5,    /* a non-finite value appeared in the new state        */
+  CSPH_ERR_NEG_DENSITY = 6,  /* rho < -0.01 rho_vac appeared in the new state       */
+  CSPH_ERR_NO_SIGNAL = 7,    /* no non-vacuum cell: the CFL step needs dt_max > 0   */
+  CSPH_ERR_BUDGET = 8,       /* a batch would exceed its device-memory budget       */
+};
+
+typedef enum { CSPH_F32 = 0, CSPH_F64 = 1 } csph_dtype;
+typedef enum { CSPH_PERIODIC = 0, CSPH_OUTFLOW = 1, CSPH_INFLOW = 2, CSPH_REFLECT = 3 } csph_bc;
+typedef enum { CSPH_CONSERVED = 0, CSPH_PRIMITIVE = 1 } csph_vars;
+
+/* Grid and gas.  One spacing h on all three axes (Sec. 2.2: x_i = x_{i-1} + h,
+ * likewise y and z).  nx, ny, nz >= 4; h > 0; gamma > 1; 0 < cfl <= 0.5;
+ * rho_vac >= 0 (cells with rho <= rho_vac are vacuum: zero velocity, left out of
+ * the CFL maximum).  The time step is dt = cfl h / max(c + |u| + |v| + |w|). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double h;
+  double origin[3];
+  double gamma;
+  double cfl;
+  double rho_vac;
+  int32_t dtype;   /* csph_dtype */
+} csph_grid_desc;
+
+typedef struct csph_sim csph_sim;
+typedef struct csph_batch csph_batch;
+
+/* Device bytes one simulation needs (state, potential, stage scratch, control
+ * block), for admission decisions and csph_create_in.  0 for an invalid desc. */
+size_t csph_required_bytes(const csph_grid_desc* desc);
+
+/* Create a simulation; the library allocates and owns its device memory.
+ * Boundaries start PERIODIC on all faces, psi = 0, state = 0, t = 0.
+ * Errors: CSPH_ERR_ARG (bad desc or NULL out), CSPH_ERR_NOMEM, CSPH_ERR_DEVICE. */
+csph_status csph_create(const csph_grid_desc* desc, void* hip_stream, csph_sim** out);
+
+/* Same, in caller-owned device memory dev_buf of `bytes` bytes (e.g. a torch
+ * tensor's data pointer) that must outlive the simulation; it is not freed by
+ * csph_destroy.  CSPH_ERR_ARG if bytes < csph_required_bytes(desc) or dev_buf
+ * is not 256-byte aligned. */
+csph_status csph_create_in(const csph_grid_desc* desc, void* hip_stream, void* dev_buf,
+                           size_t bytes, csph_sim** out);
+
+/* Free what the library owns.  NULL is accepted. */
+csph_status csph_destroy(csph_sim* sim);
+
+/* Change the stream later work is issued on (NULL = null stream). */
+csph_status csph_set_stream(csph_sim* sim, void* hip_stream);
+
+/* Set the interior state from host FP64 `[5][nz][ny][nx]`.  PRIMITIVE input is
+ * converted to conserved on the host in FP64 (m = rho u,
+ * E = p/(gamma-1) + rho |u|^2/2), then rounded to the storage type.  Rejects
+ * rho < 0 or (PRIMITIVE) p < 0 with CSPH_ERR_ARG.  Clears a sticky error. */
+csph_status csph_set_state(csph_sim* sim, csph_vars vars, const double* host);
+
+/* Set the cell-centred potential psi `[nz][ny][nx]`; NULL means psi = 0.  Its
+ * ghost cells follow the boundary rules with inflow faces copying like outflow,
+ * so set the boundaries first (or call this again after changing them). */
+csph_status csph_set_potential(csph_sim* sim, const double* host_psi);
+
+/* Boundary rule of one face: 0..5 = -x, +x, -y, +y, -z, +z.  PERIODIC must be set
+ * on both faces of an axis before stepping.  inflow_prim = (rho, u, v, w, p) is
+ * read only for CSPH_INFLOW (a Dirichlet state whose particles move by u dt). */
+csph_status csph_set_boundary(csph_sim* sim, int32_t face, csph_bc kind,
+                              const double inflow_prim[5]);
+
+/* One step with dt = min(CFL dt, dt_max if dt_max > 0).  dt_taken may be NULL;
+ * when it is not, the call synchronises and stores the step taken.  Errors found
+ * in the new state (CSPH_ERR_NONFINITE, CSPH_ERR_NEG_DENSITY, CSPH_ERR_NO_SIGNAL)
+ * are reported by the next synchronising call and make the error sticky. */
+csph_status csph_step(csph_sim* sim, double dt_max, double* dt_taken);
+
+/* Step until t == t_end exactly (the last step is shortened to land on it) or
+ * until max_steps steps; t_end = +inf gives a fixed step count.  The step loop
+ * runs on the device; the host polls a completion flag every few steps.
+ * steps_taken may be NULL.  Synchronises. */
+csph_status csph_advance(csph_sim* sim, double t_end, int64_t max_steps, int64_t* steps_taken);
+
+/* Read the interior state into caller-owned host FP64 `[5][nz][ny][nx]`. */
+csph_status csph_get_state(const csph_sim* sim, csph_vars vars, double* host_out);
+
+/* Time and step count of the current state; restore them for checkpoint/resume. */
+csph_status csph_get_time(const csph_sim* sim, double* t, int64_t* nsteps);
+csph_status csph_set_time(csph_sim* sim, double t, int64_t nsteps);
+
+/* FP64 totals (mass, x/y/z momentum, energy) x h^3 of the state written by the
+ * last step, summed on the device in a fixed order. */
+csph_status csph_totals(const csph_sim* sim, double out[5]);
+
+/* Intermediate fields of the last step, interior only, host FP64 `[nz][ny][nx]`:
+ * which = 0..3 m*, E* (predictor, Eq. (5)); 4..6 xi* (predicted particle offset);
+ * 7..10 m~, E~ (corrector, Eq. (6)); 11..13 xi^{n+1} (final particle offset). */
+csph_status csph_get_stage(const csph_sim* sim, int32_t which, double* host_out);
+
+const char* csph_last_error(void);
+
+/* ---------------- batches: many simulations advanced together ---------------
+ * A batch references simulations of one dtype; it does not own them, and each
+ * must outlive its membership.  Every member keeps its own dt, t and step
+ * target; members of different sizes are flattened into one tile list, and one
+ * launch per stage advances all of them.  hbm_budget bounds the summed
+ * csph_required_bytes of the members (0 = unbounded). */
+csph_status csph_batch_create(csph_dtype dtype, void* hip_stream, size_t hbm_budget,
+                              csph_batch** out);
+/* Add a member that stops after `steps` more steps or at t_end (first reached).
+ * slot receives its index.  CSPH_ERR_BUDGET if the budget would be exceeded. */
+csph_status csph_batch_add(csph_batch* b, csph_sim* sim, int64_t steps, double t_end,
+                           int32_t* slot);
+/* Advance every unfinished member by up to k steps; n_done (may be NULL)
+ * receives the number of members finished so far.  Does not synchronise unless
+ * n_done is non-NULL. */
+csph_status csph_batch_advance(csph_batch* b, int32_t k_steps, int32_t* n_done);
+/* List finished members (up to cap slots) without removing them.  Synchronises. */
+csph_status csph_batch_poll(csph_batch* b, int32_t* done_slots, int32_t cap, int32_t* n);
+/* Remove a member (finished or not); its slot is reused by later adds. */
+csph_status csph_batch_remove(csph_batch* b, int32_t slot);
+csph_status csph_batch_destroy(csph_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,63 @@
+"""Build the HIP library libcsph.so for gfx950 (in-tree).
+
+The kernel source is compiled twice: once for FP32 state (contraction allowed)
+and once for FP64 state (no floating-point contraction, so every expression is
+rounded as written).  Packed FP32 instructions are switched off for all device
+code.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "csrc")
+INC = os.path.join(os.path.dirname(HERE), "include")
+OUT = os.path.join(HERE, "libcsph.so")
+BUILD = os.path.join(os.path.dirname(HERE), "_build")
+
+ARCH = os.environ.get("CSPH_OFFLOAD_ARCH", "gfx950")
+HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
+
+COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", SRC, "-I", INC,
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+
+UNITS = [
+    ("csph_kernels.hip", "k32.o", ["-DCSPH_REAL=float", "-DCSPH_IS_DOUBLE=0", "-ffp-contract=fast"]),
+    ("csph_kernels.hip", "k64.o", ["-DCSPH_REAL=double", "-DCSPH_IS_DOUBLE=1", "-ffp-contract=off"]),
+    ("csph_runtime.hip", "runtime.o", ["-ffp-contract=off"]),
+    ("csph_batch.hip", "batch.o", ["-ffp-contract=off"]),
+]
+
+
+def build(verbose=False, jobs=4):
+    os.makedirs(BUILD, exist_ok=True)
+    procs = []
+    objs = []
+    for src, obj, flags in UNITS:
+        o = os.path.join(BUILD, obj)
+        objs.append(o)
+        cmd = [HIPCC, *COMMON, *flags, "-c", os.path.join(SRC, src), "-o", o]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+        if len(procs) >= jobs:
+            cmd0, p0 = procs.pop(0)
+            if p0.wait() != 0:
+                raise RuntimeError("compile failed: " + " ".join(cmd0))
+    for cmd, p in procs:
+        if p.wait() != 0:
+            raise RuntimeError("compile failed: " + " ".join(cmd))
+    tmp = OUT + ".tmp"
+    link = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

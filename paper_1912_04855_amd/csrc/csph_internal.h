@@ -1,0 +1,100 @@
+// csph_internal.h -- structures shared by the host runtime and the HIP kernels.
+//
+// Data layout in HBM (one simulation): every field is a padded 3D array of
+// (nx+4) x (ny+4) x (nz+4) cells (two ghost layers per face), x fastest, one
+// array per field (structure of arrays), each starting on a 256-byte boundary.
+// Fields: two copies of the conserved state U = (rho, mx, my, mz, E) used in
+// turn as U^n and U^{n+1}; psi; the predictor output (m*, E*, xi*); the
+// corrector output (m~, E~, xi^{n+1}).  The density never changes in the
+// Lagrangian stage, so rho* = rho~ = rho^n is not stored.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace csph {
+
+constexpr int kGhost = 2;
+
+// roles of a field for the ghost-cell rules
+enum Role : int {
+  kRho = 0, kMx = 1, kMy = 2, kMz = 3, kE = 4, kXx = 5, kXy = 6, kXz = 7, kPsi = 8
+};
+enum Bc : int { kPeriodic = 0, kOutflow = 1, kInflow = 2, kReflect = 3 };
+
+// status bits raised on the device (sticky until set_state)
+enum : int { kBadNonFinite = 1, kBadNegDensity = 2, kBadNoSignal = 4 };
+
+struct GridDev {
+  int nx, ny, nz;
+  int sx, sy, sz;        // padded extents
+  long long sxy;         // sx * sy
+  long long ncell;       // padded cell count
+  double h, inv_h, h3;
+  double gamma, gm1;     // gamma, gamma - 1
+  double rho_vac, neg_tol;
+  double cfl_h;          // cfl * h
+  double kappa_h2;       // kernel normalisation / h^2
+  // 13 lattice kernel gradients K(-h o), o in the half neighbour set
+  double klat[13][3];
+};
+
+struct BcDev {
+  int kind[6];
+  double cons[6][5];     // inflow conserved state per face
+  double vel[6][3];      // inflow velocity per face (particle offset = dt * vel)
+};
+
+// Per-simulation control block in device memory (FP64).
+struct Ctrl {
+  double t;                          // time of the current state
+  double dt;                         // step being taken
+  unsigned long long smax_bits[2];   // max signal speed (bits of a positive double)
+  long long nsteps;
+  int par;                           // which state copy holds U^n
+  int cur;                           // which smax slot belongs to U^n
+  int active;                        // the step being launched runs
+  int done;                          // t reached the requested end time
+  int status;                        // kBad* bits
+  int smax_valid;                    // smax_bits[cur] describes U^n
+  int pad[2];
+};
+
+template <typename Real>
+struct Fields {
+  Real* U[2][5];
+  Real* psi;
+  Real* ms[4];   // m*x, m*y, m*z, E*
+  Real* xs[3];   // xi*
+  Real* mt[4];   // m~x, m~y, m~z, E~
+  Real* xt[3];   // xi^{n+1}
+};
+
+// up to 7 fields filled by one ghost-cell launch
+template <typename Real>
+struct FillSet {
+  Real* f[8];
+  int role[8];
+  int n;
+};
+
+// launchers, instantiated for float and double by the kernel translation units
+template <typename Real>
+struct Launch {
+  static hipError_t fill_state(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+                               Ctrl* ctrl, hipStream_t s);
+  static hipError_t fill_psi(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+                             Ctrl* ctrl, hipStream_t s);
+  static hipError_t signal_max(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
+                               hipStream_t s);
+  // one full step: begin, ghosts, stage P, ghosts, stage C, ghosts, stage E, end
+  static hipError_t step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
+                         double* partials, double dt_max, double t_end, hipStream_t s);
+  static hipError_t totals(const GridDev& g, const double* partials, int nblocks, double* out,
+                           hipStream_t s);
+  static int stage_e_blocks(const GridDev& g);
+};
+
+}  // namespace csph

@@ -1,0 +1,622 @@
+// csph_runtime.hip -- host runtime behind the C ABI declared in include/csph.h.
+//
+// One simulation = one device allocation (library-owned or caller-lent) that
+// holds the padded fields, the FP64 control block and the per-block totals.
+// The time loop runs on the device: the step kernels read dt, t and the state
+// parity from the control block, so the host only enqueues launches and polls a
+// completion flag every few steps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/csph.h"
+#include "csph_internal.h"
+
+using namespace csph;
+
+namespace {
+
+thread_local std::string g_err;
+
+csph_status fail(csph_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(CSPH_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+constexpr int kNumFields = 25;  // U[2][5], psi, ms[4], xs[3], mt[4], xt[3]
+
+// kernel normalisation: kappa = 1 / (2 sum_{a,b in {-1,0,1}} g(q_ab)/q_ab),
+// q_ab = sqrt(1 + a^2 + b^2), g(q)/q of the M4 spline (27-point sum exact for
+// linear fields)
+double g_over_q(double q) {
+  if (q < 1.0) return 3.0 - 2.25 * q;
+  if (q < 2.0) {
+    const double t = 2.0 - q;
+    return 0.75 * t * t / q;
+  }
+  return 0.0;
+}
+
+double kernel_kappa() {
+  double sum = 0.0;
+  for (int a = -1; a <= 1; ++a)
+    for (int b = -1; b <= 1; ++b) sum += g_over_q(std::sqrt(1.0 + (double)(a * a) + (double)(b * b)));
+  return 1.0 / (2.0 * sum);
+}
+
+const int kHalf[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1},
+                          {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
+                          {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
+
+bool desc_ok(const csph_grid_desc* d, std::string* why) {
+  if (!d) {
+    *why = "desc is NULL";
+    return false;
+  }
+  if (d->nx < 4 || d->ny < 4 || d->nz < 4) {
+    *why = "nx, ny, nz must be >= 4";
+    return false;
+  }
+  if (!(d->h > 0.0) || !std::isfinite(d->h)) {
+    *why = "h must be > 0";
+    return false;
+  }
+  if (!(d->gamma > 1.0)) {
+    *why = "gamma must be > 1";
+    return false;
+  }
+  if (!(d->cfl > 0.0 && d->cfl <= 0.5)) {
+    *why = "cfl must be in (0, 0.5]";
+    return false;
+  }
+  if (!(d->rho_vac >= 0.0)) {
+    *why = "rho_vac must be >= 0";
+    return false;
+  }
+  if (d->dtype != CSPH_F32 && d->dtype != CSPH_F64) {
+    *why = "dtype must be CSPH_F32 or CSPH_F64";
+    return false;
+  }
+  const double cells = (double)(d->nx + 4) * (d->ny + 4) * (d->nz + 4);
+  if (cells > 4.0e9) {
+    *why = "grid too large";
+    return false;
+  }
+  return true;
+}
+
+struct Layout {
+  size_t field_bytes, fields_off, ctrl_off, partials_off, totals_off, total;
+  long long ncell;
+  int nblocks;
+};
+
+GridDev make_grid(const csph_grid_desc* d) {
+  GridDev g{};
+  g.nx = d->nx;
+  g.ny = d->ny;
+  g.nz = d->nz;
+  g.sx = d->nx + 2 * kGhost;
+  g.sy = d->ny + 2 * kGhost;
+  g.sz = d->nz + 2 * kGhost;
+  g.sxy = (long long)g.sx * g.sy;
+  g.ncell = g.sxy * g.sz;
+  g.h = d->h;
+  g.inv_h = 1.0 / d->h;
+  g.h3 = d->h * d->h * d->h;
+  g.gamma = d->gamma;
+  g.gm1 = d->gamma - 1.0;
+  g.rho_vac = d->rho_vac;
+  g.neg_tol = 0.01 * d->rho_vac;
+  g.cfl_h = d->cfl * d->h;
+  g.kappa_h2 = kernel_kappa() / (d->h * d->h);
+  // lattice gradients K(d) = -(kappa/h^2)(g(q)/q) d at d = -h o
+  for (int q = 0; q < 13; ++q) {
+    const double dx = -kHalf[q][0] * d->h, dy = -kHalf[q][1] * d->h, dz = -kHalf[q][2] * d->h;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double qq = std::sqrt(r2) * g.inv_h;
+    const double c = g.kappa_h2 * g_over_q(qq);
+    g.klat[q][0] = -(c * dx);
+    g.klat[q][1] = -(c * dy);
+    g.klat[q][2] = -(c * dz);
+  }
+  return g;
+}
+
+Layout make_layout(const csph_grid_desc* d) {
+  Layout L{};
+  const GridDev g = make_grid(d);
+  const size_t es = d->dtype == CSPH_F64 ? 8 : 4;
+  L.ncell = g.ncell;
+  L.field_bytes = align_up((size_t)g.ncell * es);
+  L.fields_off = 0;
+  L.ctrl_off = L.fields_off + (size_t)kNumFields * L.field_bytes;
+  L.nblocks = d->dtype == CSPH_F64 ? Launch<double>::stage_e_blocks(g) : Launch<float>::stage_e_blocks(g);
+  L.partials_off = L.ctrl_off + align_up(sizeof(Ctrl));
+  L.totals_off = L.partials_off + align_up((size_t)L.nblocks * 5 * sizeof(double));
+  L.total = L.totals_off + align_up(5 * sizeof(double));
+  return L;
+}
+
+}  // namespace
+
+struct csph_sim {
+  csph_grid_desc desc{};
+  hipStream_t stream = nullptr;
+  char* buf = nullptr;
+  bool owned = false;
+  int device = 0;
+  Layout L{};
+  GridDev g{};
+  BcDev bc{};
+  double inflow_prim[6][5]{};
+  Fields<float> f32{};
+  Fields<double> f64{};
+  Ctrl* ctrl = nullptr;
+  double* partials = nullptr;
+  double* totals_dev = nullptr;
+  bool psi_dirty = true;
+  bool need_smax = true;
+  bool stepped = false;  // partials describe the current state
+  std::vector<double> psi_host;  // interior psi, kept to refill ghosts after BC changes
+  bool has_psi = false;
+
+  bool is_f64() const { return desc.dtype == CSPH_F64; }
+  char* field_ptr(int k) const { return buf + L.fields_off + (size_t)k * L.field_bytes; }
+};
+
+namespace {
+
+template <typename Real>
+void bind_fields(csph_sim* s, Fields<Real>& F) {
+  int k = 0;
+  for (int p = 0; p < 2; ++p)
+    for (int v = 0; v < 5; ++v) F.U[p][v] = (Real*)s->field_ptr(k++);
+  F.psi = (Real*)s->field_ptr(k++);
+  for (int v = 0; v < 4; ++v) F.ms[v] = (Real*)s->field_ptr(k++);
+  for (int v = 0; v < 3; ++v) F.xs[v] = (Real*)s->field_ptr(k++);
+  for (int v = 0; v < 4; ++v) F.mt[v] = (Real*)s->field_ptr(k++);
+  for (int v = 0; v < 3; ++v) F.xt[v] = (Real*)s->field_ptr(k++);
+}
+
+csph_status read_ctrl(const csph_sim* s, Ctrl* out) {
+  HIP_TRY(hipMemcpyAsync(out, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CSPH_OK;
+}
+
+csph_status write_ctrl(csph_sim* s, const Ctrl& c) {
+  HIP_TRY(hipMemcpyAsync(s->ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CSPH_OK;
+}
+
+csph_status status_from_bits(int bits) {
+  if (bits & kBadNonFinite) return fail(CSPH_ERR_NONFINITE, "a non-finite value appeared in the state");
+  if (bits & kBadNegDensity) return fail(CSPH_ERR_NEG_DENSITY, "negative density appeared in the state");
+  if (bits & kBadNoSignal)
+    return fail(CSPH_ERR_NO_SIGNAL, "no non-vacuum cell: the CFL step needs dt_max > 0");
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status upload_field(csph_sim* s, Real* dst, const double* interior) {
+  const GridDev& g = s->g;
+  std::vector<Real> pad((size_t)g.ncell, (Real)0);
+  size_t q = 0;
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j) {
+      Real* row = pad.data() + ((size_t)(k + kGhost) * g.sy + (j + kGhost)) * g.sx + kGhost;
+      for (int i = 0; i < g.nx; ++i) row[i] = (Real)interior[q++];
+    }
+  HIP_TRY(hipMemcpyAsync(dst, pad.data(), pad.size() * sizeof(Real), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status download_field(const csph_sim* s, const Real* src, double* interior) {
+  const GridDev& g = s->g;
+  std::vector<Real> pad((size_t)g.ncell);
+  HIP_TRY(hipMemcpyAsync(pad.data(), src, pad.size() * sizeof(Real), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  size_t q = 0;
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j) {
+      const Real* row = pad.data() + ((size_t)(k + kGhost) * g.sy + (j + kGhost)) * g.sx + kGhost;
+      for (int i = 0; i < g.nx; ++i) interior[q++] = (double)row[i];
+    }
+  return CSPH_OK;
+}
+
+template <typename Real>
+Fields<Real>& fields_of(csph_sim* s);
+template <>
+Fields<float>& fields_of<float>(csph_sim* s) { return s->f32; }
+template <>
+Fields<double>& fields_of<double>(csph_sim* s) { return s->f64; }
+
+template <typename Real>
+csph_status set_state_t(csph_sim* s, const double* cons) {
+  Fields<Real>& F = fields_of<Real>(s);
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  for (int v = 0; v < 5; ++v) {
+    csph_status st = upload_field<Real>(s, F.U[0][v], cons + (size_t)v * N);
+    if (st) return st;
+  }
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status prepare(csph_sim* s) {
+  Fields<Real>& F = fields_of<Real>(s);
+  if (s->psi_dirty) {
+    HIP_TRY(Launch<Real>::fill_psi(F, s->g, s->bc, s->ctrl, s->stream));
+    s->psi_dirty = false;
+  }
+  if (s->need_smax) {
+    HIP_TRY(Launch<Real>::signal_max(F, s->g, s->ctrl, s->stream));
+    s->need_smax = false;
+  }
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status launch_steps(csph_sim* s, int n, double dt_max, double t_end) {
+  csph_status st = prepare<Real>(s);
+  if (st) return st;
+  Fields<Real>& F = fields_of<Real>(s);
+  for (int k = 0; k < n; ++k)
+    HIP_TRY(Launch<Real>::step(F, s->g, s->bc, s->ctrl, s->partials, dt_max, t_end, s->stream));
+  s->stepped = true;
+  return CSPH_OK;
+}
+
+csph_status launch(csph_sim* s, int n, double dt_max, double t_end) {
+  return s->is_f64() ? launch_steps<double>(s, n, dt_max, t_end)
+                  : launch_steps<float>(s, n, dt_max, t_end);
+}
+
+bool periodic_pairs_ok(const csph_sim* s) {
+  for (int ax = 0; ax < 3; ++ax)
+    if ((s->bc.kind[2 * ax] == kPeriodic) != (s->bc.kind[2 * ax + 1] == kPeriodic)) return false;
+  return true;
+}
+
+csph_status init_sim(csph_sim* s) {
+  s->g = make_grid(&s->desc);
+  for (int f = 0; f < 6; ++f) s->bc.kind[f] = kPeriodic;
+  if (s->is_f64())
+    bind_fields<double>(s, s->f64);
+  else
+    bind_fields<float>(s, s->f32);
+  s->ctrl = (Ctrl*)(s->buf + s->L.ctrl_off);
+  s->partials = (double*)(s->buf + s->L.partials_off);
+  s->totals_dev = (double*)(s->buf + s->L.totals_off);
+  // zero fields (psi = 0, state = 0) and the control block
+  std::vector<char> zeros(std::min<size_t>(s->L.total, (size_t)64 << 20), 0);
+  for (size_t off = 0; off < s->L.total; off += zeros.size()) {
+    const size_t n = std::min(zeros.size(), s->L.total - off);
+    HIP_TRY(hipMemcpyAsync(s->buf + off, zeros.data(), n, hipMemcpyHostToDevice, s->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CSPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* csph_last_error(void) { return g_err.c_str(); }
+
+size_t csph_required_bytes(const csph_grid_desc* desc) {
+  std::string why;
+  if (!desc_ok(desc, &why)) return 0;
+  return make_layout(desc).total;
+}
+
+static csph_status create_common(const csph_grid_desc* desc, void* stream, void* dev_buf,
+                                 size_t bytes, csph_sim** out) {
+  if (!out) return fail(CSPH_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!desc_ok(desc, &why)) return fail(CSPH_ERR_ARG, why);
+  csph_sim* s = new (std::nothrow) csph_sim();
+  if (!s) return fail(CSPH_ERR_NOMEM, "host allocation failed");
+  s->desc = *desc;
+  s->stream = (hipStream_t)stream;
+  s->L = make_layout(desc);
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(CSPH_ERR_DEVICE, "hipGetDevice failed");
+  }
+  if (dev_buf) {
+    if (bytes < s->L.total) {
+      delete s;
+      return fail(CSPH_ERR_ARG, "caller buffer smaller than csph_required_bytes");
+    }
+    if ((uintptr_t)dev_buf % kAlign) {
+      delete s;
+      return fail(CSPH_ERR_ARG, "caller buffer must be 256-byte aligned");
+    }
+    s->buf = (char*)dev_buf;
+    s->owned = false;
+  } else {
+    void* p = nullptr;
+    if (hipMalloc(&p, s->L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      delete s;
+      return fail(CSPH_ERR_NOMEM, "hipMalloc failed");
+    }
+    s->buf = (char*)p;
+    s->owned = true;
+  }
+  csph_status st = init_sim(s);
+  if (st) {
+    if (s->owned) (void)hipFree(s->buf);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return CSPH_OK;
+}
+
+csph_status csph_create(const csph_grid_desc* desc, void* hip_stream, csph_sim** out) {
+  return create_common(desc, hip_stream, nullptr, 0, out);
+}
+
+csph_status csph_create_in(const csph_grid_desc* desc, void* hip_stream, void* dev_buf,
+                           size_t bytes, csph_sim** out) {
+  if (!dev_buf) return fail(CSPH_ERR_ARG, "dev_buf is NULL");
+  return create_common(desc, hip_stream, dev_buf, bytes, out);
+}
+
+csph_status csph_destroy(csph_sim* s) {
+  if (!s) return CSPH_OK;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->owned) (void)hipFree(s->buf);
+  delete s;
+  return CSPH_OK;
+}
+
+csph_status csph_set_stream(csph_sim* s, void* hip_stream) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->stream = (hipStream_t)hip_stream;
+  return CSPH_OK;
+}
+
+csph_status csph_set_state(csph_sim* s, csph_vars vars, const double* host) {
+  if (!s || !host) return fail(CSPH_ERR_ARG, "sim or host array is NULL");
+  if (vars != CSPH_CONSERVED && vars != CSPH_PRIMITIVE) return fail(CSPH_ERR_ARG, "bad vars");
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  std::vector<double> cons;
+  const double* src = host;
+  for (size_t q = 0; q < N; ++q)
+    if (!(host[q] >= 0.0)) return fail(CSPH_ERR_ARG, "density must be >= 0");
+  if (vars == CSPH_PRIMITIVE) {
+    cons.resize(5 * N);
+    const double gm1 = s->desc.gamma - 1.0;
+    for (size_t q = 0; q < N; ++q) {
+      const double r = host[q], ux = host[N + q], uy = host[2 * N + q], uz = host[3 * N + q],
+                   p = host[4 * N + q];
+      if (!(p >= 0.0)) return fail(CSPH_ERR_ARG, "pressure must be >= 0");
+      cons[q] = r;
+      cons[N + q] = r * ux;
+      cons[2 * N + q] = r * uy;
+      cons[3 * N + q] = r * uz;
+      cons[4 * N + q] = p / gm1 + 0.5 * r * (ux * ux + uy * uy + uz * uz);
+    }
+    src = cons.data();
+  }
+  csph_status st = s->is_f64() ? set_state_t<double>(s, src) : set_state_t<float>(s, src);
+  if (st) return st;
+  Ctrl c{};
+  Ctrl old{};
+  st = read_ctrl(s, &old);
+  if (st) return st;
+  c.t = old.t;
+  c.nsteps = old.nsteps;
+  st = write_ctrl(s, c);
+  if (st) return st;
+  s->need_smax = true;
+  s->stepped = false;
+  return CSPH_OK;
+}
+
+csph_status csph_set_potential(csph_sim* s, const double* host_psi) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  s->has_psi = host_psi != nullptr;
+  s->psi_host.assign(N, 0.0);
+  if (host_psi) std::memcpy(s->psi_host.data(), host_psi, N * sizeof(double));
+  csph_status st = s->is_f64() ? upload_field<double>(s, s->f64.psi, s->psi_host.data())
+                            : upload_field<float>(s, s->f32.psi, s->psi_host.data());
+  if (st) return st;
+  s->psi_dirty = true;
+  return CSPH_OK;
+}
+
+csph_status csph_set_boundary(csph_sim* s, int32_t face, csph_bc kind, const double inflow_prim[5]) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (face < 0 || face > 5) return fail(CSPH_ERR_ARG, "face must be 0..5");
+  if (kind < CSPH_PERIODIC || kind > CSPH_REFLECT) return fail(CSPH_ERR_ARG, "bad boundary kind");
+  s->bc.kind[face] = (int)kind;
+  if (kind == CSPH_INFLOW) {
+    if (!inflow_prim) return fail(CSPH_ERR_ARG, "inflow state required");
+    const double r = inflow_prim[0], ux = inflow_prim[1], uy = inflow_prim[2], uz = inflow_prim[3],
+                 p = inflow_prim[4];
+    if (!(r >= 0.0) || !(p >= 0.0)) return fail(CSPH_ERR_ARG, "inflow rho and p must be >= 0");
+    for (int v = 0; v < 5; ++v) s->inflow_prim[face][v] = inflow_prim[v];
+    s->bc.cons[face][0] = r;
+    s->bc.cons[face][1] = r * ux;
+    s->bc.cons[face][2] = r * uy;
+    s->bc.cons[face][3] = r * uz;
+    s->bc.cons[face][4] = p / (s->desc.gamma - 1.0) + 0.5 * r * (ux * ux + uy * uy + uz * uz);
+    s->bc.vel[face][0] = ux;
+    s->bc.vel[face][1] = uy;
+    s->bc.vel[face][2] = uz;
+  }
+  s->psi_dirty = true;
+  return CSPH_OK;
+}
+
+csph_status csph_step(csph_sim* s, double dt_max, double* dt_taken) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
+  Ctrl c{};
+  // a step always runs (no end time): clear the completion flag of earlier advances
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  if (c.status) return fail(CSPH_ERR_STATE, "sticky error: call csph_set_state");
+  if (c.done) {
+    c.done = 0;
+    st = write_ctrl(s, c);
+    if (st) return st;
+  }
+  st = launch(s, 1, dt_max, INFINITY);
+  if (st) return st;
+  if (dt_taken) {
+    st = read_ctrl(s, &c);
+    if (st) return st;
+    if (c.status) return status_from_bits(c.status);
+    *dt_taken = c.dt;
+  }
+  return CSPH_OK;
+}
+
+csph_status csph_advance(csph_sim* s, double t_end, int64_t max_steps, int64_t* steps_taken) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
+  if (max_steps < 0) return fail(CSPH_ERR_ARG, "max_steps must be >= 0");
+  if (std::isnan(t_end)) return fail(CSPH_ERR_ARG, "t_end is NaN");
+  Ctrl c{};
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  if (c.status) return fail(CSPH_ERR_STATE, "sticky error: call csph_set_state");
+  const long long n0 = c.nsteps;
+  if (c.done) {
+    c.done = 0;
+    st = write_ctrl(s, c);
+    if (st) return st;
+  }
+  int64_t left = max_steps;
+  int chunk = 4;
+  while (left > 0) {
+    const int n = (int)std::min<int64_t>(left, chunk);
+    st = launch(s, n, 0.0, t_end);
+    if (st) return st;
+    left -= n;
+    st = read_ctrl(s, &c);
+    if (st) return st;
+    if (c.status || c.done) break;
+    chunk = std::min(chunk * 2, 64);
+  }
+  if (steps_taken) *steps_taken = c.nsteps - n0;
+  if (c.status) return status_from_bits(c.status);
+  return CSPH_OK;
+}
+
+csph_status csph_get_state(const csph_sim* s, csph_vars vars, double* out) {
+  if (!s || !out) return fail(CSPH_ERR_ARG, "sim or output is NULL");
+  if (vars != CSPH_CONSERVED && vars != CSPH_PRIMITIVE) return fail(CSPH_ERR_ARG, "bad vars");
+  Ctrl c{};
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  for (int v = 0; v < 5; ++v) {
+    st = s->is_f64() ? download_field<double>(s, s->f64.U[c.par][v], out + (size_t)v * N)
+                  : download_field<float>(s, s->f32.U[c.par][v], out + (size_t)v * N);
+    if (st) return st;
+  }
+  if (vars == CSPH_PRIMITIVE) {
+    const double gm1 = s->desc.gamma - 1.0;
+    for (size_t q = 0; q < N; ++q) {
+      const double r = out[q];
+      double u[3] = {0.0, 0.0, 0.0};
+      if (r > s->desc.rho_vac)
+        for (int d = 0; d < 3; ++d) u[d] = out[(1 + d) * N + q] / r;
+      const double ke = 0.5 * (out[N + q] * u[0] + out[2 * N + q] * u[1] + out[3 * N + q] * u[2]);
+      const double p = gm1 * (out[4 * N + q] - ke);
+      for (int d = 0; d < 3; ++d) out[(1 + d) * N + q] = u[d];
+      out[4 * N + q] = p > 0.0 ? p : 0.0;
+    }
+  }
+  return CSPH_OK;
+}
+
+csph_status csph_get_time(const csph_sim* s, double* t, int64_t* nsteps) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  Ctrl c{};
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  if (t) *t = c.t;
+  if (nsteps) *nsteps = c.nsteps;
+  return CSPH_OK;
+}
+
+csph_status csph_set_time(csph_sim* s, double t, int64_t nsteps) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (!std::isfinite(t) || nsteps < 0) return fail(CSPH_ERR_ARG, "bad time or step count");
+  Ctrl c{};
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  c.t = t;
+  c.nsteps = nsteps;
+  c.done = 0;
+  return write_ctrl(s, c);
+}
+
+csph_status csph_totals(const csph_sim* s, double out[5]) {
+  if (!s || !out) return fail(CSPH_ERR_ARG, "sim or output is NULL");
+  if (!s->stepped) {
+    // no step since the state was set: sum the state on the host
+    const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+    std::vector<double> U(5 * N);
+    csph_status st = csph_get_state(s, CSPH_CONSERVED, U.data());
+    if (st) return st;
+    for (int v = 0; v < 5; ++v) {
+      double a = 0.0;
+      for (size_t q = 0; q < N; ++q) a += U[(size_t)v * N + q];
+      out[v] = a * s->g.h3;
+    }
+    return CSPH_OK;
+  }
+  HIP_TRY(s->is_f64() ? Launch<double>::totals(s->g, s->partials, s->L.nblocks, s->totals_dev, s->stream)
+                   : Launch<float>::totals(s->g, s->partials, s->L.nblocks, s->totals_dev, s->stream));
+  HIP_TRY(hipMemcpyAsync(out, s->totals_dev, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CSPH_OK;
+}
+
+csph_status csph_get_stage(const csph_sim* s, int32_t which, double* out) {
+  if (!s || !out) return fail(CSPH_ERR_ARG, "sim or output is NULL");
+  if (which < 0 || which > 13) return fail(CSPH_ERR_ARG, "which must be 0..13");
+  if (s->is_f64()) {
+    const double* src = which < 4 ? s->f64.ms[which] : which < 7 ? s->f64.xs[which - 4]
+                      : which < 11 ? s->f64.mt[which - 7] : s->f64.xt[which - 11];
+    return download_field<double>(s, src, out);
+  }
+  const float* src = which < 4 ? s->f32.ms[which] : which < 7 ? s->f32.xs[which - 4]
+                   : which < 11 ? s->f32.mt[which - 7] : s->f32.xt[which - 11];
+  return download_field<float>(s, src, out);
+}
+
+// batches are implemented in csph_batch.hip
+
+}  // extern "C"

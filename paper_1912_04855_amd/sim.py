@@ -1,0 +1,185 @@
+"""Python face of the library: ``Sim`` (one simulation) and helpers.
+
+Every step of the method runs in the HIP kernels behind the C ABI; this module
+only marshals arguments.  Device memory can be lent by PyTorch (``torch=True``:
+a uint8 CUDA tensor sized by ``csph_required_bytes``) and work can be issued on
+torch's current stream, so the library interoperates with torch code.
+"""
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import _lib
+from ._lib import CONSERVED, F32, F64, PRIMITIVE, check
+
+
+def _dtype_code(dtype):
+    if dtype in ("f32", "float32", F32, np.float32):
+        return F32
+    if dtype in ("f64", "float64", F64, np.float64):
+        return F64
+    raise ValueError(f"dtype must be f32 or f64, got {dtype!r}")
+
+
+def make_desc(shape, h, gamma=1.4, cfl=0.4, rho_vac=1e-10, dtype="f64", origin=(0.0, 0.0, 0.0)):
+    d = _lib.GridDesc()
+    d.nx, d.ny, d.nz = (int(v) for v in shape)
+    d.h = float(h)
+    for a in range(3):
+        d.origin[a] = float(origin[a])
+    d.gamma, d.cfl, d.rho_vac = float(gamma), float(cfl), float(rho_vac)
+    d.dtype = _dtype_code(dtype)
+    return d
+
+
+def required_bytes(shape, h=1.0, dtype="f64", **kw) -> int:
+    d = make_desc(shape, h, dtype=dtype, **kw)
+    return int(_lib.load().csph_required_bytes(C.byref(d)))
+
+
+def _ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data)
+
+
+class Sim:
+    """One CSPH-TVD simulation on the current HIP device.
+
+    shape = (nx, ny, nz).  Arrays are numpy float64, [5, nz, ny, nx] for states.
+    ``torch=True`` allocates the device buffer as a torch tensor and issues work on
+    torch's current stream."""
+
+    def __init__(self, shape, h, gamma=1.4, cfl=0.4, rho_vac=1e-10, dtype="f64",
+                 origin=(0.0, 0.0, 0.0), torch=False, stream=None):
+        L = _lib.load()
+        self.shape = (int(shape[2]), int(shape[1]), int(shape[0]))  # (nz, ny, nx)
+        self.dtype = _dtype_code(dtype)
+        self.desc = make_desc(shape, h, gamma, cfl, rho_vac, dtype, origin)
+        self.gamma = gamma
+        self._buf = None
+        self._h = C.c_void_p()
+        if torch:
+            import torch as _t
+            nbytes = int(L.csph_required_bytes(C.byref(self.desc)))
+            if nbytes == 0:
+                raise ValueError("invalid grid description")
+            # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+            self._buf = _t.empty(nbytes, dtype=_t.uint8, device="cuda")
+            if stream is None:
+                stream = _t.cuda.current_stream().cuda_stream
+            check(L.csph_create_in(C.byref(self.desc), C.c_void_p(stream),
+                                   C.c_void_p(self._buf.data_ptr()), nbytes, C.byref(self._h)),
+                  "csph_create_in")
+        else:
+            check(L.csph_create(C.byref(self.desc), C.c_void_p(stream or 0), C.byref(self._h)),
+                  "csph_create")
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if self._h:
+            _lib.load().csph_destroy(self._h)
+            self._h = C.c_void_p()
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ------------------------------------------------------------------ setup
+    def set_boundary(self, face, kind, inflow=None):
+        arr = None
+        if inflow is not None:
+            arr = np.ascontiguousarray(inflow, dtype=np.float64)
+            assert arr.shape == (5,)
+        check(_lib.load().csph_set_boundary(self._h, int(face), int(kind),
+                                            _ptr(arr) if arr is not None else None),
+              "csph_set_boundary")
+
+    def set_state(self, arr, vars=PRIMITIVE):
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        assert a.shape == (5,) + self.shape, a.shape
+        check(_lib.load().csph_set_state(self._h, int(vars), _ptr(a)), "csph_set_state")
+
+    def set_primitive(self, W):
+        self.set_state(W, PRIMITIVE)
+
+    def set_conserved(self, U):
+        self.set_state(U, CONSERVED)
+
+    def set_potential(self, psi):
+        if psi is None:
+            check(_lib.load().csph_set_potential(self._h, None), "csph_set_potential")
+            return
+        a = np.ascontiguousarray(psi, dtype=np.float64)
+        assert a.shape == self.shape
+        check(_lib.load().csph_set_potential(self._h, _ptr(a)), "csph_set_potential")
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, dt_max=0.0, sync=True) -> float:
+        dt = C.c_double()
+        check(_lib.load().csph_step(self._h, float(dt_max), C.byref(dt) if sync else None),
+              "csph_step")
+        return dt.value
+
+    def advance(self, t_end=math.inf, max_steps=2**62) -> int:
+        n = C.c_int64()
+        check(_lib.load().csph_advance(self._h, float(t_end), int(max_steps), C.byref(n)),
+              "csph_advance")
+        return n.value
+
+    # ------------------------------------------------------------------ read back
+    def get_state(self, vars=CONSERVED) -> np.ndarray:
+        out = np.empty((5,) + self.shape)
+        check(_lib.load().csph_get_state(self._h, int(vars), _ptr(out)), "csph_get_state")
+        return out
+
+    def conserved(self):
+        return self.get_state(CONSERVED)
+
+    def primitive(self):
+        return self.get_state(PRIMITIVE)
+
+    def time(self):
+        t, n = C.c_double(), C.c_int64()
+        check(_lib.load().csph_get_time(self._h, C.byref(t), C.byref(n)), "csph_get_time")
+        return t.value, n.value
+
+    def set_time(self, t, nsteps):
+        check(_lib.load().csph_set_time(self._h, float(t), int(nsteps)), "csph_set_time")
+
+    def totals(self) -> np.ndarray:
+        out = np.zeros(5)
+        check(_lib.load().csph_totals(self._h, _ptr(out)), "csph_totals")
+        return out
+
+    STAGE_FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
+                    "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz"]
+
+    def stage(self, name) -> np.ndarray:
+        out = np.empty(self.shape)
+        check(_lib.load().csph_get_stage(self._h, self.STAGE_FIELDS.index(name), _ptr(out)),
+              "csph_get_stage")
+        return out
+
+
+def from_problem(prob, dtype="f64", torch=False, stream=None) -> Sim:
+    """A Sim set up from a ``problems.Problem`` description."""
+    s = Sim(prob.shape, prob.h, gamma=prob.gamma, cfl=prob.cfl, rho_vac=prob.rho_vac,
+            dtype=dtype, origin=prob.origin, torch=torch, stream=stream)
+    for f in range(6):
+        s.set_boundary(f, prob.bc[f], prob.inflow.get(f) if prob.bc[f] == _lib.INFLOW else None)
+    s.set_potential(prob.psi)
+    s.set_primitive(prob.prim)
+    return s
