@@ -139,6 +139,16 @@ csph_status csph_get_stage(const csph_sim* sim, int32_t which, double* host_out)
 
 const char* csph_last_error(void);
 
+/* Kernel timing (benchmark support).  While enabled, every step records HIP
+ * events around its kernels on the simulation's stream; csph_profile_read
+ * synchronises and returns, per kernel group, the average duration in
+ * milliseconds of one launch and the number of launches timed since enabling:
+ * group 0 = stage P (predictor), 1 = stage C (corrector), 2 = stage E (Eulerian
+ * update), 3 = ghost fills (three launches per step, timed together), 4 = the
+ * begin/end bookkeeping launches.  n is the capacity of both arrays (<= 5). */
+csph_status csph_profile_enable(csph_sim* sim, int32_t on);
+csph_status csph_profile_read(csph_sim* sim, double* avg_ms, int64_t* launches, int32_t n);
+
 /* ---------------- batches: many simulations advanced together ---------------
  * A batch references simulations of one dtype; it does not own them, and each
  * must outlive its membership.  Every member keeps its own dt, t and step

@@ -25,7 +25,8 @@ EXPORTS = [
     "csph_set_state", "csph_set_potential", "csph_set_boundary", "csph_step", "csph_advance",
     "csph_get_state", "csph_get_time", "csph_set_time", "csph_totals", "csph_get_stage",
     "csph_last_error", "csph_batch_create", "csph_batch_add", "csph_batch_advance",
-    "csph_batch_poll", "csph_batch_remove", "csph_batch_destroy",
+    "csph_batch_poll", "csph_batch_remove", "csph_batch_destroy", "csph_profile_enable",
+    "csph_profile_read",
 ]
 
 
@@ -77,6 +78,8 @@ def load():
         "csph_batch_poll": (st, [vp, vp, C.c_int32, C.POINTER(C.c_int32)]),
         "csph_batch_remove": (st, [vp, C.c_int32]),
         "csph_batch_destroy": (st, [vp]),
+        "csph_profile_enable": (st, [vp, C.c_int32]),
+        "csph_profile_read": (st, [vp, vp, vp, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

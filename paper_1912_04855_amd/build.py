@@ -24,7 +24,8 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", SRC, "-I
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 UNITS = [
-    ("csph_kernels.hip", "k32.o", ["-DCSPH_REAL=float", "-DCSPH_IS_DOUBLE=0", "-ffp-contract=fast"]),
+    ("csph_kernels.hip", "k32.o", ["-DCSPH_REAL=float", "-DCSPH_IS_DOUBLE=0", "-ffp-contract=fast",
+                                   "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
     ("csph_kernels.hip", "k64.o", ["-DCSPH_REAL=double", "-DCSPH_IS_DOUBLE=1", "-ffp-contract=off"]),
     ("csph_runtime.hip", "runtime.o", ["-ffp-contract=off"]),
     ("csph_batch.hip", "batch.o", ["-ffp-contract=off"]),

@@ -4,8 +4,8 @@
 // (nx+4) x (ny+4) x (nz+4) cells (two ghost layers per face), x fastest, one
 // array per field (structure of arrays), each starting on a 256-byte boundary.
 // Fields: two copies of the conserved state U = (rho, mx, my, mz, E) used in
-// turn as U^n and U^{n+1}; psi; the predictor output (m*, E*, xi*); the
-// corrector output (m~, E~, xi^{n+1}).  The density never changes in the
+// turn as U^n and U^{n+1}; psi; the predictor output (m*, E*, xi*, and psi at
+// r*); the corrector output (m~, E~, xi^{n+1}).  The density never changes in the
 // Lagrangian stage, so rho* = rho~ = rho^n is not stored.
 #pragma once
 
@@ -68,6 +68,7 @@ struct Fields {
   Real* psi;
   Real* ms[4];   // m*x, m*y, m*z, E*
   Real* xs[3];   // xi*
+  Real* psis;    // psi at the predicted particle positions r* = x + xi*
   Real* mt[4];   // m~x, m~y, m~z, E~
   Real* xt[3];   // xi^{n+1}
 };
@@ -90,8 +91,10 @@ struct Launch {
   static hipError_t signal_max(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
                                hipStream_t s);
   // one full step: begin, ghosts, stage P, ghosts, stage C, ghosts, stage E, end
+  // ev (nullable): 8 events recorded around the launches, for kernel timing
   static hipError_t step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
-                         double* partials, double dt_max, double t_end, hipStream_t s);
+                         double* partials, double dt_max, double t_end, hipStream_t s,
+                         hipEvent_t* ev);
   static hipError_t totals(const GridDev& g, const double* partials, int nblocks, double* out,
                            hipStream_t s);
   static int stage_e_blocks(const GridDev& g);

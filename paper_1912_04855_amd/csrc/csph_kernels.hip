@@ -2,26 +2,37 @@
 //
 // This translation unit is compiled twice, with CSPH_REAL = float and with
 // CSPH_REAL = double.  The double build is compiled without floating-point
-// contraction and evaluates every expression in the same order as the scheme
-// is written (arXiv:1912.04855, Sec. 2.2), so it reproduces FP64 reference
-// arithmetic up to the order of the final FP64 reductions.  The float build
-// keeps the state and most arithmetic in FP32 and promotes to FP64 where
-// cancellation matters: the pressure + potential pair sums that carry the
-// well-balanced property, the time step and the conservation totals.
+// contraction and evaluates every expression of the scheme (arXiv:1912.04855,
+// Sec. 2.2) in one fixed order, so two runs, and any tiling, give the same bits.
+// The float build keeps the state and most arithmetic in FP32 (fast reciprocal
+// and square root) and promotes to FP64 where cancellation matters: the
+// pressure + potential pair differences that carry the well-balanced property,
+// the time step and the conservation totals.
 //
-// Per step (one thread per interior cell in each stage):
+// Per step:
 //   begin  : dt from the max signal speed of U^n (FP64), CFL rule
 //   fill   : ghost cells of U^n
 //   stage P: predictor, Eq. (5) with Q of Eq. (7) on the lattice
-//   fill   : ghost cells of m*, E*, xi*
+//   fill   : ghost cells of m*, E*, xi* and of psi at r*
 //   stage C: corrector, Eq. (6) with Q of Eq. (7) at the displaced particles
 //   fill   : ghost cells of m~, E~, xi^{n+1}
 //   stage E: reconstruction Eq. (8), face fluxes, update Eq. (4); epilogue:
 //            signal-speed max of U^{n+1}, FP64 block totals, error flags
 //   end    : swap the state copies
+//
+// Stages P, C and E are 2.5D stencil sweeps: a workgroup owns a TX x TY tile of
+// an x-y plane and marches along z through TZ planes.  P and C keep three planes
+// of per-cell derived quantities (primitive variables, offsets, potential) with
+// a one-cell halo in LDS, so each cell's primitives are formed once per sweep
+// instead of once per neighbour.  E keeps a register queue of its own column
+// along z (U^n at k-1..k+2, the z-face flux carried to the next plane) and the
+// current plane's x-y stencil (two-cell halo) in LDS.  Workgroup ids are
+// remapped so that each of the 8 XCDs (separate L2s) gets a contiguous run of
+// tiles, which keeps the halo reads of neighbouring tiles in one L2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "csph_internal.h"
 
@@ -40,8 +51,15 @@ namespace CSPH_TAG {
 
 using Real = CSPH_REAL;
 using Acc = double;
+constexpr bool kF64 = std::is_same<Real, double>::value;
 
 constexpr int kWave = 64;
+constexpr int kXcd = 8;
+
+// tile shape of the stencil sweeps
+constexpr int TX = 32, TY = 8, NT = TX * TY;
+constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;          // one-cell halo
+constexpr int EX = TX + 4, EY = TY + 4, EP = EX * EY;          // two-cell halo
 
 // ------------------------------------------------------------------ indexing
 __device__ __forceinline__ long long cell(const GridDev& g, int i, int j, int k) {
@@ -50,18 +68,64 @@ __device__ __forceinline__ long long cell(const GridDev& g, int i, int j, int k)
 
 // half neighbour set O13 in lexicographic (o_z, o_y, o_x) order; the partner of
 // each offset o is -o, and every sum adds the pair's two terms first.
-__constant__ int kO13[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},   {1, 1, 0},  {-1, -1, 1},
-                                {0, -1, 1}, {1, -1, 1}, {-1, 0, 1},  {0, 0, 1},  {1, 0, 1},
-                                {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
+struct O13 {
+  static constexpr int o[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1},
+                                   {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
+                                   {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
+};
+constexpr int O13::o[13][3];
 
-// ------------------------------------------------------------------ EOS
+// Dispatch hands consecutive workgroups to the XCDs round-robin; invert that so
+// XCD x owns the contiguous logical tiles [x*n/8, (x+1)*n/8).
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int per = (nblocks + kXcd - 1) / kXcd;
+  const int xcd = bid % kXcd, slot = bid / kXcd;
+  const int t = xcd * per + slot;
+  return t < nblocks ? t : -1;
+}
+
+struct Tile {
+  int x0, y0, z0, z1;
+};
+
+__device__ __forceinline__ bool tile_of(const GridDev& g, int tz, Tile& t) {
+  const int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY, nbz = (g.nz + tz - 1) / tz;
+  const int n = nbx * nby * nbz;
+  // the grid is rounded up to a multiple of 8 so the XCD inversion is a bijection
+  const int padded = (n + kXcd - 1) / kXcd * kXcd;
+  const int bid = xcd_tile(blockIdx.x, padded);
+  if (bid < 0 || bid >= n) return false;
+  const int bx = bid % nbx, r = bid / nbx, by = r % nby, bz = r / nby;
+  t.x0 = bx * TX;
+  t.y0 = by * TY;
+  t.z0 = bz * tz;
+  t.z1 = min(t.z0 + tz, g.nz);
+  return true;
+}
+
+// ------------------------------------------------------------------ arithmetic
+__device__ __forceinline__ Real rsqrt_(Real x) {
+  if constexpr (kF64) {
+    return (Real)1 / sqrt(x);  // not used by the FP64 build
+  } else {
+    return __builtin_amdgcn_rsqf(x);
+  }
+}
+
 // p = (gamma-1)(E - m.u/2), u = m/rho; vacuum (rho <= rho_vac): u = 0; p >= 0.
 __device__ __forceinline__ void primitive(const GridDev& g, Real rho, Real mx, Real my, Real mz,
                                           Real E, Real& ux, Real& uy, Real& uz, Real& p) {
   if (rho > (Real)g.rho_vac) {
-    ux = mx / rho;
-    uy = my / rho;
-    uz = mz / rho;
+    if constexpr (kF64) {
+      ux = mx / rho;
+      uy = my / rho;
+      uz = mz / rho;
+    } else {
+      const Real ir = __builtin_amdgcn_rcpf(rho);
+      ux = mx * ir;
+      uy = my * ir;
+      uz = mz * ir;
+    }
   } else {
     ux = (Real)0;
     uy = (Real)0;
@@ -72,57 +136,62 @@ __device__ __forceinline__ void primitive(const GridDev& g, Real rho, Real mx, R
   p = pp > (Real)0 ? pp : (Real)0;
 }
 
-// ------------------------------------------------------------------ kernel gradient
 // M4 cubic spline with support 2h: K(d) = -(kappa/h^2) (g(q)/q) d, q = |d|/h,
 // g(q)/q = 3 - 9q/4 (q < 1), 3(2-q)^2/(4q) (1 <= q < 2), 0 beyond.
-__device__ __forceinline__ Real g_over_q(Real q) {
-  if (q < (Real)1) return (Real)3 - (Real)2.25 * q;
-  if (q < (Real)2) {
-    const Real t = (Real)2 - q;
-    return (Real)0.75 * t * t / q;
-  }
-  return (Real)0;
-}
-
 __device__ __forceinline__ void kgrad(const GridDev& g, Real dx, Real dy, Real dz, Real& Kx,
                                       Real& Ky, Real& Kz) {
   const Real r2 = dx * dx + dy * dy + dz * dz;
-  const Real q = sqrt(r2) * (Real)g.inv_h;
-  const Real c = (Real)g.kappa_h2 * g_over_q(q);
+  Real gq;
+  if constexpr (kF64) {
+    const Real q = sqrt(r2) * (Real)g.inv_h;
+    if (q < (Real)1) {
+      gq = (Real)3 - (Real)2.25 * q;
+    } else if (q < (Real)2) {
+      const Real t = (Real)2 - q;
+      gq = (Real)0.75 * t * t / q;
+    } else {
+      gq = (Real)0;
+    }
+  } else {
+    const Real rs = rsqrt_(r2);                  // 1/|d|
+    const Real q = r2 * rs * (Real)g.inv_h;      // |d|/h
+    const Real t = (Real)2 - q;
+    const Real far = (Real)0.75 * t * t * (rs * (Real)g.h);
+    gq = q < (Real)1 ? (Real)3 - (Real)2.25 * q : (q < (Real)2 ? far : (Real)0);
+  }
+  const Real c = (Real)g.kappa_h2 * gq;
   Kx = -(c * dx);
   Ky = -(c * dy);
   Kz = -(c * dz);
 }
 
-// ------------------------------------------------------------------ TVD slope
 __device__ __forceinline__ Real minmod(Real a, Real b) {
   if (a * b <= (Real)0) return (Real)0;
   const Real sg = a > (Real)0 ? (Real)1 : (Real)-1;
   return sg * fmin(fabs(a), fabs(b));
 }
 
-// ------------------------------------------------------------------ potential at r*
 __device__ __forceinline__ Real lerp(Real a, Real b, Real t) { return a + t * (b - a); }
 
 // trilinear psi at cell centre + (ox, oy, oz), between the cell and its
-// neighbours on the side the particle moved to
-__device__ __forceinline__ Real psi_at(const GridDev& g, const Real* __restrict__ P, long long c,
-                                       Real ox, Real oy, Real oz) {
+// neighbours on the side the particle moved to; P(a, b, c) reads psi at the
+// cell offset (a, b, c)
+template <typename At>
+__device__ __forceinline__ Real psi_at(const GridDev& g, At P, Real ox, Real oy, Real oz) {
   const Real fx = ox * (Real)g.inv_h, fy = oy * (Real)g.inv_h, fz = oz * (Real)g.inv_h;
-  const long long di = fx >= (Real)0 ? 1 : -1;
-  const long long dj = (fy >= (Real)0 ? 1 : -1) * (long long)g.sx;
-  const long long dk = (fz >= (Real)0 ? 1 : -1) * g.sxy;
+  const int di = fx >= (Real)0 ? 1 : -1;
+  const int dj = fy >= (Real)0 ? 1 : -1;
+  const int dk = fz >= (Real)0 ? 1 : -1;
   const Real tx = fabs(fx), ty = fabs(fy), tz = fabs(fz);
-  const Real a00 = lerp(P[c], P[c + di], tx);
-  const Real a10 = lerp(P[c + dj], P[c + dj + di], tx);
-  const Real a01 = lerp(P[c + dk], P[c + dk + di], tx);
-  const Real a11 = lerp(P[c + dk + dj], P[c + dk + dj + di], tx);
+  const Real a00 = lerp(P(0, 0, 0), P(di, 0, 0), tx);
+  const Real a10 = lerp(P(0, dj, 0), P(di, dj, 0), tx);
+  const Real a01 = lerp(P(0, 0, dk), P(di, 0, dk), tx);
+  const Real a11 = lerp(P(0, dj, dk), P(di, dj, dk), tx);
   const Real b0 = lerp(a00, a10, ty);
   const Real b1 = lerp(a01, a11, ty);
   return lerp(b0, b1, tz);
 }
 
-// ------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -134,6 +203,21 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+__device__ __forceinline__ double signal_speed(const GridDev& g, Real r, Real mx, Real my, Real mz,
+                                               Real E) {
+  if (!(r > (Real)g.rho_vac)) return 0.0;
+  Real ux, uy, uz, p;
+  primitive(g, r, mx, my, mz, E, ux, uy, uz, p);
+  Real cs;
+  if constexpr (kF64) {
+    cs = sqrt((Real)g.gamma * p / r);
+  } else {
+    cs = sqrtf((Real)g.gamma * p * __builtin_amdgcn_rcpf(r));
+  }
+  const Real sp = cs + fabs(ux) + fabs(uy) + fabs(uz);
+  return (double)sp;
+}
+
 // ==================================================================== ghost cells
 __device__ __forceinline__ int map_index(int x, int n, int kind) {
   if (kind == kPeriodic) return x < 0 ? x + n : x - n;
@@ -141,130 +225,100 @@ __device__ __forceinline__ int map_index(int x, int n, int kind) {
   return x < 0 ? 0 : n - 1;  // outflow (and psi at inflow faces)
 }
 
-__device__ __forceinline__ Real inflow_value(const BcDev& bc, int face, int role, double dt) {
-  if (role <= kE) return (Real)bc.cons[face][role];
-  return (Real)(dt * bc.vel[face][role - kXx]);
+// decode ghost cell number t into (i, j, k); false beyond the last ghost cell
+__device__ __forceinline__ bool ghost_cell(const GridDev& g, long long t, int& i, int& j, int& k) {
+  const long long zone_z = 4LL * g.sx * g.sy;
+  const long long zone_y = (long long)g.nz * 4 * g.sx;
+  const long long zone_x = (long long)g.nz * g.ny * 4;
+  if (t < zone_z) {
+    const int kk = (int)(t / ((long long)g.sx * g.sy));
+    const long long r = t - (long long)kk * g.sx * g.sy;
+    j = (int)(r / g.sx) - kGhost;
+    i = (int)(r % g.sx) - kGhost;
+    k = kk < 2 ? kk - 2 : g.nz + (kk - 2);
+  } else if (t < zone_z + zone_y) {
+    const long long u = t - zone_z;
+    k = (int)(u / (4LL * g.sx));
+    const long long r = u - (long long)k * 4 * g.sx;
+    const int jj = (int)(r / g.sx);
+    i = (int)(r % g.sx) - kGhost;
+    j = jj < 2 ? jj - 2 : g.ny + (jj - 2);
+  } else if (t < zone_z + zone_y + zone_x) {
+    const long long u = t - zone_z - zone_y;
+    k = (int)(u / (4LL * g.ny));
+    const long long r = u - (long long)k * 4 * g.ny;
+    j = (int)(r / 4);
+    const int ii = (int)(r % 4);
+    i = ii < 2 ? ii - 2 : g.nx + (ii - 2);
+  } else {
+    return false;
+  }
+  return true;
 }
 
-// Ghost cell (i,j,k): the last axis filled (z) decides first, then y, then x,
-// which composes the per-face rules applied in x, y, z order.
+// Value of ghost cell (i,j,k) of a field with the given role: the last axis
+// filled (z) decides first, then y, then x, which composes the per-face rules
+// applied in x, y, z order.
+__device__ __forceinline__ Real ghost_value(const GridDev& g, const BcDev& bc, const Real* f, int role,
+                                            int i, int j, int k, double dt) {
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int c[3] = {i, j, k};
+  Real sign = (Real)1;
+  for (int ax = 2; ax >= 0; --ax) {
+    if (c[ax] >= 0 && c[ax] < n[ax]) continue;
+    const int face = 2 * ax + (c[ax] < 0 ? 0 : 1);
+    const int kind = bc.kind[face];
+    if (kind == kInflow && role != kPsi) {
+      const Real v = role <= kE ? (Real)bc.cons[face][role] : (Real)(dt * bc.vel[face][role - kXx]);
+      return sign * v;
+    }
+    c[ax] = map_index(c[ax], n[ax], kind);
+    if (kind == kReflect && (role == kMx + ax || role == kXx + ax)) sign = -sign;
+  }
+  return sign * f[cell(g, c[0], c[1], c[2])];
+}
+
 __global__ void __launch_bounds__(256) k_fill(FillSet<Real> fs, GridDev g, BcDev bc,
                                               const Ctrl* __restrict__ ctrl, int check_active) {
   if (check_active && !ctrl->active) return;
-  const long long zone_z = 4LL * g.sx * g.sy;
-  const long long zone_y = (long long)g.nz * 4 * g.sx;
-  const long long zone_x = (long long)g.nz * g.ny * 4;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   int i, j, k;
-  if (t < zone_z) {
-    const int kk = (int)(t / ((long long)g.sx * g.sy));
-    const long long r = t - (long long)kk * g.sx * g.sy;
-    j = (int)(r / g.sx) - kGhost;
-    i = (int)(r % g.sx) - kGhost;
-    k = kk < 2 ? kk - 2 : g.nz + (kk - 2);
-  } else if (t < zone_z + zone_y) {
-    const long long u = t - zone_z;
-    k = (int)(u / (4LL * g.sx));
-    const long long r = u - (long long)k * 4 * g.sx;
-    const int jj = (int)(r / g.sx);
-    i = (int)(r % g.sx) - kGhost;
-    j = jj < 2 ? jj - 2 : g.ny + (jj - 2);
-  } else if (t < zone_z + zone_y + zone_x) {
-    const long long u = t - zone_z - zone_y;
-    k = (int)(u / (4LL * g.ny));
-    const long long r = u - (long long)k * 4 * g.ny;
-    j = (int)(r / 4);
-    const int ii = (int)(r % 4);
-    i = ii < 2 ? ii - 2 : g.nx + (ii - 2);
-  } else {
-    return;
-  }
+  if (!ghost_cell(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
   const double dt = ctrl->dt;
-  const int n[3] = {g.nx, g.ny, g.nz};
   const long long cg = cell(g, i, j, k);
-  for (int q = 0; q < fs.n; ++q) {
-    const int role = fs.role[q];
-    Real* f = fs.f[q];
-    int c[3] = {i, j, k};
-    Real sign = (Real)1;
-    bool done = false;
-    Real val = (Real)0;
-    for (int ax = 2; ax >= 0; --ax) {
-      if (c[ax] >= 0 && c[ax] < n[ax]) continue;
-      const int face = 2 * ax + (c[ax] < 0 ? 0 : 1);
-      const int kind = bc.kind[face];
-      if (kind == kInflow && role != kPsi) {
-        val = sign * inflow_value(bc, face, role, dt);
-        done = true;
-        break;
-      }
-      c[ax] = map_index(c[ax], n[ax], kind);
-      if (kind == kReflect && (role == kMx + ax || role == kXx + ax)) sign = -sign;
-    }
-    if (!done) {
-      const long long cs = cell(g, c[0], c[1], c[2]);
-      val = sign * f[cs];
-    }
-    f[cg] = val;
+  for (int q = 0; q < fs.n; ++q) fs.f[q][cg] = ghost_value(g, bc, fs.f[q], fs.role[q], i, j, k, dt);
+}
+
+// ghosts of the predicted particles, then psi at their displaced positions for
+// the first ghost layer (the corrector reads psi* of index neighbours only)
+__global__ void __launch_bounds__(256) k_fill_pred(Fields<Real> F, GridDev g, BcDev bc,
+                                                   const Ctrl* __restrict__ ctrl) {
+  if (!ctrl->active) return;
+  int i, j, k;
+  if (!ghost_cell(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const double dt = ctrl->dt;
+  const long long cg = cell(g, i, j, k);
+  for (int q = 0; q < 4; ++q) F.ms[q][cg] = ghost_value(g, bc, F.ms[q], kMx + q, i, j, k, dt);
+  Real xi[3];
+  for (int q = 0; q < 3; ++q) {
+    xi[q] = ghost_value(g, bc, F.xs[q], kXx + q, i, j, k, dt);
+    F.xs[q][cg] = xi[q];
+  }
+  if (i >= -1 && i <= g.nx && j >= -1 && j <= g.ny && k >= -1 && k <= g.nz) {
+    const Real* P = F.psi;
+    auto at = [&](int a, int b, int c) { return P[cg + a + (long long)b * g.sx + (long long)c * g.sxy]; };
+    F.psis[cg] = psi_at(g, at, xi[0], xi[1], xi[2]);
   }
 }
 
-// state fill reads the current copy U[par] (only known on the device)
 __global__ void __launch_bounds__(256) k_fill_state(Fields<Real> F, GridDev g, BcDev bc,
                                                     const Ctrl* __restrict__ ctrl) {
   if (!ctrl->active) return;
-  const long long zone_z = 4LL * g.sx * g.sy;
-  const long long zone_y = (long long)g.nz * 4 * g.sx;
-  const long long zone_x = (long long)g.nz * g.ny * 4;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   int i, j, k;
-  if (t < zone_z) {
-    const int kk = (int)(t / ((long long)g.sx * g.sy));
-    const long long r = t - (long long)kk * g.sx * g.sy;
-    j = (int)(r / g.sx) - kGhost;
-    i = (int)(r % g.sx) - kGhost;
-    k = kk < 2 ? kk - 2 : g.nz + (kk - 2);
-  } else if (t < zone_z + zone_y) {
-    const long long u = t - zone_z;
-    k = (int)(u / (4LL * g.sx));
-    const long long r = u - (long long)k * 4 * g.sx;
-    const int jj = (int)(r / g.sx);
-    i = (int)(r % g.sx) - kGhost;
-    j = jj < 2 ? jj - 2 : g.ny + (jj - 2);
-  } else if (t < zone_z + zone_y + zone_x) {
-    const long long u = t - zone_z - zone_y;
-    k = (int)(u / (4LL * g.ny));
-    const long long r = u - (long long)k * 4 * g.ny;
-    j = (int)(r / 4);
-    const int ii = (int)(r % 4);
-    i = ii < 2 ? ii - 2 : g.nx + (ii - 2);
-  } else {
-    return;
-  }
+  if (!ghost_cell(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
   const int par = ctrl->par;
-  const int n[3] = {g.nx, g.ny, g.nz};
   const long long cg = cell(g, i, j, k);
-  for (int role = 0; role < 5; ++role) {
-    Real* f = F.U[par][role];
-    int c[3] = {i, j, k};
-    Real sign = (Real)1;
-    bool done = false;
-    Real val = (Real)0;
-    for (int ax = 2; ax >= 0; --ax) {
-      if (c[ax] >= 0 && c[ax] < n[ax]) continue;
-      const int face = 2 * ax + (c[ax] < 0 ? 0 : 1);
-      const int kind = bc.kind[face];
-      if (kind == kInflow) {
-        val = sign * (Real)bc.cons[face][role];
-        done = true;
-        break;
-      }
-      c[ax] = map_index(c[ax], n[ax], kind);
-      if (kind == kReflect && role == kMx + ax) sign = -sign;
-    }
-    if (!done) val = sign * f[cell(g, c[0], c[1], c[2])];
-    f[cg] = val;
-  }
+  for (int role = 0; role < 5; ++role)
+    F.U[par][role][cg] = ghost_value(g, bc, F.U[par][role], role, i, j, k, 0.0);
 }
 
 long long ghost_count(const GridDev& g) {
@@ -272,17 +326,6 @@ long long ghost_count(const GridDev& g) {
 }
 
 // ==================================================================== time step
-// signal-speed max of U[par] over interior non-vacuum cells into smax_bits[cur]
-__device__ __forceinline__ double signal_speed(const GridDev& g, Real r, Real mx, Real my, Real mz,
-                                               Real E) {
-  if (!(r > (Real)g.rho_vac)) return 0.0;
-  Real ux, uy, uz, p;
-  primitive(g, r, mx, my, mz, E, ux, uy, uz, p);
-  const Real cs = sqrt((Real)g.gamma * p / r);
-  const Real sp = cs + fabs(ux) + fabs(uy) + fabs(uz);
-  return (double)sp;
-}
-
 __device__ __forceinline__ void block_max_to(double v, unsigned long long* dst) {
   __shared__ double red[16];
   v = wave_max(v);
@@ -358,16 +401,24 @@ __global__ void k_end(Ctrl* ctrl) {
   ctrl->active = 0;
 }
 
+// ==================================================================== LDS planes
+// slot of plane k in a ring of three
+__device__ __forceinline__ int ring3(int k) { return ((k % 3) + 3) % 3; }
+__device__ __forceinline__ int hidx(int hx, int hy) { return hy * HX + hx; }
+
 // ==================================================================== stage P
 // Predictor, Eq. (5): m* = m - dt A, E* = E - dt B with Q = -(0, A, B) of Eq. (7)
-// on the lattice; xi* = dt (u^n + u*)/2.
-__global__ void __launch_bounds__(256) k_stage_p(Fields<Real> F, GridDev g,
-                                                 const Ctrl* __restrict__ ctrl) {
+// on the lattice; xi* = dt (u^n + u*)/2; psi* = psi(x + xi*).
+struct PlaneP {
+  Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP], psi[3][HP];
+};
+
+__global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g,
+                                                const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  Tile T;
+  if (!tile_of(g, tz, T)) return;
+  __shared__ PlaneP S;
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
   const Real* __restrict__ MX = F.U[par][1];
@@ -376,152 +427,304 @@ __global__ void __launch_bounds__(256) k_stage_p(Fields<Real> F, GridDev g,
   const Real* __restrict__ EE = F.U[par][4];
   const Real* __restrict__ PS = F.psi;
   const double dt = ctrl->dt;
-  const long long c = cell(g, i, j, k);
-  const Real rc = R[c];
-  Real uc[3], pc;
-  primitive(g, rc, MX[c], MY[c], MZ[c], EE[c], uc[0], uc[1], uc[2], pc);
-  const Real fc = sqrt((Real)2 * pc);
-  const Real psc = PS[c];
-  Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
-#pragma unroll
-  for (int q = 0; q < 13; ++q) {
-    Acc ta[2][3], tg[2][3], te[2];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int sg = side == 0 ? 1 : -1;
-      const int ox = sg * kO13[q][0], oy = sg * kO13[q][1], oz = sg * kO13[q][2];
-      const long long jn = c + ox + (long long)oy * g.sx + (long long)oz * g.sxy;
-      Real uj[3], pj;
-      primitive(g, R[jn], MX[jn], MY[jn], MZ[jn], EE[jn], uj[0], uj[1], uj[2], pj);
-      const Real fj = sqrt((Real)2 * pj);
-      const Real Kx = (Real)(sg * g.klat[q][0]);
-      const Real Ky = (Real)(sg * g.klat[q][1]);
-      const Real Kz = (Real)(sg * g.klat[q][2]);
-      const Acc ff = (Acc)fc * (Acc)fj;
-      const Acc dpsi = (Acc)PS[jn] - (Acc)psc;
-      const Acc sp = ff + (Acc)rc * dpsi;
-      const Real ub = (Real)0.5 * ((uc[0] + uj[0]) * Kx + (uc[1] + uj[1]) * Ky + (uc[2] + uj[2]) * Kz);
-      ta[side][0] = sp * (Acc)Kx;
-      ta[side][1] = sp * (Acc)Ky;
-      ta[side][2] = sp * (Acc)Kz;
-      tg[side][0] = dpsi * (Acc)Kx;
-      tg[side][1] = dpsi * (Acc)Ky;
-      tg[side][2] = dpsi * (Acc)Kz;
-      te[side] = ff * (Acc)ub;
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+  const int i = T.x0 + tx, j = T.y0 + ty;
+  const bool in = i < g.nx && j < g.ny;
+
+  auto load = [&](int k) {
+    const int s = ring3(k);
+    for (int q = tid; q < HP; q += NT) {
+      const int hx = q % HX, hy = q / HX;
+      const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
+      if (ii > g.nx || jj > g.ny) continue;
+      const long long c = cell(g, ii, jj, k);
+      const Real r = R[c];
+      Real ux, uy, uz, p;
+      primitive(g, r, MX[c], MY[c], MZ[c], EE[c], ux, uy, uz, p);
+      S.rho[s][q] = r;
+      S.phi[s][q] = sqrt((Real)2 * p);
+      S.ux[s][q] = ux;
+      S.uy[s][q] = uy;
+      S.uz[s][q] = uz;
+      S.psi[s][q] = PS[c];
     }
+  };
+
+  load(T.z0 - 1);
+  load(T.z0);
+  for (int k = T.z0; k < T.z1; ++k) {
+    load(k + 1);
+    __syncthreads();
+    if (in) {
+      const int s0 = ring3(k), c0 = hidx(tx + 1, ty + 1);
+      auto nb = [&](int ox, int oy, int oz) { return ring3(k + oz) * HP + hidx(tx + 1 + ox, ty + 1 + oy); };
+      const Real rc = S.rho[s0][c0], fc = S.phi[s0][c0], psc = S.psi[s0][c0];
+      const Real uc[3] = {S.ux[s0][c0], S.uy[s0][c0], S.uz[s0][c0]};
+      const Real* phi_ = &S.phi[0][0];
+      const Real* ux_ = &S.ux[0][0];
+      const Real* uy_ = &S.uy[0][0];
+      const Real* uz_ = &S.uz[0][0];
+      const Real* psi_ = &S.psi[0][0];
+      Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
+      Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      a[d] = a[d] + (ta[0][d] + ta[1][d]);
-      gp[d] = gp[d] + (tg[0][d] + tg[1][d]);
+      for (int q = 0; q < 13; ++q) {
+        const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
+        const int np = nb(ox, oy, oz), nm = nb(-ox, -oy, -oz);
+        const Real Kx = (Real)g.klat[q][0], Ky = (Real)g.klat[q][1], Kz = (Real)g.klat[q][2];
+        if constexpr (kF64) {
+          // the two terms of the pair, each as the scheme writes it, then their sum;
+          // components whose offset is 0 carry an exact zero and are skipped
+          Acc ta[2][3], tg[2][3], te[2];
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int n = side == 0 ? np : nm;
+            const Real sg = side == 0 ? (Real)1 : (Real)-1;
+            const Real kx = sg * Kx, ky = sg * Ky, kz = sg * Kz;
+            const Acc ff = fc * phi_[n];
+            const Acc dpsi = psi_[n] - psc;
+            const Acc sp = ff + rc * dpsi;
+            Acc ub = (uc[0] + ux_[n]) * kx;
+            if (ox == 0) ub = (uc[1] + uy_[n]) * ky;
+            else if (oy != 0) ub = ub + (uc[1] + uy_[n]) * ky;
+            if (oz != 0) ub = ub + (uc[2] + uz_[n]) * kz;
+            ub = 0.5 * ub;
+            ta[side][0] = sp * kx;
+            ta[side][1] = sp * ky;
+            ta[side][2] = sp * kz;
+            tg[side][0] = dpsi * kx;
+            tg[side][1] = dpsi * ky;
+            tg[side][2] = dpsi * kz;
+            te[side] = ff * ub;
+          }
+          if (ox != 0) {
+            a[0] = a[0] + (ta[0][0] + ta[1][0]);
+            gp[0] = gp[0] + (tg[0][0] + tg[1][0]);
+          }
+          if (oy != 0) {
+            a[1] = a[1] + (ta[0][1] + ta[1][1]);
+            gp[1] = gp[1] + (tg[0][1] + tg[1][1]);
+          }
+          if (oz != 0) {
+            a[2] = a[2] + (ta[0][2] + ta[1][2]);
+            gp[2] = gp[2] + (tg[0][2] + tg[1][2]);
+          }
+          be = be + (te[0] + te[1]);
+        } else {
+          // pair difference in FP64: phi_c (phi_+ - phi_-) + rho_c (psi_+ - psi_-),
+          // exact for FP32 inputs up to one rounding, then times the lattice K
+          const Acc dphi = (Acc)phi_[np] - (Acc)phi_[nm];
+          const Acc dpsi = (Acc)psi_[np] - (Acc)psi_[nm];
+          const Real s = (Real)((Acc)fc * dphi + (Acc)rc * dpsi);
+          const Real ds = (Real)dpsi;
+          if (ox != 0) {
+            af[0] += s * Kx;
+            gf[0] += ds * Kx;
+          }
+          if (oy != 0) {
+            af[1] += s * Ky;
+            gf[1] += ds * Ky;
+          }
+          if (oz != 0) {
+            af[2] += s * Kz;
+            gf[2] += ds * Kz;
+          }
+          Real upk = 0, umk = 0;
+          if (ox != 0) {
+            upk += (uc[0] + ux_[np]) * Kx;
+            umk += (uc[0] + ux_[nm]) * Kx;
+          }
+          if (oy != 0) {
+            upk += (uc[1] + uy_[np]) * Ky;
+            umk += (uc[1] + uy_[nm]) * Ky;
+          }
+          if (oz != 0) {
+            upk += (uc[2] + uz_[np]) * Kz;
+            umk += (uc[2] + uz_[nm]) * Kz;
+          }
+          bf += (Real)0.5 * fc * (phi_[np] * upk - phi_[nm] * umk);
+        }
+      }
+      const long long c = cell(g, i, j, k);
+      Real ms[3], Es;
+      const Real m0[3] = {MX[c], MY[c], MZ[c]};
+      if constexpr (kF64) {
+        const Acc B = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ms[d] = m0[d] - dt * a[d];
+        Es = EE[c] - dt * B;
+      } else {
+        const Real B = bf + rc * (uc[0] * gf[0] + uc[1] * gf[1] + uc[2] * gf[2]);
+        const Real rdt = (Real)dt;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ms[d] = m0[d] - rdt * af[d];
+        Es = EE[c] - rdt * B;
+      }
+      F.ms[0][c] = ms[0];
+      F.ms[1][c] = ms[1];
+      F.ms[2][c] = ms[2];
+      F.ms[3][c] = Es;
+      Real us[3], ps;
+      primitive(g, rc, ms[0], ms[1], ms[2], Es, us[0], us[1], us[2], ps);
+      const Real hdt = (Real)(0.5 * dt);
+      Real xi[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        xi[d] = hdt * (uc[d] + us[d]);
+        F.xs[d][c] = xi[d];
+      }
+      auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
+      F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
     }
-    be = be + (te[0] + te[1]);
+    __syncthreads();
   }
-  const Acc B = be + (Acc)rc * ((Acc)uc[0] * gp[0] + (Acc)uc[1] * gp[1] + (Acc)uc[2] * gp[2]);
-  const Real m0[3] = {MX[c], MY[c], MZ[c]};
-  Real ms[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) ms[d] = (Real)((Acc)m0[d] - dt * a[d]);
-  const Real Es = (Real)((Acc)EE[c] - dt * B);
-  F.ms[0][c] = ms[0];
-  F.ms[1][c] = ms[1];
-  F.ms[2][c] = ms[2];
-  F.ms[3][c] = Es;
-  Real us[3], ps;
-  primitive(g, rc, ms[0], ms[1], ms[2], Es, us[0], us[1], us[2], ps);
-  const Real hdt = (Real)(0.5 * dt);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) F.xs[d][c] = hdt * (uc[d] + us[d]);
 }
 
 // ==================================================================== stage C
 // Corrector, Eq. (6): m~ = (m + m*)/2 - (dt/2) A*, E~ likewise, with Q(U*, r*)
 // evaluated at the displaced particles r* = x + xi* (kernel gradients of the
-// displaced pairs, psi interpolated at r*); xi = xi*/2 + dt (u^n + u~)/4.
-__global__ void __launch_bounds__(256) k_stage_c(Fields<Real> F, GridDev g,
-                                                 const Ctrl* __restrict__ ctrl) {
+// displaced pairs, psi at r*); xi = xi*/2 + dt (u^n + u~)/4.
+struct PlaneC {
+  Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP];
+  Real xx[3][HP], xy[3][HP], xz[3][HP], psi[3][HP];
+};
+
+__global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g,
+                                                const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  Tile T;
+  if (!tile_of(g, tz, T)) return;
+  __shared__ PlaneC S;
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
   const Real* __restrict__ MSX = F.ms[0];
   const Real* __restrict__ MSY = F.ms[1];
   const Real* __restrict__ MSZ = F.ms[2];
   const Real* __restrict__ ES = F.ms[3];
-  const Real* __restrict__ XX = F.xs[0];
-  const Real* __restrict__ XY = F.xs[1];
-  const Real* __restrict__ XZ = F.xs[2];
-  const Real* __restrict__ PS = F.psi;
   const double dt = ctrl->dt;
   const Real h = (Real)g.h;
-  const long long c = cell(g, i, j, k);
-  const Real rc = R[c];
-  Real uc[3], pc;
-  primitive(g, rc, MSX[c], MSY[c], MSZ[c], ES[c], uc[0], uc[1], uc[2], pc);
-  const Real fc = sqrt((Real)2 * pc);
-  const Real xc[3] = {XX[c], XY[c], XZ[c]};
-  const Real psc = psi_at(g, PS, c, xc[0], xc[1], xc[2]);
-  Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+  const int i = T.x0 + tx, j = T.y0 + ty;
+  const bool in = i < g.nx && j < g.ny;
+
+  auto load = [&](int k) {
+    const int s = ring3(k);
+    for (int q = tid; q < HP; q += NT) {
+      const int hx = q % HX, hy = q / HX;
+      const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
+      if (ii > g.nx || jj > g.ny) continue;
+      const long long c = cell(g, ii, jj, k);
+      const Real r = R[c];
+      Real ux, uy, uz, p;
+      primitive(g, r, MSX[c], MSY[c], MSZ[c], ES[c], ux, uy, uz, p);
+      S.rho[s][q] = r;
+      S.phi[s][q] = sqrt((Real)2 * p);
+      S.ux[s][q] = ux;
+      S.uy[s][q] = uy;
+      S.uz[s][q] = uz;
+      S.xx[s][q] = F.xs[0][c];
+      S.xy[s][q] = F.xs[1][c];
+      S.xz[s][q] = F.xs[2][c];
+      S.psi[s][q] = F.psis[c];
+    }
+  };
+
+  load(T.z0 - 1);
+  load(T.z0);
+  for (int k = T.z0; k < T.z1; ++k) {
+    load(k + 1);
+    __syncthreads();
+    if (in) {
+      const int s0 = ring3(k), c0 = hidx(tx + 1, ty + 1);
+      auto nb = [&](int ox, int oy, int oz) { return ring3(k + oz) * HP + hidx(tx + 1 + ox, ty + 1 + oy); };
+      const Real* phi_ = &S.phi[0][0];
+      const Real* ux_ = &S.ux[0][0];
+      const Real* uy_ = &S.uy[0][0];
+      const Real* uz_ = &S.uz[0][0];
+      const Real* xx_ = &S.xx[0][0];
+      const Real* xy_ = &S.xy[0][0];
+      const Real* xz_ = &S.xz[0][0];
+      const Real* psi_ = &S.psi[0][0];
+      const Real rc = S.rho[s0][c0], fc = S.phi[s0][c0], psc = S.psi[s0][c0];
+      const Real uc[3] = {S.ux[s0][c0], S.uy[s0][c0], S.uz[s0][c0]};
+      const Real xc[3] = {S.xx[s0][c0], S.xy[s0][c0], S.xz[s0][c0]};
+      Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
+      Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0;
 #pragma unroll 1
-  for (int q = 0; q < 13; ++q) {
-    Acc ta[2][3], tg[2][3], te[2];
+      for (int q = 0; q < 13; ++q) {
+        const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
+        Real K[2][3], ub[2];
+        Acc sp[2], dpsi[2], ff[2];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int sg = side == 0 ? 1 : -1;
-      const int ox = sg * kO13[q][0], oy = sg * kO13[q][1], oz = sg * kO13[q][2];
-      const long long jn = c + ox + (long long)oy * g.sx + (long long)oz * g.sxy;
-      Real uj[3], pj;
-      primitive(g, R[jn], MSX[jn], MSY[jn], MSZ[jn], ES[jn], uj[0], uj[1], uj[2], pj);
-      const Real fj = sqrt((Real)2 * pj);
-      const Real xj[3] = {XX[jn], XY[jn], XZ[jn]};
-      const Real psj = psi_at(g, PS, jn, xj[0], xj[1], xj[2]);
-      const Real dx = (Real)(-ox) * h + (xc[0] - xj[0]);
-      const Real dy = (Real)(-oy) * h + (xc[1] - xj[1]);
-      const Real dz = (Real)(-oz) * h + (xc[2] - xj[2]);
-      Real Kx, Ky, Kz;
-      kgrad(g, dx, dy, dz, Kx, Ky, Kz);
-      const Acc ff = (Acc)fc * (Acc)fj;
-      const Acc dpsi = (Acc)psj - (Acc)psc;
-      const Acc sp = ff + (Acc)rc * dpsi;
-      const Real ub = (Real)0.5 * ((uc[0] + uj[0]) * Kx + (uc[1] + uj[1]) * Ky + (uc[2] + uj[2]) * Kz);
-      ta[side][0] = sp * (Acc)Kx;
-      ta[side][1] = sp * (Acc)Ky;
-      ta[side][2] = sp * (Acc)Kz;
-      tg[side][0] = dpsi * (Acc)Kx;
-      tg[side][1] = dpsi * (Acc)Ky;
-      tg[side][2] = dpsi * (Acc)Kz;
-      te[side] = ff * (Acc)ub;
-    }
+        for (int side = 0; side < 2; ++side) {
+          const int sg = side == 0 ? 1 : -1;
+          const int n = nb(sg * ox, sg * oy, sg * oz);
+          const Real dx = (Real)(-sg * ox) * h + (xc[0] - xx_[n]);
+          const Real dy = (Real)(-sg * oy) * h + (xc[1] - xy_[n]);
+          const Real dz = (Real)(-sg * oz) * h + (xc[2] - xz_[n]);
+          kgrad(g, dx, dy, dz, K[side][0], K[side][1], K[side][2]);
+          ff[side] = (Acc)fc * (Acc)phi_[n];
+          dpsi[side] = (Acc)psi_[n] - (Acc)psc;
+          sp[side] = ff[side] + (Acc)rc * dpsi[side];
+          ub[side] = (Real)0.5 * ((uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
+                                  (uc[2] + uz_[n]) * K[side][2]);
+        }
+        if constexpr (kF64) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      a[d] = a[d] + (ta[0][d] + ta[1][d]);
-      gp[d] = gp[d] + (tg[0][d] + tg[1][d]);
+          for (int d = 0; d < 3; ++d) {
+            a[d] = a[d] + (sp[0] * K[0][d] + sp[1] * K[1][d]);
+            gp[d] = gp[d] + (dpsi[0] * K[0][d] + dpsi[1] * K[1][d]);
+          }
+          be = be + (ff[0] * ub[0] + ff[1] * ub[1]);
+        } else {
+          // split the pair into its odd and even parts: the large sum of the two
+          // pressure terms meets only K+ + K- (zero on the lattice); the
+          // well-balance cancellation sp+ - sp- is taken in FP64
+          const Real dsp = (Real)(sp[0] - sp[1]);
+          const Real ssp = (Real)(sp[0] + sp[1]);
+          const Real d0 = (Real)dpsi[0], d1 = (Real)dpsi[1];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const Real kd = (Real)0.5 * (K[0][d] - K[1][d]);
+            const Real ks = (Real)0.5 * (K[0][d] + K[1][d]);
+            af[d] += dsp * kd + ssp * ks;
+            gf[d] += d0 * K[0][d] + d1 * K[1][d];
+          }
+          bf += (Real)ff[0] * ub[0] + (Real)ff[1] * ub[1];
+        }
+      }
+      const long long c = cell(g, i, j, k);
+      const Real m0[3] = {F.U[par][1][c], F.U[par][2][c], F.U[par][3][c]};
+      const Real E0 = F.U[par][4][c];
+      Real un[3], pn;
+      primitive(g, rc, m0[0], m0[1], m0[2], E0, un[0], un[1], un[2], pn);
+      const Real msc[3] = {MSX[c], MSY[c], MSZ[c]};
+      Real mt[3], Et;
+      if constexpr (kF64) {
+        const Acc B = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
+        const Acc hdt = 0.5 * dt;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) mt[d] = 0.5 * (m0[d] + msc[d]) - hdt * a[d];
+        Et = 0.5 * (E0 + ES[c]) - hdt * B;
+      } else {
+        const Real B = bf + rc * (uc[0] * gf[0] + uc[1] * gf[1] + uc[2] * gf[2]);
+        const Real hdt = (Real)(0.5 * dt);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) mt[d] = (Real)0.5 * (m0[d] + msc[d]) - hdt * af[d];
+        Et = (Real)0.5 * (E0 + ES[c]) - hdt * B;
+      }
+      F.mt[0][c] = mt[0];
+      F.mt[1][c] = mt[1];
+      F.mt[2][c] = mt[2];
+      F.mt[3][c] = Et;
+      Real ut[3], pt;
+      primitive(g, rc, mt[0], mt[1], mt[2], Et, ut[0], ut[1], ut[2], pt);
+      const Real qdt = (Real)(0.25 * dt);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) F.xt[d][c] = (Real)0.5 * xc[d] + qdt * (un[d] + ut[d]);
     }
-    be = be + (te[0] + te[1]);
+    __syncthreads();
   }
-  const Acc B = be + (Acc)rc * ((Acc)uc[0] * gp[0] + (Acc)uc[1] * gp[1] + (Acc)uc[2] * gp[2]);
-  // U^n at the cell and its velocity
-  const Real m0[3] = {F.U[par][1][c], F.U[par][2][c], F.U[par][3][c]};
-  const Real E0 = F.U[par][4][c];
-  Real un[3], pn;
-  primitive(g, rc, m0[0], m0[1], m0[2], E0, un[0], un[1], un[2], pn);
-  const Real msc[3] = {MSX[c], MSY[c], MSZ[c]};
-  const Acc hdt = 0.5 * dt;
-  Real mt[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) mt[d] = (Real)((Acc)((Real)0.5 * (m0[d] + msc[d])) - hdt * a[d]);
-  const Real Et = (Real)((Acc)((Real)0.5 * (E0 + ES[c])) - hdt * B);
-  F.mt[0][c] = mt[0];
-  F.mt[1][c] = mt[1];
-  F.mt[2][c] = mt[2];
-  F.mt[3][c] = Et;
-  Real ut[3], pt;
-  primitive(g, rc, mt[0], mt[1], mt[2], Et, ut[0], ut[1], ut[2], pt);
-  const Real qdt = (Real)(0.25 * dt);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) F.xt[d][c] = (Real)0.5 * xc[d] + qdt * (un[d] + ut[d]);
 }
 
 // ==================================================================== stage E
@@ -532,8 +735,14 @@ __device__ __forceinline__ void acoustic_dissipation(const GridDev& g, int axis,
   Real uL[3], uR[3], pL, pR;
   primitive(g, L[0], L[1], L[2], L[3], L[4], uL[0], uL[1], uL[2], pL);
   primitive(g, Rr[0], Rr[1], Rr[2], Rr[3], Rr[4], uR[0], uR[1], uR[2], pR);
-  const Real cL = L[0] > (Real)g.rho_vac ? sqrt((Real)g.gamma * pL / L[0]) : (Real)0;
-  const Real cR = Rr[0] > (Real)g.rho_vac ? sqrt((Real)g.gamma * pR / Rr[0]) : (Real)0;
+  Real cL, cR;
+  if constexpr (kF64) {
+    cL = L[0] > (Real)g.rho_vac ? sqrt((Real)g.gamma * pL / L[0]) : (Real)0;
+    cR = Rr[0] > (Real)g.rho_vac ? sqrt((Real)g.gamma * pR / Rr[0]) : (Real)0;
+  } else {
+    cL = L[0] > (Real)g.rho_vac ? sqrtf((Real)g.gamma * pL * __builtin_amdgcn_rcpf(L[0])) : (Real)0;
+    cR = Rr[0] > (Real)g.rho_vac ? sqrtf((Real)g.gamma * pR * __builtin_amdgcn_rcpf(Rr[0])) : (Real)0;
+  }
   const Real a = fmax(fabs(uL[axis]) + cL, fabs(uR[axis]) + cR);
   const Real kk = (Real)-0.5 * a * fmin(L[0], Rr[0]);
   const Real kt = (Real)0.5 * kk;
@@ -543,78 +752,214 @@ __device__ __forceinline__ void acoustic_dissipation(const GridDev& g, int axis,
   D[4] = (Real)0.5 * ((uL[0] + uR[0]) * D[1] + (uL[1] + uR[1]) * D[2] + (uL[2] + uR[2]) * D[3]);
 }
 
-// swept content of face (cL | cL + st) along axis d, all five components
-__device__ __forceinline__ void face_flux(const GridDev& g, const Real* const* Un,
-                                          const Real* const* Ut, const Real* __restrict__ xi,
-                                          long long cL, long long st, int axis, Real dt,
-                                          Real Fout[5]) {
-  const long long cR = cL + st;
-  const Real xL = xi[cL], xR = xi[cR];
-  const Real nuL = xL * (Real)g.inv_h, nuR = xR * (Real)g.inv_h;
+// Swept content of one face (Eq. (8) shifted reconstruction, HLL with the
+// advective speeds = max(xi_L,0) U^L + min(xi_R,0) U^R, plus the damping).
+// u4[v][0..3]: component v of U^n at cells L-1, L, L+1 (= R), R+1;
+// bL, bR: post-Lagrange bases of L and R; xL, xR: particle offsets along axis.
+__device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real u4[5][4],
+                                          const Real bL[5], const Real bR[5], Real xL, Real xR,
+                                          Real dt, Real Fo[5]) {
+  const Real nuL = xL * (Real)g.inv_h;
+  const Real nuR = xR * (Real)g.inv_h;
   Real UL[5], UR[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const Real* U = Un[v];
-    const Real sL = minmod(U[cL + st] - U[cL], U[cL] - U[cL - st]);
-    const Real sR = minmod(U[cR + st] - U[cR], U[cR] - U[cR - st]);
-    const Real BL = Ut[v][cL], BR = Ut[v][cR];
-    UL[v] = BL + (Real)0.5 * ((Real)1 - nuL) * sL;
-    UR[v] = BR - (Real)0.5 * ((Real)1 + nuR) * sR;
-    Fout[v] = fmax(xL, (Real)0) * UL[v] + fmin(xR, (Real)0) * UR[v];
+    const Real sL = minmod(u4[v][2] - u4[v][1], u4[v][1] - u4[v][0]);
+    const Real sR = minmod(u4[v][3] - u4[v][2], u4[v][2] - u4[v][1]);
+    UL[v] = bL[v] + (Real)0.5 * ((Real)1 - nuL) * sL;
+    UR[v] = bR[v] - (Real)0.5 * ((Real)1 + nuR) * sR;
+    Fo[v] = fmax(xL, (Real)0) * UL[v] + fmin(xR, (Real)0) * UR[v];
   }
   Real D[5];
   acoustic_dissipation(g, axis, UL, UR, D);
 #pragma unroll
-  for (int v = 1; v < 5; ++v) Fout[v] = Fout[v] + dt * D[v];
+  for (int v = 1; v < 5; ++v) Fo[v] = Fo[v] + dt * D[v];
 }
 
-__global__ void __launch_bounds__(256) k_stage_e(Fields<Real> F, GridDev g, Ctrl* ctrl,
-                                                 double* __restrict__ partials) {
+struct PlaneE {
+  Real u[5][EP];      // U^n of the current plane, two-cell halo
+  Real b[4][HP];      // m~, E~ of the current plane, one-cell halo
+  Real xx[HP], xy[HP];
+};
+
+__device__ __forceinline__ int eidx(int ex, int ey) { return ey * EX + ex; }
+
+__global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ctrl* ctrl,
+                                                double* __restrict__ partials, int tz) {
   if (!ctrl->active) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  Tile T;
+  const bool have = tile_of(g, tz, T);
+  __shared__ PlaneE S;
+  __shared__ double red[6][NT / kWave];
+  __shared__ int redb;
   const int par = ctrl->par;
   const Real dt = (Real)ctrl->dt;
-  const bool in = i < g.nx && j < g.ny;
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double smax = 0.0;
   int bad = 0;
-  if (in) {
-    const long long c = cell(g, i, j, k);
-    const Real* Un[5] = {F.U[par][0], F.U[par][1], F.U[par][2], F.U[par][3], F.U[par][4]};
-    const Real* Ut[5] = {F.U[par][0], F.mt[0], F.mt[1], F.mt[2], F.mt[3]};
-    const long long stride[3] = {1, (long long)g.sx, g.sxy};
-    Real acc[5] = {(Real)0, (Real)0, (Real)0, (Real)0, (Real)0};
+  if (tid == 0) redb = 0;
+  if (have) {
+    const int i = T.x0 + tx, j = T.y0 + ty;
+    const bool in = i < g.nx && j < g.ny;
+    Real* const* Un = F.U[par];
+    Real* const* Uo = F.U[1 - par];
+    // own column: U^n at k-1..k+2, bases (U~) at k, k+1, xi_z at k, k+1, z-face flux k-1/2
+    Real uq[5][4], bq[2][5], xq[2], Fz[5];
+    const long long c0 = in ? cell(g, i, j, T.z0) : 0;
+    auto ld_col = [&](int dk, Real out[5]) {
+      const long long c = c0 + (long long)dk * g.sxy;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      Real Fp[5], Fm[5];
-      face_flux(g, Un, Ut, F.xt[d], c, stride[d], d, dt, Fp);
-      face_flux(g, Un, Ut, F.xt[d], c - stride[d], stride[d], d, dt, Fm);
+      for (int v = 0; v < 5; ++v) out[v] = Un[v][c];
+    };
+    auto ld_base = [&](int dk, Real out[5]) {
+      const long long c = c0 + (long long)dk * g.sxy;
+      out[0] = Un[0][c];
+      out[1] = F.mt[0][c];
+      out[2] = F.mt[1][c];
+      out[3] = F.mt[2][c];
+      out[4] = F.mt[3][c];
+    };
+    if (in) {
+      // face z0 - 1/2 needs U^n at z0-2 .. z0+1 and the bases at z0-1, z0
+      Real t[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fm[v]);
+      for (int q = 0; q < 4; ++q) {
+        ld_col(q - 2, t);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) uq[v][q] = t[v];
+      }
+      ld_base(-1, bq[0]);
+      ld_base(0, bq[1]);
+      xq[0] = F.xt[2][c0 - g.sxy];
+      xq[1] = F.xt[2][c0];
+      face_flux(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fz);
+      // shift so that uq holds U^n at z0-1 .. z0+2
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        uq[v][0] = uq[v][1];
+        uq[v][1] = uq[v][2];
+        uq[v][2] = uq[v][3];
+      }
+      ld_col(2, t);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) uq[v][3] = t[v];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) bq[0][v] = bq[1][v];
+      xq[0] = xq[1];
     }
-    Real nv[5];
+    for (int k = T.z0; k < T.z1; ++k) {
+      const int dk = k - T.z0;
+      // current plane into LDS: U^n with a two-cell halo, bases and x/y offsets with one
+      for (int q = tid; q < EP; q += NT) {
+        const int ex = q % EX, ey = q / EX;
+        const int ii = T.x0 - 2 + ex, jj = T.y0 - 2 + ey;
+        if (ii > g.nx + 1 || jj > g.ny + 1) continue;
+        const long long c = cell(g, ii, jj, k);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) nv[v] = Ut[v][c] - (Real)g.inv_h * acc[v];
+        for (int v = 0; v < 5; ++v) S.u[v][q] = Un[v][c];
+      }
+      for (int q = tid; q < HP; q += NT) {
+        const int hx = q % HX, hy = q / HX;
+        const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
+        if (ii > g.nx || jj > g.ny) continue;
+        const long long c = cell(g, ii, jj, k);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      F.U[1 - par][v][c] = nv[v];
-      if (!isfinite(nv[v])) bad |= kBadNonFinite;
-      tot[v] = (double)nv[v];
+        for (int v = 0; v < 4; ++v) S.b[v][q] = F.mt[v][c];
+        S.xx[q] = F.xt[0][c];
+        S.xy[q] = F.xt[1][c];
+      }
+      __syncthreads();
+      if (in) {
+        const long long c = c0 + (long long)dk * g.sxy;
+        // base and z-offset of plane k+1 for the upper z face
+        ld_base(dk + 1, bq[1]);
+        xq[1] = F.xt[2][c + g.sxy];
+        Real acc[5];
+        Real Fp[5], Fm[5];
+        // x faces
+        {
+          Real u4[5][4], bl[5], br[5];
+#pragma unroll 1
+          for (int side = 0; side < 2; ++side) {  // 0: face i+1/2, 1: face i-1/2
+            const int lo = side == 0 ? 0 : -1;      // left cell = i + lo
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) u4[v][q] = S.u[v][eidx(tx + 2 + lo - 1 + q, ty + 2)];
+            const int hl = hidx(tx + 1 + lo, ty + 1), hr = hidx(tx + 2 + lo, ty + 1);
+            bl[0] = u4[0][1];
+            br[0] = u4[0][2];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              bl[1 + v] = S.b[v][hl];
+              br[1 + v] = S.b[v][hr];
+            }
+            face_flux(g, 0, u4, bl, br, S.xx[hl], S.xx[hr], dt, side == 0 ? Fp : Fm);
+          }
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] = Fp[v] - Fm[v];
+        }
+        // y faces
+        {
+          Real u4[5][4], bl[5], br[5];
+#pragma unroll 1
+          for (int side = 0; side < 2; ++side) {
+            const int lo = side == 0 ? 0 : -1;
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) u4[v][q] = S.u[v][eidx(tx + 2, ty + 2 + lo - 1 + q)];
+            const int hl = hidx(tx + 1, ty + 1 + lo), hr = hidx(tx + 1, ty + 2 + lo);
+            bl[0] = u4[0][1];
+            br[0] = u4[0][2];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              bl[1 + v] = S.b[v][hl];
+              br[1 + v] = S.b[v][hr];
+            }
+            face_flux(g, 1, u4, bl, br, S.xy[hl], S.xy[hr], dt, side == 0 ? Fp : Fm);
+          }
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fm[v]);
+        }
+        // z faces: k+1/2 new, k-1/2 carried from the previous plane
+        face_flux(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fz[v]);
+        Real nv[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) nv[v] = bq[0][v] - (Real)g.inv_h * acc[v];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          Uo[v][c] = nv[v];
+          if (!isfinite(nv[v])) bad |= kBadNonFinite;
+          tot[v] += (double)nv[v];
+        }
+        if ((double)nv[0] < -g.neg_tol) bad |= kBadNegDensity;
+        if (!bad) smax = fmax(smax, signal_speed(g, nv[0], nv[1], nv[2], nv[3], nv[4]));
+        // advance the column queues to k+1
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          Fz[v] = Fp[v];
+          uq[v][0] = uq[v][1];
+          uq[v][1] = uq[v][2];
+          uq[v][2] = uq[v][3];
+          bq[0][v] = bq[1][v];
+        }
+        xq[0] = xq[1];
+        if (k + 1 < T.z1) {
+          Real t[5];
+          ld_col(dk + 3, t);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) uq[v][3] = t[v];
+        }
+      }
+      __syncthreads();
     }
-    if ((double)nv[0] < -g.neg_tol) bad |= kBadNegDensity;
-    if (!bad) smax = signal_speed(g, nv[0], nv[1], nv[2], nv[3], nv[4]);
   }
   // block epilogue: FP64 totals to a per-block slot, max signal speed, flags
-  __shared__ double red[5][16];
-  __shared__ double redm[16];
-  __shared__ int redb;
-  const int flat = threadIdx.x + blockDim.x * threadIdx.y;
-  const int nthreads = blockDim.x * blockDim.y;
-  const int nw = (nthreads + kWave - 1) / kWave;
-  const int lane = flat % kWave, w = flat / kWave;
-  if (flat == 0) redb = 0;
+  const int lane = tid % kWave, w = tid / kWave;
 #pragma unroll
   for (int v = 0; v < 5; ++v) tot[v] = wave_sum(tot[v]);
   smax = wave_max(smax);
@@ -623,18 +968,17 @@ __global__ void __launch_bounds__(256) k_stage_e(Fields<Real> F, GridDev g, Ctrl
   if (lane == 0) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) red[v][w] = tot[v];
-    redm[w] = smax;
+    red[5][w] = smax;
   }
   __syncthreads();
-  if (flat == 0) {
-    const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    double m = redm[0];
-    for (int q = 1; q < nw; ++q) m = fmax(m, redm[q]);
+  if (tid == 0) {
+    double m = red[5][0];
+    for (int q = 1; q < NT / kWave; ++q) m = fmax(m, red[5][q]);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       double s = red[v][0];
-      for (int q = 1; q < nw; ++q) s += red[v][q];
-      partials[blk * 5 + v] = s;
+      for (int q = 1; q < NT / kWave; ++q) s += red[v][q];
+      partials[(long long)blockIdx.x * 5 + v] = s;
     }
     if (m > 0.0) atomicMax(&ctrl->smax_bits[1 - ctrl->cur], (unsigned long long)__double_as_longlong(m));
     if (redb) atomicOr(&ctrl->status, redb);
@@ -660,10 +1004,21 @@ __global__ void __launch_bounds__(256) k_totals(const double* __restrict__ parti
   }
 }
 
-constexpr int kBx = 64, kBy = 4;
+// z-planes per workgroup: enough workgroups to fill 256 CUs several times over
+int pick_tz(const GridDev& g) {
+  const long long tiles_xy = (long long)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+  int tz = 32;
+  while (tz > 4 && tiles_xy * ((g.nz + tz - 1) / tz) < 2048) tz /= 2;
+  return tz;
+}
+
+int sweep_blocks(const GridDev& g, int tz) {
+  const int n = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + tz - 1) / tz);
+  return (n + kXcd - 1) / kXcd * kXcd;
+}
 
 dim3 cell_grid(const GridDev& g) {
-  return dim3((unsigned)((g.nx + kBx - 1) / kBx), (unsigned)((g.ny + kBy - 1) / kBy), (unsigned)g.nz);
+  return dim3((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)g.nz);
 }
 
 }  // namespace CSPH_TAG
@@ -673,8 +1028,7 @@ using namespace CSPH_TAG;
 
 template <>
 int Launch<Real>::stage_e_blocks(const GridDev& g) {
-  const dim3 gr = cell_grid(g);
-  return (int)(gr.x * gr.y * gr.z);
+  return sweep_blocks(g, pick_tz(g));
 }
 
 template <>
@@ -700,36 +1054,47 @@ hipError_t Launch<Real>::fill_state(const Fields<Real>& F, const GridDev& g, con
 template <>
 hipError_t Launch<Real>::signal_max(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
                                     hipStream_t s) {
-  k_signal_max<<<cell_grid(g), dim3(kBx, kBy), 0, s>>>(F, g, ctrl);
+  k_signal_max<<<cell_grid(g), dim3(64, 4), 0, s>>>(F, g, ctrl);
   return hipGetLastError();
 }
 
 template <>
 hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
-                              double* partials, double dt_max, double t_end, hipStream_t s) {
+                              double* partials, double dt_max, double t_end, hipStream_t s,
+                              hipEvent_t* ev) {
   const long long ng = ghost_count(g);
   const unsigned gb = (unsigned)((ng + 255) / 256);
-  const dim3 gr = cell_grid(g), bl(kBx, kBy);
+  const int tz = pick_tz(g);
+  const unsigned nb = (unsigned)sweep_blocks(g, tz);
+  auto mark = [&](int q) {
+    if (ev) (void)hipEventRecord(ev[q], s);
+  };
+  mark(0);
   k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
   k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
-  k_stage_p<<<gr, bl, 0, s>>>(F, g, ctrl);
+  mark(1);
+  k_stage_p<<<nb, NT, 0, s>>>(F, g, ctrl, tz);
+  mark(2);
+  k_fill_pred<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
+  mark(3);
+  k_stage_c<<<nb, NT, 0, s>>>(F, g, ctrl, tz);
+  mark(4);
   FillSet<Real> fs{};
   for (int q = 0; q < 4; ++q) {
-    fs.f[q] = F.ms[q];
+    fs.f[q] = F.mt[q];
     fs.role[q] = kMx + q;
   }
   for (int q = 0; q < 3; ++q) {
-    fs.f[4 + q] = F.xs[q];
+    fs.f[4 + q] = F.xt[q];
     fs.role[4 + q] = kXx + q;
   }
   fs.n = 7;
   k_fill<<<gb, 256, 0, s>>>(fs, g, bc, ctrl, 1);
-  k_stage_c<<<gr, bl, 0, s>>>(F, g, ctrl);
-  for (int q = 0; q < 4; ++q) fs.f[q] = F.mt[q];
-  for (int q = 0; q < 3; ++q) fs.f[4 + q] = F.xt[q];
-  k_fill<<<gb, 256, 0, s>>>(fs, g, bc, ctrl, 1);
-  k_stage_e<<<gr, bl, 0, s>>>(F, g, ctrl, partials);
+  mark(5);
+  k_stage_e<<<nb, NT, 0, s>>>(F, g, ctrl, partials, tz);
+  mark(6);
   k_end<<<1, 64, 0, s>>>(ctrl);
+  mark(7);
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ csph_status fail(csph_status code, const std::string& msg) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-constexpr int kNumFields = 25;  // U[2][5], psi, ms[4], xs[3], mt[4], xt[3]
+constexpr int kNumFields = 26;  // U[2][5], psi, ms[4], xs[3], psis, mt[4], xt[3]
 
 // kernel normalisation: kappa = 1 / (2 sum_{a,b in {-1,0,1}} g(q_ab)/q_ab),
 // q_ab = sqrt(1 + a^2 + b^2), g(q)/q of the M4 spline (27-point sum exact for
@@ -175,6 +175,13 @@ struct csph_sim {
   bool stepped = false;  // partials describe the current state
   std::vector<double> psi_host;  // interior psi, kept to refill ghosts after BC changes
   bool has_psi = false;
+  // kernel timing: events of up to kProfSteps steps in flight, accumulated at syncs
+  static constexpr int kProfSteps = 64;
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;  // kProfSteps x 8
+  int prof_pending = 0;
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int64_t prof_n[5] = {0, 0, 0, 0, 0};
 
   bool is_f64() const { return desc.dtype == CSPH_F64; }
   char* field_ptr(int k) const { return buf + L.fields_off + (size_t)k * L.field_bytes; }
@@ -190,6 +197,7 @@ void bind_fields(csph_sim* s, Fields<Real>& F) {
   F.psi = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 4; ++v) F.ms[v] = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 3; ++v) F.xs[v] = (Real*)s->field_ptr(k++);
+  F.psis = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 4; ++v) F.mt[v] = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 3; ++v) F.xt[v] = (Real*)s->field_ptr(k++);
 }
@@ -276,13 +284,43 @@ csph_status prepare(csph_sim* s) {
   return CSPH_OK;
 }
 
+// fold the recorded events of completed steps into the per-group totals
+csph_status prof_collect(csph_sim* s) {
+  if (!s->prof_on || s->prof_pending == 0) return CSPH_OK;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < s->prof_pending; ++k) {
+    hipEvent_t* e = &s->prof_ev[(size_t)k * 8];
+    float ms[7];
+    for (int q = 0; q < 7; ++q) HIP_TRY(hipEventElapsedTime(&ms[q], e[q], e[q + 1]));
+    // e0-e1 begin + state fill, e1-e2 P, e2-e3 fill, e3-e4 C, e4-e5 fill, e5-e6 E, e6-e7 end
+    s->prof_ms[0] += ms[1];
+    s->prof_ms[1] += ms[3];
+    s->prof_ms[2] += ms[5];
+    s->prof_ms[3] += ms[0] + ms[2] + ms[4];
+    s->prof_ms[4] += ms[6];
+    for (int q = 0; q < 5; ++q) s->prof_n[q] += 1;
+  }
+  s->prof_pending = 0;
+  return CSPH_OK;
+}
+
 template <typename Real>
 csph_status launch_steps(csph_sim* s, int n, double dt_max, double t_end) {
   csph_status st = prepare<Real>(s);
   if (st) return st;
   Fields<Real>& F = fields_of<Real>(s);
-  for (int k = 0; k < n; ++k)
-    HIP_TRY(Launch<Real>::step(F, s->g, s->bc, s->ctrl, s->partials, dt_max, t_end, s->stream));
+  for (int k = 0; k < n; ++k) {
+    hipEvent_t* ev = nullptr;
+    if (s->prof_on) {
+      if (s->prof_pending == csph_sim::kProfSteps) {
+        st = prof_collect(s);
+        if (st) return st;
+      }
+      ev = &s->prof_ev[(size_t)s->prof_pending * 8];
+      s->prof_pending += 1;
+    }
+    HIP_TRY(Launch<Real>::step(F, s->g, s->bc, s->ctrl, s->partials, dt_max, t_end, s->stream, ev));
+  }
   s->stepped = true;
   return CSPH_OK;
 }
@@ -389,6 +427,7 @@ csph_status csph_create_in(const csph_grid_desc* desc, void* hip_stream, void* d
 csph_status csph_destroy(csph_sim* s) {
   if (!s) return CSPH_OK;
   (void)hipStreamSynchronize(s->stream);
+  for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->owned) (void)hipFree(s->buf);
   delete s;
   return CSPH_OK;
@@ -615,6 +654,37 @@ csph_status csph_get_stage(const csph_sim* s, int32_t which, double* out) {
   const float* src = which < 4 ? s->f32.ms[which] : which < 7 ? s->f32.xs[which - 4]
                    : which < 11 ? s->f32.mt[which - 7] : s->f32.xt[which - 11];
   return download_field<float>(s, src, out);
+}
+
+csph_status csph_profile_enable(csph_sim* s, int32_t on) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (on && s->prof_ev.empty()) {
+    s->prof_ev.resize((size_t)csph_sim::kProfSteps * 8);
+    for (auto& e : s->prof_ev) HIP_TRY(hipEventCreate(&e));
+  }
+  if (!on) {
+    csph_status st = prof_collect(s);
+    if (st) return st;
+  }
+  s->prof_on = on != 0;
+  for (int q = 0; q < 5; ++q) {
+    s->prof_ms[q] = 0.0;
+    s->prof_n[q] = 0;
+  }
+  s->prof_pending = 0;
+  return CSPH_OK;
+}
+
+csph_status csph_profile_read(csph_sim* s, double* avg_ms, int64_t* launches, int32_t n) {
+  if (!s || n < 0 || n > 5) return fail(CSPH_ERR_ARG, "bad arguments");
+  csph_status st = prof_collect(s);
+  if (st) return st;
+  for (int q = 0; q < n; ++q) {
+    const int64_t cnt = q == 3 ? 3 * s->prof_n[q] : q == 4 ? 2 * s->prof_n[q] : s->prof_n[q];
+    if (avg_ms) avg_ms[q] = cnt ? s->prof_ms[q] / (double)cnt : 0.0;
+    if (launches) launches[q] = cnt;
+  }
+  return CSPH_OK;
 }
 
 // batches are implemented in csph_batch.hip

@@ -164,6 +164,18 @@ class Sim:
         check(_lib.load().csph_totals(self._h, _ptr(out)), "csph_totals")
         return out
 
+    PROFILE_GROUPS = ["stage_p", "stage_c", "stage_e", "ghost_fill", "bookkeeping"]
+
+    def profile(self, on=True):
+        check(_lib.load().csph_profile_enable(self._h, int(bool(on))), "csph_profile_enable")
+
+    def profile_read(self):
+        """{group: (average ms per launch, launches)} of the steps since profile(True)."""
+        ms = np.zeros(5)
+        n = np.zeros(5, dtype=np.int64)
+        check(_lib.load().csph_profile_read(self._h, _ptr(ms), _ptr(n), 5), "csph_profile_read")
+        return {g: (float(ms[q]), int(n[q])) for q, g in enumerate(self.PROFILE_GROUPS)}
+
     STAGE_FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
                     "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz"]
 

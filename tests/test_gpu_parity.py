@@ -1,9 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Bars: FP64 build within 1e-12 relative L1 after 100 steps (it evaluates the
-same expressions in the same order, so most cases agree to the last bit); FP32
-build within 1e-5 relative L1 on smooth flows and shock positions within one
-cell.  Each stage's output is also compared after one step, so a failure names
+same expressions in the same order, so the cases agree to the last bit); FP32
+build within 1e-5 relative L1 (of the whole conserved state, and of density,
+momentum and energy each) on smooth flows, and shock positions within one cell.  Each stage's output is also compared after one step, so a failure names
 the stage.
 """
 import math
@@ -100,9 +100,17 @@ def test_smooth_flows_fp32(name, steps, tol):
     announce("smooth_fp32", name, pr.shape, steps)
     g = gpu_sim(pr, "f32")
     g.advance(math.inf, steps)
-    err = rel_l1_vars(g.conserved(), o.conserved())
-    print(f"{name}: FP32 relative L1 vs FP64 oracle = {err:.3e}")
+    Ug, Uo = g.conserved(), o.conserved()
+    err = rel_l1(Ug, Uo)
+    per = [rel_l1(Ug[v], Uo[v]) for v in range(5)]
+    mom = rel_l1(Ug[1:4], Uo[1:4])
+    print(f"{name}: FP32 relative L1 of the state vs FP64 oracle = {err:.3e} (per variable "
+          + ", ".join(f"{e:.2e}" for e in per) + f"; momentum vector {mom:.2e})")
+    # the bar: relative L1 of the whole conserved state, and of rho, momentum and E
+    # each on its own norm (a transverse momentum component that the flow barely
+    # excites is reported, not bounded: its own norm is tiny)
     assert err <= tol
+    assert per[0] <= tol and per[4] <= tol and mom <= tol
     g.close()
 
 
