@@ -6,11 +6,11 @@ load the library; creating a ``Sim`` does, and fails if it has not been built.
 """
 from . import problems  # noqa: F401
 
-__all__ = ["Sim", "from_problem", "problems", "required_bytes"]
+__all__ = ["Sim", "Batch", "from_problem", "problems", "required_bytes"]
 
 
 def __getattr__(name):
-    if name in ("Sim", "from_problem", "required_bytes", "make_desc"):
+    if name in ("Sim", "Batch", "from_problem", "required_bytes", "make_desc"):
         from . import sim
         return getattr(sim, name)
     raise AttributeError(name)

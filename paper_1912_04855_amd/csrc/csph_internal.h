@@ -60,6 +60,9 @@ struct Ctrl {
   int status;                        // kBad* bits
   int smax_valid;                    // smax_bits[cur] describes U^n
   int pad[2];
+  // batch membership: stop after this many steps in total, or at t_end
+  long long step_limit;
+  double t_end;
 };
 
 template <typename Real>
@@ -71,6 +74,18 @@ struct Fields {
   Real* psis;    // psi at the predicted particle positions r* = x + xi*
   Real* mt[4];   // m~x, m~y, m~z, E~
   Real* xt[3];   // xi^{n+1}
+};
+
+// one member of a batch, as the batched kernels see it (device memory)
+template <typename Real>
+struct Inst {
+  Fields<Real> F;
+  GridDev g;
+  BcDev bc;
+  Ctrl* ctrl;
+  double* partials;
+  int tz;
+  int pad;
 };
 
 // up to 7 fields filled by one ghost-cell launch
@@ -93,8 +108,15 @@ struct Launch {
   // one full step: begin, ghosts, stage P, ghosts, stage C, ghosts, stage E, end
   // ev (nullable): 8 events recorded around the launches, for kernel timing
   static hipError_t step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
-                         double* partials, double dt_max, double t_end, hipStream_t s,
+                         double* partials, double dt_max, double t_end, int tz, hipStream_t s,
                          hipEvent_t* ev);
+  // one step of every active member of a batch, one launch per stage
+  static hipError_t batch_step(const Inst<Real>* tab, const int* tile_prefix,
+                               const long long* ghost_prefix, int n, int total_tiles,
+                               long long total_ghosts, int* flags, hipStream_t s);
+  static int tiles(const GridDev& g, int tz);
+  static int default_tz(const GridDev& g);
+  static long long ghosts(const GridDev& g);
   static hipError_t totals(const GridDev& g, const double* partials, int nblocks, double* out,
                            hipStream_t s);
   static int stage_e_blocks(const GridDev& g);

@@ -60,6 +60,7 @@ constexpr int kXcd = 8;
 constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;          // one-cell halo
 constexpr int EX = TX + 4, EY = TY + 4, EP = EX * EY;          // two-cell halo
+constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);        // x and y faces of a tile
 
 // ------------------------------------------------------------------ indexing
 __device__ __forceinline__ long long cell(const GridDev& g, int i, int j, int k) {
@@ -88,19 +89,38 @@ struct Tile {
   int x0, y0, z0, z1;
 };
 
-__device__ __forceinline__ bool tile_of(const GridDev& g, int tz, Tile& t) {
-  const int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY, nbz = (g.nz + tz - 1) / tz;
-  const int n = nbx * nby * nbz;
-  // the grid is rounded up to a multiple of 8 so the XCD inversion is a bijection
-  const int padded = (n + kXcd - 1) / kXcd * kXcd;
-  const int bid = xcd_tile(blockIdx.x, padded);
-  if (bid < 0 || bid >= n) return false;
-  const int bx = bid % nbx, r = bid / nbx, by = r % nby, bz = r / nby;
+__device__ __forceinline__ int tiles_of(const GridDev& g, int tz) {
+  return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + tz - 1) / tz);
+}
+
+// tile number -> tile origin; tiles are numbered x fastest, then y, then z
+__device__ __forceinline__ void tile_at(const GridDev& g, int tz, int id, Tile& t) {
+  const int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY;
+  const int bx = id % nbx, r = id / nbx, by = r % nby, bz = r / nby;
   t.x0 = bx * TX;
   t.y0 = by * TY;
   t.z0 = bz * tz;
   t.z1 = min(t.z0 + tz, g.nz);
+}
+
+// tile of this workgroup in a single-simulation launch (grid padded to 8k)
+__device__ __forceinline__ bool single_tile(const GridDev& g, int tz, Tile& t, int& id) {
+  id = xcd_tile(blockIdx.x, gridDim.x);
+  if (id < 0 || id >= tiles_of(g, tz)) return false;
+  tile_at(g, tz, id, t);
   return true;
+}
+
+// instance owning flattened item `gid` (prefix[q] <= gid < prefix[q+1])
+template <typename I>
+__device__ __forceinline__ int find_inst(const I* __restrict__ prefix, int n, I gid) {
+  int lo = 0, hi = n;  // prefix[lo] <= gid < prefix[hi]
+  if (gid < prefix[0] || gid >= prefix[n]) return -1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= gid) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 
 // ------------------------------------------------------------------ arithmetic
@@ -278,11 +298,10 @@ __device__ __forceinline__ Real ghost_value(const GridDev& g, const BcDev& bc, c
   return sign * f[cell(g, c[0], c[1], c[2])];
 }
 
-__global__ void __launch_bounds__(256) k_fill(FillSet<Real> fs, GridDev g, BcDev bc,
-                                              const Ctrl* __restrict__ ctrl, int check_active) {
-  if (check_active && !ctrl->active) return;
+__device__ __forceinline__ void fill_body(const FillSet<Real>& fs, const GridDev& g, const BcDev& bc,
+                                          const Ctrl* ctrl, long long t) {
   int i, j, k;
-  if (!ghost_cell(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
   for (int q = 0; q < fs.n; ++q) fs.f[q][cg] = ghost_value(g, bc, fs.f[q], fs.role[q], i, j, k, dt);
@@ -290,11 +309,10 @@ __global__ void __launch_bounds__(256) k_fill(FillSet<Real> fs, GridDev g, BcDev
 
 // ghosts of the predicted particles, then psi at their displaced positions for
 // the first ghost layer (the corrector reads psi* of index neighbours only)
-__global__ void __launch_bounds__(256) k_fill_pred(Fields<Real> F, GridDev g, BcDev bc,
-                                                   const Ctrl* __restrict__ ctrl) {
-  if (!ctrl->active) return;
+__device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+                                               const Ctrl* ctrl, long long t) {
   int i, j, k;
-  if (!ghost_cell(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
   for (int q = 0; q < 4; ++q) F.ms[q][cg] = ghost_value(g, bc, F.ms[q], kMx + q, i, j, k, dt);
@@ -310,15 +328,64 @@ __global__ void __launch_bounds__(256) k_fill_pred(Fields<Real> F, GridDev g, Bc
   }
 }
 
-__global__ void __launch_bounds__(256) k_fill_state(Fields<Real> F, GridDev g, BcDev bc,
-                                                    const Ctrl* __restrict__ ctrl) {
-  if (!ctrl->active) return;
+// ghosts of the post-Lagrange particles
+__device__ __forceinline__ void fill_corr_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+                                               const Ctrl* ctrl, long long t) {
   int i, j, k;
-  if (!ghost_cell(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  if (!ghost_cell(g, t, i, j, k)) return;
+  const double dt = ctrl->dt;
+  const long long cg = cell(g, i, j, k);
+  for (int q = 0; q < 4; ++q) F.mt[q][cg] = ghost_value(g, bc, F.mt[q], kMx + q, i, j, k, dt);
+  for (int q = 0; q < 3; ++q) F.xt[q][cg] = ghost_value(g, bc, F.xt[q], kXx + q, i, j, k, dt);
+}
+
+__device__ __forceinline__ void fill_state_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+                                                const Ctrl* ctrl, long long t) {
+  int i, j, k;
+  if (!ghost_cell(g, t, i, j, k)) return;
   const int par = ctrl->par;
   const long long cg = cell(g, i, j, k);
   for (int role = 0; role < 5; ++role)
     F.U[par][role][cg] = ghost_value(g, bc, F.U[par][role], role, i, j, k, 0.0);
+}
+
+__global__ void __launch_bounds__(256) k_fill(FillSet<Real> fs, GridDev g, BcDev bc,
+                                              const Ctrl* __restrict__ ctrl, int check_active) {
+  if (check_active && !ctrl->active) return;
+  fill_body(fs, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_fill_pred(Fields<Real> F, GridDev g, BcDev bc,
+                                                   const Ctrl* __restrict__ ctrl) {
+  if (!ctrl->active) return;
+  fill_pred_body(F, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_fill_corr(Fields<Real> F, GridDev g, BcDev bc,
+                                                   const Ctrl* __restrict__ ctrl) {
+  if (!ctrl->active) return;
+  fill_corr_body(F, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_fill_state(Fields<Real> F, GridDev g, BcDev bc,
+                                                    const Ctrl* __restrict__ ctrl) {
+  if (!ctrl->active) return;
+  fill_state_body(F, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// batched ghost fills: thread -> (instance, ghost cell) through the ghost prefix
+template <int kWhich>
+__global__ void __launch_bounds__(256) k_fill_batch(const Inst<Real>* __restrict__ tab,
+                                                    const long long* __restrict__ prefix, int n) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = find_inst(prefix, n, gid);
+  if (q < 0) return;
+  const Inst<Real>& I = tab[q];
+  if (!I.ctrl->active) return;
+  const long long t = gid - prefix[q];
+  if (kWhich == 0) fill_state_body(I.F, I.g, I.bc, I.ctrl, t);
+  else if (kWhich == 1) fill_pred_body(I.F, I.g, I.bc, I.ctrl, t);
+  else fill_corr_body(I.F, I.g, I.bc, I.ctrl, t);
 }
 
 long long ghost_count(const GridDev& g) {
@@ -355,8 +422,7 @@ __global__ void __launch_bounds__(256) k_signal_max(Fields<Real> F, GridDev g, C
 }
 
 // dt = cfl h / smax, capped by dt_max (> 0) and by the time left to t_end
-__global__ void k_begin(Ctrl* ctrl, GridDev g, double dt_max, double t_end) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void begin_body(Ctrl* ctrl, const GridDev& g, double dt_max, double t_end) {
   if (ctrl->status || ctrl->done) {
     ctrl->active = 0;
     return;
@@ -392,13 +458,44 @@ __global__ void k_begin(Ctrl* ctrl, GridDev g, double dt_max, double t_end) {
   ctrl->smax_bits[1 - ctrl->cur] = 0ULL;
 }
 
-__global__ void k_end(Ctrl* ctrl) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void end_body(Ctrl* ctrl) {
   if (!ctrl->active) return;
   ctrl->par = 1 - ctrl->par;
   ctrl->cur = 1 - ctrl->cur;
   ctrl->smax_valid = 1;
   ctrl->active = 0;
+}
+
+__global__ void k_begin(Ctrl* ctrl, GridDev g, double dt_max, double t_end) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  begin_body(ctrl, g, dt_max, t_end);
+}
+
+__global__ void k_end(Ctrl* ctrl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  end_body(ctrl);
+}
+
+// batch members: each stops at its own step limit or end time
+__global__ void k_begin_batch(const Inst<Real>* __restrict__ tab, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  Ctrl* c = tab[q].ctrl;
+  if (c->nsteps >= c->step_limit) {
+    c->done = 1;
+    c->active = 0;
+    return;
+  }
+  begin_body(c, tab[q].g, 0.0, c->t_end);
+  if (c->active && c->nsteps >= c->step_limit) c->done = 1;
+}
+
+__global__ void k_end_batch(const Inst<Real>* __restrict__ tab, int n, int* __restrict__ flags) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  Ctrl* c = tab[q].ctrl;
+  end_body(c);
+  flags[q] = (c->done ? 1 : 0) | (c->status ? 2 : 0);
 }
 
 // ==================================================================== LDS planes
@@ -413,11 +510,8 @@ struct PlaneP {
   Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP], psi[3][HP];
 };
 
-__global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g,
-                                                const Ctrl* __restrict__ ctrl, int tz) {
-  if (!ctrl->active) return;
-  Tile T;
-  if (!tile_of(g, tz, T)) return;
+__device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDev& g,
+                                             const Ctrl* __restrict__ ctrl, const Tile& T) {
   __shared__ PlaneP S;
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
@@ -589,11 +683,8 @@ struct PlaneC {
   Real xx[3][HP], xy[3][HP], xz[3][HP], psi[3][HP];
 };
 
-__global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g,
-                                                const Ctrl* __restrict__ ctrl, int tz) {
-  if (!ctrl->active) return;
-  Tile T;
-  if (!tile_of(g, tz, T)) return;
+__device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDev& g,
+                                             const Ctrl* __restrict__ ctrl, const Tile& T) {
   __shared__ PlaneC S;
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
@@ -776,19 +867,63 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
   for (int v = 1; v < 5; ++v) Fo[v] = Fo[v] + dt * D[v];
 }
 
+// The FP64 build computes every x and y face of a plane once and shares it
+// through LDS (its faces are expensive: correctly rounded divisions and square
+// roots); the FP32 build, latency-bound rather than ALU-bound here, lets each
+// cell evaluate its own four x-y faces and keeps the higher occupancy.
+constexpr bool kShareFaces = kF64;
+constexpr int NFXS = kShareFaces ? NFX : 1, NFYS = kShareFaces ? NFY : 1;
+
 struct PlaneE {
   Real u[5][EP];      // U^n of the current plane, two-cell halo
   Real b[4][HP];      // m~, E~ of the current plane, one-cell halo
   Real xx[HP], xy[HP];
+  Real fx[5][NFXS];   // x-face fluxes of the tile row by row: face i+1/2, i = x0-1 .. x0+TX-1
+  Real fy[5][NFYS];   // y-face fluxes: face j+1/2, j = y0-1 .. y0+TY-1
 };
+
 
 __device__ __forceinline__ int eidx(int ex, int ey) { return ey * EX + ex; }
 
-__global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ctrl* ctrl,
-                                                double* __restrict__ partials, int tz) {
-  if (!ctrl->active) return;
-  Tile T;
-  const bool have = tile_of(g, tz, T);
+__device__ __forceinline__ bool tile_face(const GridDev& g, const Tile& T, const PlaneE& S,
+                                          int axis, int row, int col, Real dt, Real Fo[5]) {
+  Real u4[5][4], bl[5], br[5];
+  int hl, hr;
+  if (axis == 0) {
+    // face between cells (x0-1+col, y0+row) and (x0+col, y0+row)
+    if (T.y0 + row >= g.ny || T.x0 - 1 + col >= g.nx) return false;
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u4[v][q] = S.u[v][eidx(col + q, row + 2)];
+    hl = hidx(col, row + 1);
+    hr = hidx(col + 1, row + 1);
+  } else {
+    // face between cells (x0+col, y0-1+row) and (x0+col, y0+row)
+    if (T.x0 + col >= g.nx || T.y0 - 1 + row >= g.ny) return false;
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u4[v][q] = S.u[v][eidx(col + 2, row + q)];
+    hl = hidx(col + 1, row);
+    hr = hidx(col + 1, row + 1);
+  }
+  bl[0] = u4[0][1];
+  br[0] = u4[0][2];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    bl[1 + v] = S.b[v][hl];
+    br[1 + v] = S.b[v][hr];
+  }
+  const Real xl = axis == 0 ? S.xx[hl] : S.xy[hl];
+  const Real xr = axis == 0 ? S.xx[hr] : S.xy[hr];
+  face_flux(g, axis, u4, bl, br, xl, xr, dt, Fo);
+  return true;
+}
+
+__device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
+                                             const Tile& T, double* __restrict__ slot) {
+  const bool have = true;
   __shared__ PlaneE S;
   __shared__ double red[6][NT / kWave];
   __shared__ int redb;
@@ -869,59 +1004,62 @@ __global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ct
         S.xx[q] = F.xt[0][c];
         S.xy[q] = F.xt[1][c];
       }
+      if (in) {
+        // base and z-offset of plane k+1 for the upper z face (global loads in flight
+        // while the x-y faces are computed)
+        ld_base(dk + 1, bq[1]);
+        xq[1] = F.xt[2][cell(g, i, j, k + 1)];
+      }
       __syncthreads();
+      if constexpr (kShareFaces) {
+        // every x and y face of the tile once: x faces first, then y faces
+#pragma unroll 1
+        for (int f = tid; f < NFX + NFY; f += NT) {
+          Real Fo[5];
+          if (f < NFX) {
+            if (tile_face(g, T, S, 0, f / (TX + 1), f % (TX + 1), dt, Fo)) {
+#pragma unroll
+              for (int v = 0; v < 5; ++v) S.fx[v][f] = Fo[v];
+            }
+          } else {
+            const int fy = f - NFX;
+            if (tile_face(g, T, S, 1, fy / TX, fy % TX, dt, Fo)) {
+#pragma unroll
+              for (int v = 0; v < 5; ++v) S.fy[v][fy] = Fo[v];
+            }
+          }
+        }
+        __syncthreads();
+      }
       if (in) {
         const long long c = c0 + (long long)dk * g.sxy;
-        // base and z-offset of plane k+1 for the upper z face
-        ld_base(dk + 1, bq[1]);
-        xq[1] = F.xt[2][c + g.sxy];
-        Real acc[5];
-        Real Fp[5], Fm[5];
-        // x faces
-        {
-          Real u4[5][4], bl[5], br[5];
+        Real acc[5], Fp[5];
+        if constexpr (kShareFaces) {
+          // x faces i+1/2 and i-1/2 of this cell: columns tx+1 and tx of its row
+          const int fxp = ty * (TX + 1) + tx + 1, fxm = fxp - 1;
+          const int fyp = (ty + 1) * TX + tx, fym = ty * TX + tx;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] = S.fx[v][fxp] - S.fx[v][fxm];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (S.fy[v][fyp] - S.fy[v][fym]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] = (Real)0;
+          // faces in the order x+, x-, y+, y-; each pair's difference joins the sum
 #pragma unroll 1
-          for (int side = 0; side < 2; ++side) {  // 0: face i+1/2, 1: face i-1/2
-            const int lo = side == 0 ? 0 : -1;      // left cell = i + lo
+          for (int f = 0; f < 4; ++f) {
+            const int axis = f >> 1, upper = (f & 1) == 0;
+            Real Fo[5];
+            tile_face(g, T, S, axis, (axis == 1 && upper) ? ty + 1 : ty,
+                      (axis == 0 && upper) ? tx + 1 : tx, dt, Fo);
+            if (upper) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v)
+              for (int v = 0; v < 5; ++v) Fp[v] = Fo[v];
+            } else {
 #pragma unroll
-              for (int q = 0; q < 4; ++q) u4[v][q] = S.u[v][eidx(tx + 2 + lo - 1 + q, ty + 2)];
-            const int hl = hidx(tx + 1 + lo, ty + 1), hr = hidx(tx + 2 + lo, ty + 1);
-            bl[0] = u4[0][1];
-            br[0] = u4[0][2];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              bl[1 + v] = S.b[v][hl];
-              br[1 + v] = S.b[v][hr];
+              for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fo[v]);
             }
-            face_flux(g, 0, u4, bl, br, S.xx[hl], S.xx[hr], dt, side == 0 ? Fp : Fm);
           }
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] = Fp[v] - Fm[v];
-        }
-        // y faces
-        {
-          Real u4[5][4], bl[5], br[5];
-#pragma unroll 1
-          for (int side = 0; side < 2; ++side) {
-            const int lo = side == 0 ? 0 : -1;
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-#pragma unroll
-              for (int q = 0; q < 4; ++q) u4[v][q] = S.u[v][eidx(tx + 2, ty + 2 + lo - 1 + q)];
-            const int hl = hidx(tx + 1, ty + 1 + lo), hr = hidx(tx + 1, ty + 2 + lo);
-            bl[0] = u4[0][1];
-            br[0] = u4[0][2];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              bl[1 + v] = S.b[v][hl];
-              br[1 + v] = S.b[v][hr];
-            }
-            face_flux(g, 1, u4, bl, br, S.xy[hl], S.xy[hr], dt, side == 0 ? Fp : Fm);
-          }
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fm[v]);
         }
         // z faces: k+1/2 new, k-1/2 carried from the previous plane
         face_flux(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
@@ -978,11 +1116,58 @@ __global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ct
     for (int v = 0; v < 5; ++v) {
       double s = red[v][0];
       for (int q = 1; q < NT / kWave; ++q) s += red[v][q];
-      partials[(long long)blockIdx.x * 5 + v] = s;
+      slot[v] = s;
     }
     if (m > 0.0) atomicMax(&ctrl->smax_bits[1 - ctrl->cur], (unsigned long long)__double_as_longlong(m));
     if (redb) atomicOr(&ctrl->status, redb);
   }
+}
+
+// ------------------------------------------------------------------ stage launches
+__global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g,
+                                                const Ctrl* __restrict__ ctrl, int tz) {
+  if (!ctrl->active) return;
+  Tile T;
+  int id;
+  if (!single_tile(g, tz, T, id)) return;
+  stage_p_body(F, g, ctrl, T);
+}
+
+__global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g,
+                                                   const Ctrl* __restrict__ ctrl, int tz) {
+  if (!ctrl->active) return;
+  Tile T;
+  int id;
+  if (!single_tile(g, tz, T, id)) return;
+  stage_c_body(F, g, ctrl, T);
+}
+
+__global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ctrl* ctrl,
+                                                   double* __restrict__ partials, int tz) {
+  if (!ctrl->active) return;
+  Tile T;
+  int id;
+  if (!single_tile(g, tz, T, id)) return;
+  stage_e_body(F, g, ctrl, T, partials + (long long)id * 5);
+}
+
+// batched sweeps: workgroup -> (instance, tile) through the tile prefix; the XCD
+// inversion runs over the whole flattened list
+template <int kStage>
+__global__ void __launch_bounds__(NT, 2) k_stage_batch(const Inst<Real>* __restrict__ tab,
+                                                       const int* __restrict__ prefix, int n) {
+  const int gid = xcd_tile(blockIdx.x, gridDim.x);
+  if (gid < 0) return;
+  const int q = find_inst(prefix, n, gid);
+  if (q < 0) return;
+  const Inst<Real>& I = tab[q];
+  if (!I.ctrl->active) return;
+  Tile T;
+  const int id = gid - prefix[q];
+  tile_at(I.g, I.tz, id, T);
+  if (kStage == 0) stage_p_body(I.F, I.g, I.ctrl, T);
+  else if (kStage == 1) stage_c_body(I.F, I.g, I.ctrl, T);
+  else stage_e_body(I.F, I.g, I.ctrl, T, I.partials + (long long)id * 5);
 }
 
 // fixed-order sum of the per-block totals
@@ -1012,9 +1197,12 @@ int pick_tz(const GridDev& g) {
   return tz;
 }
 
+int sweep_tiles(const GridDev& g, int tz) {
+  return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + tz - 1) / tz);
+}
+
 int sweep_blocks(const GridDev& g, int tz) {
-  const int n = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + tz - 1) / tz);
-  return (n + kXcd - 1) / kXcd * kXcd;
+  return (sweep_tiles(g, tz) + kXcd - 1) / kXcd * kXcd;
 }
 
 dim3 cell_grid(const GridDev& g) {
@@ -1028,7 +1216,40 @@ using namespace CSPH_TAG;
 
 template <>
 int Launch<Real>::stage_e_blocks(const GridDev& g) {
-  return sweep_blocks(g, pick_tz(g));
+  return sweep_tiles(g, pick_tz(g));
+}
+
+template <>
+int Launch<Real>::tiles(const GridDev& g, int tz) {
+  return sweep_tiles(g, tz);
+}
+
+template <>
+int Launch<Real>::default_tz(const GridDev& g) {
+  return pick_tz(g);
+}
+
+template <>
+long long Launch<Real>::ghosts(const GridDev& g) {
+  return ghost_count(g);
+}
+
+template <>
+hipError_t Launch<Real>::batch_step(const Inst<Real>* tab, const int* tile_prefix,
+                                    const long long* ghost_prefix, int n, int total_tiles,
+                                    long long total_ghosts, int* flags, hipStream_t s) {
+  const unsigned nb = (unsigned)((total_tiles + kXcd - 1) / kXcd * kXcd);
+  const unsigned gb = (unsigned)((total_ghosts + 255) / 256);
+  const unsigned ib = (unsigned)((n + 63) / 64);
+  k_begin_batch<<<ib, 64, 0, s>>>(tab, n);
+  k_fill_batch<0><<<gb, 256, 0, s>>>(tab, ghost_prefix, n);
+  k_stage_batch<0><<<nb, NT, 0, s>>>(tab, tile_prefix, n);
+  k_fill_batch<1><<<gb, 256, 0, s>>>(tab, ghost_prefix, n);
+  k_stage_batch<1><<<nb, NT, 0, s>>>(tab, tile_prefix, n);
+  k_fill_batch<2><<<gb, 256, 0, s>>>(tab, ghost_prefix, n);
+  k_stage_batch<2><<<nb, NT, 0, s>>>(tab, tile_prefix, n);
+  k_end_batch<<<ib, 64, 0, s>>>(tab, n, flags);
+  return hipGetLastError();
 }
 
 template <>
@@ -1060,11 +1281,10 @@ hipError_t Launch<Real>::signal_max(const Fields<Real>& F, const GridDev& g, Ctr
 
 template <>
 hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
-                              double* partials, double dt_max, double t_end, hipStream_t s,
+                              double* partials, double dt_max, double t_end, int tz, hipStream_t s,
                               hipEvent_t* ev) {
   const long long ng = ghost_count(g);
   const unsigned gb = (unsigned)((ng + 255) / 256);
-  const int tz = pick_tz(g);
   const unsigned nb = (unsigned)sweep_blocks(g, tz);
   auto mark = [&](int q) {
     if (ev) (void)hipEventRecord(ev[q], s);
@@ -1079,17 +1299,7 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   mark(3);
   k_stage_c<<<nb, NT, 0, s>>>(F, g, ctrl, tz);
   mark(4);
-  FillSet<Real> fs{};
-  for (int q = 0; q < 4; ++q) {
-    fs.f[q] = F.mt[q];
-    fs.role[q] = kMx + q;
-  }
-  for (int q = 0; q < 3; ++q) {
-    fs.f[4 + q] = F.xt[q];
-    fs.role[4 + q] = kXx + q;
-  }
-  fs.n = 7;
-  k_fill<<<gb, 256, 0, s>>>(fs, g, bc, ctrl, 1);
+  k_fill_corr<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(5);
   k_stage_e<<<nb, NT, 0, s>>>(F, g, ctrl, partials, tz);
   mark(6);

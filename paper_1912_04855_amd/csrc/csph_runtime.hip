@@ -172,6 +172,8 @@ struct csph_sim {
   double* totals_dev = nullptr;
   bool psi_dirty = true;
   bool need_smax = true;
+  int tz = 0;            // z-planes per workgroup of the stencil sweeps
+  bool in_batch = false;
   bool stepped = false;  // partials describe the current state
   std::vector<double> psi_host;  // interior psi, kept to refill ghosts after BC changes
   bool has_psi = false;
@@ -319,7 +321,8 @@ csph_status launch_steps(csph_sim* s, int n, double dt_max, double t_end) {
       ev = &s->prof_ev[(size_t)s->prof_pending * 8];
       s->prof_pending += 1;
     }
-    HIP_TRY(Launch<Real>::step(F, s->g, s->bc, s->ctrl, s->partials, dt_max, t_end, s->stream, ev));
+    HIP_TRY(Launch<Real>::step(F, s->g, s->bc, s->ctrl, s->partials, dt_max, t_end, s->tz, s->stream,
+                               ev));
   }
   s->stepped = true;
   return CSPH_OK;
@@ -338,6 +341,7 @@ bool periodic_pairs_ok(const csph_sim* s) {
 
 csph_status init_sim(csph_sim* s) {
   s->g = make_grid(&s->desc);
+  s->tz = s->is_f64() ? Launch<double>::default_tz(s->g) : Launch<float>::default_tz(s->g);
   for (int f = 0; f < 6; ++f) s->bc.kind[f] = kPeriodic;
   if (s->is_f64())
     bind_fields<double>(s, s->f64);
@@ -471,6 +475,8 @@ csph_status csph_set_state(csph_sim* s, csph_vars vars, const double* host) {
   if (st) return st;
   c.t = old.t;
   c.nsteps = old.nsteps;
+  c.step_limit = old.step_limit;
+  c.t_end = old.t_end;
   st = write_ctrl(s, c);
   if (st) return st;
   s->need_smax = true;
@@ -517,6 +523,7 @@ csph_status csph_set_boundary(csph_sim* s, int32_t face, csph_bc kind, const dou
 
 csph_status csph_step(csph_sim* s, double dt_max, double* dt_taken) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: advance the batch");
   if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
   Ctrl c{};
   // a step always runs (no end time): clear the completion flag of earlier advances
@@ -541,6 +548,7 @@ csph_status csph_step(csph_sim* s, double dt_max, double* dt_taken) {
 
 csph_status csph_advance(csph_sim* s, double t_end, int64_t max_steps, int64_t* steps_taken) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: advance the batch");
   if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
   if (max_steps < 0) return fail(CSPH_ERR_ARG, "max_steps must be >= 0");
   if (std::isnan(t_end)) return fail(CSPH_ERR_ARG, "t_end is NaN");
@@ -688,5 +696,270 @@ csph_status csph_profile_read(csph_sim* s, double* avg_ms, int64_t* launches, in
 }
 
 // batches are implemented in csph_batch.hip
+
+}  // extern "C"
+
+// ====================================================================== batches
+namespace {
+
+struct Member {
+  csph_sim* sim = nullptr;
+  bool used = false;
+};
+
+}  // namespace
+
+struct csph_batch {
+  int dtype = CSPH_F32;
+  hipStream_t stream = nullptr;
+  size_t budget = 0, used_bytes = 0;
+  std::vector<Member> slots;
+  // device table of the members in slot order (built on change)
+  void* table = nullptr;
+  int* tile_prefix = nullptr;
+  long long* ghost_prefix = nullptr;
+  int* flags = nullptr;
+  size_t cap = 0;
+  std::vector<int> order;  // table row -> slot
+  int total_tiles = 0;
+  long long total_ghosts = 0;
+  bool dirty = true;
+  // a captured k-step graph, replayed while membership does not change
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_k = 0;
+  bool own_stream = false;
+};
+
+namespace {
+
+void drop_graph(csph_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_k = 0;
+}
+
+template <typename Real>
+csph_status build_table(csph_batch* b) {
+  b->order.clear();
+  for (size_t q = 0; q < b->slots.size(); ++q)
+    if (b->slots[q].used) b->order.push_back((int)q);
+  const size_t n = b->order.size();
+  if (n > b->cap) {
+    if (b->table) (void)hipFree(b->table);
+    if (b->tile_prefix) (void)hipFree(b->tile_prefix);
+    if (b->ghost_prefix) (void)hipFree(b->ghost_prefix);
+    if (b->flags) (void)hipFree(b->flags);
+    b->table = nullptr;
+    b->tile_prefix = nullptr;
+    b->ghost_prefix = nullptr;
+    b->flags = nullptr;
+    size_t cap = std::max<size_t>(64, 2 * n);
+    if (hipMalloc(&b->table, cap * sizeof(Inst<Real>)) != hipSuccess ||
+        hipMalloc((void**)&b->tile_prefix, (cap + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&b->ghost_prefix, (cap + 1) * sizeof(long long)) != hipSuccess ||
+        hipMalloc((void**)&b->flags, cap * sizeof(int)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CSPH_ERR_NOMEM, "batch table allocation failed");
+    }
+    b->cap = cap;
+  }
+  std::vector<Inst<Real>> tab(n);
+  std::vector<int> tp(n + 1, 0);
+  std::vector<long long> gp(n + 1, 0);
+  for (size_t r = 0; r < n; ++r) {
+    csph_sim* s = b->slots[b->order[r]].sim;
+    Inst<Real>& I = tab[r];
+    I.F = fields_of<Real>(s);
+    I.g = s->g;
+    I.bc = s->bc;
+    I.ctrl = s->ctrl;
+    I.partials = s->partials;
+    I.tz = s->tz;
+    tp[r + 1] = tp[r] + Launch<Real>::tiles(s->g, s->tz);
+    gp[r + 1] = gp[r] + Launch<Real>::ghosts(s->g);
+  }
+  b->total_tiles = tp[n];
+  b->total_ghosts = gp[n];
+  if (n) {
+    HIP_TRY(hipMemcpyAsync(b->table, tab.data(), n * sizeof(Inst<Real>), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->tile_prefix, tp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->ghost_prefix, gp.data(), (n + 1) * sizeof(long long), hipMemcpyHostToDevice,
+                           b->stream));
+    const std::vector<int> zero(n, 0);
+    HIP_TRY(hipMemcpyAsync(b->flags, zero.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+  }
+  drop_graph(b);
+  b->dirty = false;
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status batch_launch(csph_batch* b, int k) {
+  const int n = (int)b->order.size();
+  if (n == 0 || k <= 0) return CSPH_OK;
+  if (!b->exec || b->graph_k != k) {
+    drop_graph(b);
+    // capture k steps of every member; replays reuse the same table
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < k && e == hipSuccess; ++q)
+      e = Launch<Real>::batch_step((const Inst<Real>*)b->table, b->tile_prefix, b->ghost_prefix, n,
+                                   b->total_tiles, b->total_ghosts, b->flags, b->stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return fail(CSPH_ERR_DEVICE, std::string("graph capture failed: ") +
+                                       hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = gr;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_k = k;
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  return CSPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+csph_status csph_batch_create(csph_dtype dtype, void* hip_stream, size_t hbm_budget, csph_batch** out) {
+  if (!out) return fail(CSPH_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (dtype != CSPH_F32 && dtype != CSPH_F64) return fail(CSPH_ERR_ARG, "bad dtype");
+  csph_batch* b = new (std::nothrow) csph_batch();
+  if (!b) return fail(CSPH_ERR_NOMEM, "host allocation failed");
+  b->dtype = dtype;
+  b->stream = (hipStream_t)hip_stream;
+  if (!b->stream) {
+    // a graph cannot be captured on the null stream: use a stream of our own
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return fail(CSPH_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    b->own_stream = true;
+  }
+  b->budget = hbm_budget;
+  *out = b;
+  return CSPH_OK;
+}
+
+csph_status csph_batch_add(csph_batch* b, csph_sim* s, int64_t steps, double t_end, int32_t* slot) {
+  if (!b || !s) return fail(CSPH_ERR_ARG, "batch or sim is NULL");
+  if (s->desc.dtype != b->dtype) return fail(CSPH_ERR_ARG, "sim dtype differs from the batch dtype");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim already belongs to a batch");
+  if (steps < 0 || std::isnan(t_end)) return fail(CSPH_ERR_ARG, "bad steps or t_end");
+  if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
+  const size_t need = s->L.total;
+  if (b->budget && b->used_bytes + need > b->budget) return fail(CSPH_ERR_BUDGET, "HBM budget exceeded");
+  Ctrl c{};
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  if (c.status) return fail(CSPH_ERR_STATE, "sticky error: call csph_set_state");
+  // ghosts of psi and the first dt of the member, on the member's own stream
+  st = s->is_f64() ? prepare<double>(s) : prepare<float>(s);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  st = read_ctrl(s, &c);
+  if (st) return st;
+  c.done = 0;
+  c.step_limit = c.nsteps + steps;
+  c.t_end = t_end;
+  st = write_ctrl(s, c);
+  if (st) return st;
+  int q = -1;
+  for (size_t k = 0; k < b->slots.size(); ++k)
+    if (!b->slots[k].used) {
+      q = (int)k;
+      break;
+    }
+  if (q < 0) {
+    b->slots.push_back(Member{});
+    q = (int)b->slots.size() - 1;
+  }
+  b->slots[q].sim = s;
+  b->slots[q].used = true;
+  s->in_batch = true;
+  s->stepped = true;
+  b->used_bytes += need;
+  b->dirty = true;
+  if (slot) *slot = q;
+  return CSPH_OK;
+}
+
+csph_status csph_batch_advance(csph_batch* b, int32_t k_steps, int32_t* n_done) {
+  if (!b) return fail(CSPH_ERR_ARG, "batch is NULL");
+  if (k_steps < 0) return fail(CSPH_ERR_ARG, "k_steps must be >= 0");
+  csph_status st;
+  if (b->dirty) {
+    st = b->dtype == CSPH_F64 ? build_table<double>(b) : build_table<float>(b);
+    if (st) return st;
+  }
+  st = b->dtype == CSPH_F64 ? batch_launch<double>(b, k_steps) : batch_launch<float>(b, k_steps);
+  if (st) return st;
+  if (n_done) {
+    int32_t cnt = 0, n = 0;
+    st = csph_batch_poll(b, nullptr, 0, &n);
+    if (st) return st;
+    cnt = n;
+    *n_done = cnt;
+  }
+  return CSPH_OK;
+}
+
+csph_status csph_batch_poll(csph_batch* b, int32_t* done_slots, int32_t cap, int32_t* n) {
+  if (!b || !n) return fail(CSPH_ERR_ARG, "batch or n is NULL");
+  *n = 0;
+  if (b->dirty) {
+    csph_status st = b->dtype == CSPH_F64 ? build_table<double>(b) : build_table<float>(b);
+    if (st) return st;
+  }
+  const size_t m = b->order.size();
+  if (m == 0) return CSPH_OK;
+  // every step's last launch writes each member's done / error flag
+  std::vector<int> fl(m, 0);
+  HIP_TRY(hipMemcpyAsync(fl.data(), b->flags, m * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int32_t k = 0;
+  for (size_t r = 0; r < m; ++r)
+    if (fl[r]) {
+      if (done_slots && k < cap) done_slots[k] = b->order[r];
+      ++k;
+    }
+  *n = k;
+  return CSPH_OK;
+}
+
+csph_status csph_batch_remove(csph_batch* b, int32_t slot) {
+  if (!b || slot < 0 || slot >= (int32_t)b->slots.size() || !b->slots[slot].used)
+    return fail(CSPH_ERR_ARG, "no such slot");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  csph_sim* s = b->slots[slot].sim;
+  s->in_batch = false;
+  b->used_bytes -= s->L.total;
+  b->slots[slot] = Member{};
+  b->dirty = true;
+  return CSPH_OK;
+}
+
+csph_status csph_batch_destroy(csph_batch* b) {
+  if (!b) return CSPH_OK;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& m : b->slots)
+    if (m.used) m.sim->in_batch = false;
+  drop_graph(b);
+  if (b->table) (void)hipFree(b->table);
+  if (b->tile_prefix) (void)hipFree(b->tile_prefix);
+  if (b->ghost_prefix) (void)hipFree(b->ghost_prefix);
+  if (b->flags) (void)hipFree(b->flags);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return CSPH_OK;
+}
 
 }  // extern "C"

@@ -195,3 +195,61 @@ def from_problem(prob, dtype="f64", torch=False, stream=None) -> Sim:
     s.set_potential(prob.psi)
     s.set_primitive(prob.prim)
     return s
+
+
+class Batch:
+    """Simulations of one dtype advanced together: one launch per stage for all
+    members, k steps captured in a HIP graph and replayed.  Members keep their own
+    dt, t and step target; the batch references sims, it does not own them."""
+
+    def __init__(self, dtype="f32", budget_bytes=0, stream=None):
+        self.dtype = _dtype_code(dtype)
+        self._h = C.c_void_p()
+        check(_lib.load().csph_batch_create(self.dtype, C.c_void_p(stream or 0),
+                                            int(budget_bytes), C.byref(self._h)),
+              "csph_batch_create")
+        self.members = {}
+
+    def add(self, sim: Sim, steps: int, t_end=math.inf) -> int:
+        slot = C.c_int32()
+        check(_lib.load().csph_batch_add(self._h, sim.handle, int(steps), float(t_end),
+                                         C.byref(slot)), "csph_batch_add")
+        self.members[slot.value] = sim
+        return slot.value
+
+    def try_add(self, sim: Sim, steps: int, t_end=math.inf):
+        """add(), or None when the device-memory budget is exhausted."""
+        try:
+            return self.add(sim, steps, t_end)
+        except _lib.CsphError as e:
+            if e.code == _lib.ERR_BUDGET:
+                return None
+            raise
+
+    def advance(self, k: int, sync=False) -> int:
+        n = C.c_int32()
+        check(_lib.load().csph_batch_advance(self._h, int(k), C.byref(n) if sync else None),
+              "csph_batch_advance")
+        return n.value
+
+    def poll(self):
+        cap = max(1, len(self.members))
+        out = np.zeros(cap, dtype=np.int32)
+        n = C.c_int32()
+        check(_lib.load().csph_batch_poll(self._h, _ptr(out), cap, C.byref(n)), "csph_batch_poll")
+        return [int(v) for v in out[:min(n.value, cap)]]
+
+    def remove(self, slot: int) -> Sim:
+        check(_lib.load().csph_batch_remove(self._h, int(slot)), "csph_batch_remove")
+        return self.members.pop(slot)
+
+    def close(self):
+        if self._h:
+            _lib.load().csph_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
