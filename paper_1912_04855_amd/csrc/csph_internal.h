@@ -39,6 +39,8 @@ struct GridDev {
   double kappa_h2;       // kernel normalisation / h^2
   // 13 lattice kernel gradients K(-h o), o in the half neighbour set
   double klat[13][3];
+  // -h o for the same 13 offsets (the lattice part of a pair separation)
+  double hoff[13][3];
 };
 
 struct BcDev {

@@ -175,8 +175,8 @@ __device__ __forceinline__ void kgrad(const GridDev& g, Real dx, Real dy, Real d
   } else {
     const Real rs = rsqrt_(r2);                  // 1/|d|
     const Real q = r2 * rs * (Real)g.inv_h;      // |d|/h
-    const Real t = (Real)2 - q;
-    const Real far = (Real)0.75 * t * t * (rs * (Real)g.h);
+    // (3/4)(2-q)^2/q = 3/q - 3 + (3/4) q
+    const Real far = (Real)3 * (rs * (Real)g.h) - (Real)3 + (Real)0.75 * q;
     gq = q < (Real)1 ? (Real)3 - (Real)2.25 * q : (q < (Real)2 ? far : (Real)0);
   }
   const Real c = (Real)g.kappa_h2 * gq;
@@ -605,12 +605,12 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
           }
           be = be + (te[0] + te[1]);
         } else {
-          // pair difference in FP64: phi_c (phi_+ - phi_-) + rho_c (psi_+ - psi_-),
-          // exact for FP32 inputs up to one rounding, then times the lattice K
-          const Acc dphi = (Acc)phi_[np] - (Acc)phi_[nm];
-          const Acc dpsi = (Acc)psi_[np] - (Acc)psi_[nm];
-          const Real s = (Real)((Acc)fc * dphi + (Acc)rc * dpsi);
-          const Real ds = (Real)dpsi;
+          // pair difference phi_c (phi_+ - phi_-) + rho_c (psi_+ - psi_-): the FP32
+          // differences are exact for neighbours within a factor 2, the combination
+          // is formed in FP64, then times the lattice K
+          const Real dphi = phi_[np] - phi_[nm];
+          const Real ds = psi_[np] - psi_[nm];
+          const Real s = (Real)((Acc)fc * (Acc)dphi + (Acc)rc * (Acc)ds);
           if (ox != 0) {
             af[0] += s * Kx;
             gf[0] += ds * Kx;
@@ -693,7 +693,6 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
   const Real* __restrict__ MSZ = F.ms[2];
   const Real* __restrict__ ES = F.ms[3];
   const double dt = ctrl->dt;
-  const Real h = (Real)g.h;
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int i = T.x0 + tx, j = T.y0 + ty;
   const bool in = i < g.nx && j < g.ny;
@@ -741,26 +740,37 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       const Real xc[3] = {S.xx[s0][c0], S.xy[s0][c0], S.xz[s0][c0]};
       Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
       Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0;
+      const int tb = hidx(tx + 1, ty + 1);
 #pragma unroll 1
       for (int q = 0; q < 13; ++q) {
         const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
-        Real K[2][3], ub[2];
-        Acc sp[2], dpsi[2], ff[2];
+        // LDS index of the two partners: this thread's cell + a uniform offset
+        const int np = tb + ring3(k + oz) * HP + oy * HX + ox;
+        const int nm = tb + ring3(k - oz) * HP - oy * HX - ox;
+        const Real hx = (Real)g.hoff[q][0], hy = (Real)g.hoff[q][1], hz = (Real)g.hoff[q][2];
+        Real K[2][3], ub[2], fn[2], pn[2];
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-          const int sg = side == 0 ? 1 : -1;
-          const int n = nb(sg * ox, sg * oy, sg * oz);
-          const Real dx = (Real)(-sg * ox) * h + (xc[0] - xx_[n]);
-          const Real dy = (Real)(-sg * oy) * h + (xc[1] - xy_[n]);
-          const Real dz = (Real)(-sg * oz) * h + (xc[2] - xz_[n]);
+          const int n = side == 0 ? np : nm;
+          // separation r_c - r_n = -h o + (xi_c - xi_n) (o -> -o on the minus side)
+          const Real dx = side == 0 ? hx + (xc[0] - xx_[n]) : (xc[0] - xx_[n]) - hx;
+          const Real dy = side == 0 ? hy + (xc[1] - xy_[n]) : (xc[1] - xy_[n]) - hy;
+          const Real dz = side == 0 ? hz + (xc[2] - xz_[n]) : (xc[2] - xz_[n]) - hz;
           kgrad(g, dx, dy, dz, K[side][0], K[side][1], K[side][2]);
-          ff[side] = (Acc)fc * (Acc)phi_[n];
-          dpsi[side] = (Acc)psi_[n] - (Acc)psc;
-          sp[side] = ff[side] + (Acc)rc * dpsi[side];
-          ub[side] = (Real)0.5 * ((uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
-                                  (uc[2] + uz_[n]) * K[side][2]);
+          fn[side] = phi_[n];
+          pn[side] = psi_[n];
+          ub[side] = (uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
+                     (uc[2] + uz_[n]) * K[side][2];
+          if constexpr (kF64) ub[side] = 0.5 * ub[side];
         }
         if constexpr (kF64) {
+          Acc sp[2], dpsi[2], ff[2];
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            ff[side] = fc * fn[side];
+            dpsi[side] = pn[side] - psc;
+            sp[side] = ff[side] + rc * dpsi[side];
+          }
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
             a[d] = a[d] + (sp[0] * K[0][d] + sp[1] * K[1][d]);
@@ -768,22 +778,25 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
           }
           be = be + (ff[0] * ub[0] + ff[1] * ub[1]);
         } else {
-          // split the pair into its odd and even parts: the large sum of the two
-          // pressure terms meets only K+ + K- (zero on the lattice); the
-          // well-balance cancellation sp+ - sp- is taken in FP64
-          const Real dsp = (Real)(sp[0] - sp[1]);
-          const Real ssp = (Real)(sp[0] + sp[1]);
-          const Real d0 = (Real)dpsi[0], d1 = (Real)dpsi[1];
+          // sp+ K+ + sp- K- = (sp+ - sp-) K+ + sp- (K+ + K-).  The difference
+          // sp+ - sp- = phi_c (phi+ - phi-) + rho_c (psi+ - psi-) carries the
+          // well-balance cancellation: its two FP32 differences are exact for
+          // neighbours within a factor 2, and their combination is formed in FP64.
+          // K+ + K- vanishes on the lattice, so the large sp- meets only a small
+          // factor.
+          const Real dphi = fn[0] - fn[1], dps = pn[0] - pn[1];
+          const Real dsp = (Real)((Acc)fc * (Acc)dphi + (Acc)rc * (Acc)dps);
+          const Real d0 = pn[0] - psc, d1 = pn[1] - psc;
+          const Real spm = fc * fn[1] + rc * d1;
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const Real kd = (Real)0.5 * (K[0][d] - K[1][d]);
-            const Real ks = (Real)0.5 * (K[0][d] + K[1][d]);
-            af[d] += dsp * kd + ssp * ks;
+            af[d] += dsp * K[0][d] + spm * (K[0][d] + K[1][d]);
             gf[d] += d0 * K[0][d] + d1 * K[1][d];
           }
-          bf += (Real)ff[0] * ub[0] + (Real)ff[1] * ub[1];
+          bf += fn[0] * ub[0] + fn[1] * ub[1];
         }
       }
+      if constexpr (!kF64) bf *= (Real)0.5 * fc;
       const long long c = cell(g, i, j, k);
       const Real m0[3] = {F.U[par][1][c], F.U[par][2][c], F.U[par][3][c]};
       const Real E0 = F.U[par][4][c];

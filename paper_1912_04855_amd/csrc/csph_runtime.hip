@@ -134,6 +134,9 @@ GridDev make_grid(const csph_grid_desc* d) {
     g.klat[q][0] = -(c * dx);
     g.klat[q][1] = -(c * dy);
     g.klat[q][2] = -(c * dz);
+    g.hoff[q][0] = dx;
+    g.hoff[q][1] = dy;
+    g.hoff[q][2] = dz;
   }
   return g;
 }
