@@ -7,9 +7,11 @@ dt) of every interior cell; the metric is cell-updates/s = cells * steps / time,
 with the state resident in HBM before the timed region starts.
 
 Prints one JSON line.  Besides the headline it carries:
-  roofline     -- the dominant kernel's algorithmic bytes per launch over its
-                  average launch time (HIP events recorded by the library
-                  around each kernel during the timed steps), against 8 TB/s;
+  roofline     -- the dominant kernel against the vector-ALU peak that bounds
+                  it: algorithmic flops per launch over its average launch time
+                  (HIP events recorded by the library around each kernel during
+                  the timed steps), with its HBM figures (algorithmic bytes over
+                  the same time against 8 TB/s; counted traffic from rocprofv3);
   cpu_baseline -- the FP64 CPU oracle timed on this host (rank 0 only) on a
                   bounded sample of the same workload;
   fp64         -- the same workload with FP64 state, timed the same way.
@@ -25,6 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # bytes/s, MI355X
+# Vector ALU peaks of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x
+# 2.4 GHz = 78.6 TFLOP/s for non-packed FP32 and for FP64; packed FP32 doubles
+# the FP32 figure to the published 157.3 TFLOP/s.  The kernels are built with
+# packed FP32 switched off, so 78.6 is the rate they can reach; the published
+# figure is reported as the peak.
+ALU_PEAK = {"f32": 157.3e12, "f64": 78.6e12}
+ALU_PEAK_NONPACKED = 78.6e12
+VALU_ISSUE = 256 * 4 * 16 * 2.4e9   # lane-instructions/s (one wave64 op per SIMD per 4 clocks)
 
 # Algorithmic bytes per interior cell of each stage kernel, in words (4 B in
 # FP32, 8 B in FP64): every input read once, every output written once.
@@ -32,6 +42,20 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X
 #   stage C: read rho, m*, E* (5) + xi* (3) + psi (1) + m^n, E^n (4); write m~, E~ (4) + xi (3)
 #   stage E: read U^n (5) + m~, E~ (4) + xi (3); write U^{n+1} (5)
 WORDS = {"stage_p": 13, "stage_c": 20, "stage_e": 17}
+# Algorithmic floating-point operations per interior cell of each stage (each
+# +, -, *, /, sqrt, min, max counted once; a fused multiply-add is two), as the
+# method defines them, not as the kernels happen to issue them:
+#   stage P: primitives (14) + the 13 lattice pair terms of A (119), D[psi] (54)
+#            and B (212) + rho u.D[psi] (7) + the predictor update (20) + psi at
+#            r* (27)                                                      = 453
+#   stage C: per neighbour (26): separation (5), |d| and q (7), g(q)/q (4), K (4),
+#            pressure-potential term (4), A (6), D[psi] (6), (u_i+u_j).K/2 (9),
+#            B (2) = 47.1; plus primitives, corrector update and xi (51)  = 1275
+#   stage E: three faces per cell (a face is shared by two cells) x 148 (slopes
+#            and minmod 45, reconstruction and swept flux 41, acoustic damping
+#            62) + the update (35) + the next step's signal speed (21) and the
+#            totals (5)                                                    = 505
+FLOPS = {"stage_p": 453, "stage_c": 1275, "stage_e": 505}
 KERNEL_NAMES = {"stage_p": "k_stage_p", "stage_c": "k_stage_c", "stage_e": "k_stage_e"}
 
 
@@ -39,12 +63,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(prob, dtype, steps, warmup):
+def run_gpu(prob, dtype, steps, warmup, autotune=True, tile_depth=0):
     import torch
     from paper_1912_04855_amd.sim import from_problem
 
     sim = from_problem(prob, dtype=dtype, torch=True)
     stream = torch.cuda.current_stream()
+    if tile_depth:
+        sim.tile_depth = tile_depth
+    elif autotune:
+        sim.autotune(trial_steps=3)
+    tz = sim.tile_depth
     if warmup:
         sim.advance(math.inf, warmup)
     torch.cuda.synchronize()
@@ -63,30 +92,118 @@ def run_gpu(prob, dtype, steps, warmup):
     assert n == steps, (n, steps)
     t, nsteps = sim.time()
     sim.close()
-    return {"wall_s": wall, "event_ms": gpu_ms, "profile": prof, "t": t}
+    return {"wall_s": wall, "event_ms": gpu_ms, "profile": prof, "t": t, "tile_depth": tz}
+
+
+def _counters(kernel, dtype, cells):
+    """rocprofv3 counter summary of this kernel build and workload, if one was
+    taken of the current kernel source (else None)."""
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tf):
+        return None
+    try:
+        rec = json.load(open(tf)).get(f"{kernel}:{dtype}:{cells}")
+    except Exception:
+        return None
+    if rec and rec.get("source_hash") == source_hash():
+        return rec
+    return None
 
 
 def roofline(prof, cells, dtype):
     word = 8 if dtype == "f64" else 4
     dom = max(WORDS, key=lambda k: prof[k][0])
-    ms = prof[dom][0]
+    sec = prof[dom][0] * 1e-3
     bytes_per_launch = WORDS[dom] * word * cells
-    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    flops_per_launch = FLOPS[dom] * cells
+    gbps = bytes_per_launch / sec / 1e9
+    tflops = flops_per_launch / sec / 1e12
+    rec = _counters(KERNEL_NAMES[dom], dtype, cells)
     per = {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1],
-               "GBps": round(WORDS[k] * word * cells / (prof[k][0] * 1e-3) / 1e9, 1)}
+               "GBps": round(WORDS[k] * word * cells / (prof[k][0] * 1e-3) / 1e9, 1),
+               "TFLOPs": round(FLOPS[k] * cells / (prof[k][0] * 1e-3) / 1e12, 2)}
            for k in WORDS}
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf):
-        try:
-            rec = json.load(open(tf)).get(f"{KERNEL_NAMES[dom]}:{dtype}:{cells}")
-            if rec and rec.get("source_hash") == source_hash():
-                traffic = rec["bytes_per_launch"]
-        except Exception:
-            traffic = None
-    return {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
-            "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved * 1e9 / HBM_PEAK, 4),
-            "traffic": traffic, "bytes_per_launch": bytes_per_launch, "kernels": per}
+    out = {"bound": "alu", "kernel": KERNEL_NAMES[dom], "achieved": round(tflops, 2),
+           "peak": ALU_PEAK[dtype] / 1e12, "unit": "TFLOP/s",
+           "frac": round(tflops * 1e12 / ALU_PEAK[dtype], 4),
+           "traffic": rec["bytes_per_launch"] if rec else None,
+           "flops_per_launch": flops_per_launch,
+           "peak_nonpacked": ALU_PEAK_NONPACKED / 1e12,
+           "frac_nonpacked": round(tflops * 1e12 / ALU_PEAK_NONPACKED, 4),
+           "hbm": {"achieved": round(gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                   "frac": round(gbps * 1e9 / HBM_PEAK, 4), "bytes_per_launch": bytes_per_launch,
+                   "traffic": rec["bytes_per_launch"] if rec else None},
+           "kernels": per}
+    if rec and rec.get("valu_per_cell"):
+        # VALU issue utilisation from the counted instructions per cell
+        out["valu_issue_frac"] = round(rec["valu_per_cell"] * cells / sec / VALU_ISSUE, 3)
+    return out
+
+
+def run_batch(count=512, steps=100, seed=0, chunk=10):
+    """The batched workload: `count` independent simulations of uneven sizes
+    (edges in {32, 48, 64, 96} per axis, a Sod tube or a Sedov blast each), FP32,
+    advanced together `steps` steps each; one launch per stage for the whole
+    batch, `chunk` steps per captured HIP graph."""
+    import torch
+    from paper_1912_04855_amd import problems as P
+    from paper_1912_04855_amd.sim import Batch, from_problem
+
+    t0 = time.perf_counter()
+    sims, cells = [], 0
+    b = Batch("f32")
+    for k in range(count):
+        pr = P.batch_instance(seed, k, steps=steps)
+        s = from_problem(pr, dtype="f32")
+        sims.append(s)
+        cells += pr.cells
+        b.add(s, steps)
+    setup = time.perf_counter() - t0
+    tz, _ = b.autotune(trial_steps=3)
+    # the batch runs on a stream of its own: the timed region is bracketed by
+    # device synchronisations and measured on the host clock
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range((steps + chunk - 1) // chunk):
+        b.advance(chunk, sync=False)
+    done = len(b.poll())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    assert done == count, (done, count)
+    for s in sims:
+        t, n = s.time()
+        assert n == steps, n
+    b.close()
+    for s in sims:
+        s.close()
+    return {"value": round(cells * steps / wall, 1), "unit": "cell-updates/s", "instances": count,
+            "cells": cells, "steps_each": steps, "ms_per_step": round(wall * 1e3 / steps, 4),
+            "tile": f"32x8x{tz}", "setup_s": round(setup, 2), "dtype": "f32",
+            "workload": f"{count} instances, edges uniform in {{32,48,64,96}} per axis, "
+                        "Sod tube or Sedov blast by seed"}
+
+
+def run_serve(count=40, rate=None, seed=0, budget=64 << 30):
+    """A Poisson stream of solve requests through the continuous-batching loop:
+    cube edge in {64, ..., 256}, kind in {Sod, Sedov, well, cloud}, FP32 or FP64,
+    50-500 steps.  The arrival rate defaults to about 0.7 x the loop's throughput
+    measured on a short saturated burst first."""
+    from paper_1912_04855_amd import problems as P
+    from paper_1912_04855_amd import serve as S
+
+    if rate is None:
+        burst = P.serve_requests(count=8, rate=1e6, seed=seed + 1)
+        st = S.serve(burst, budget_bytes=budget)
+        rate = 0.7 * len(burst) / st.wall_s
+    reqs = P.serve_requests(count=count, rate=rate, seed=seed)
+    st = S.serve(reqs, budget_bytes=budget)
+    out = st.summary()
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+    out["arrival_rate_per_s"] = round(rate, 3)
+    out["budget_bytes"] = budget
+    out["workload"] = ("Poisson arrivals; cube edge in {64..256}, kind in {sod, sedov, well, "
+                       "cloud}, dtype f32 or f64, 50-500 steps; latency = arrival to result on host")
+    return out
 
 
 def source_hash():
@@ -130,6 +247,14 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in tile depth instead of autotuning it first")
+    ap.add_argument("--tile-depth", type=int, default=0,
+                    help="use this tile depth (z-planes per workgroup) instead of autotuning")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-count", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for the HBM "
                          "byte counters) and exit")
@@ -157,7 +282,8 @@ def main():
     cells = pr.cells
     log(f"[bench] potential-well flow {args.n}^3 {args.dtype}: warmup {args.warmup}, "
         f"{args.steps} timed steps")
-    r = run_gpu(pr, args.dtype, args.steps, args.warmup)
+    r = run_gpu(pr, args.dtype, args.steps, args.warmup, autotune=not args.no_autotune,
+                tile_depth=args.tile_depth)
     ms_step = r["event_ms"] / args.steps
     value = cells * args.steps / (r["event_ms"] * 1e-3)
     log(f"[bench] {ms_step:.3f} ms/step, {value:.3e} cell-updates/s "
@@ -170,17 +296,33 @@ def main():
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": f"potential-well flow {args.n}^3 (Mach-2 inflow, "
                                f"psi=-exp(-r^2/0.01), gamma=5/3)",
-                   "cells": cells, "dtype": args.dtype, "parallelism": "single GPU"},
+                   "cells": cells, "dtype": args.dtype, "parallelism": "single GPU",
+                   "tile": f"32x8x{r['tile_depth']}"},
         "roofline": rl,
         "algorithmic_hbm_frac": round(value * (44 if args.dtype == "f32" else 88) / HBM_PEAK, 4),
     }
     if not args.no_fp64 and args.dtype == "f32":
         k64 = max(10, args.steps // 2)
         log(f"[bench] FP64 companion: {k64} steps")
-        r64 = run_gpu(pr, "f64", k64, args.warmup)
+        r64 = run_gpu(pr, "f64", k64, args.warmup, autotune=not args.no_autotune)
         v64 = cells * k64 / (r64["event_ms"] * 1e-3)
         out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(r64["event_ms"] / k64, 4),
-                       "steps": k64, "roofline": roofline(r64["profile"], cells, "f64")}
+                       "steps": k64, "tile": f"32x8x{r64['tile_depth']}",
+                       "roofline": roofline(r64["profile"], cells, "f64")}
+    if not args.no_batch:
+        log(f"[bench] batched workload: {args.batch_count} instances")
+        try:
+            out["batched"] = run_batch(count=args.batch_count)
+            log(f"[bench] batched: {out['batched']['value']:.3e} cell-updates/s")
+        except Exception as e:  # the headline stands without it
+            out["batched"] = {"error": repr(e)}
+    if not args.no_serve:
+        log(f"[bench] serving workload: {args.serve_count} requests")
+        try:
+            out["serving"] = run_serve(count=args.serve_count)
+            log(f"[bench] serving: p50 {out['serving']['p50_s']} s, p99 {out['serving']['p99_s']} s")
+        except Exception as e:
+            out["serving"] = {"error": repr(e)}
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

@@ -149,6 +149,23 @@ const char* csph_last_error(void);
 csph_status csph_profile_enable(csph_sim* sim, int32_t on);
 csph_status csph_profile_read(csph_sim* sim, double* avg_ms, int64_t* launches, int32_t n);
 
+/* Tile depth: the stencil sweeps give each workgroup a 32 x 8 tile of an x-y
+ * plane and march it through tz planes along z.  Deeper tiles reuse more of the
+ * halo they stage; shallower ones give more workgroups.  Valid depths are
+ * 2..64; a new simulation starts from a built-in rule, or from the depth
+ * csph_autotune chose earlier in this process for the same device, dtype and
+ * grid shape.  Not allowed on a batch member. */
+csph_status csph_set_tile_depth(csph_sim* sim, int32_t tz);
+csph_status csph_get_tile_depth(const csph_sim* sim, int32_t* tz);
+
+/* Autotuner: time trial_steps steps (1..1000) at each candidate depth (2, 4,
+ * 8, ... up to the grid's nz) on a library-owned copy of the simulation (its
+ * state, potential, boundaries and time; csph_required_bytes of extra device
+ * memory while it runs), keep the fastest on `sim` and remember it for the
+ * shape.  The simulation itself is not advanced.  tz_out and ms_per_step
+ * (the winner's step time) may be NULL.  Synchronises. */
+csph_status csph_autotune(csph_sim* sim, int32_t trial_steps, int32_t* tz_out, double* ms_per_step);
+
 /* ---------------- batches: many simulations advanced together ---------------
  * A batch references simulations of one dtype; it does not own them, and each
  * must outlive its membership.  Every member keeps its own dt, t and step
@@ -169,6 +186,12 @@ csph_status csph_batch_advance(csph_batch* b, int32_t k_steps, int32_t* n_done);
 csph_status csph_batch_poll(csph_batch* b, int32_t* done_slots, int32_t cap, int32_t* n);
 /* Remove a member (finished or not); its slot is reused by later adds. */
 csph_status csph_batch_remove(csph_batch* b, int32_t slot);
+/* Autotuner for the batched launch: time trial_steps steps of the whole batch
+ * with every member at each candidate tile depth, keep the fastest depth on all
+ * members, and restore every member's state and time afterwards (a snapshot of
+ * each member is held in extra device memory while it runs).  Synchronises. */
+csph_status csph_batch_autotune(csph_batch* b, int32_t trial_steps, int32_t* tz_out,
+                                double* ms_per_step);
 csph_status csph_batch_destroy(csph_batch* b);
 
 #ifdef __cplusplus

@@ -7,7 +7,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcsph.so")
+# CSPH_LIB may name another build of the same library (to compare builds)
+LIB_PATH = os.environ.get("CSPH_LIB") or os.path.join(HERE, "libcsph.so")
 
 OK, ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_NONFINITE, ERR_NEG_DENSITY, ERR_NO_SIGNAL, \
     ERR_BUDGET = range(9)
@@ -26,7 +27,8 @@ EXPORTS = [
     "csph_get_state", "csph_get_time", "csph_set_time", "csph_totals", "csph_get_stage",
     "csph_last_error", "csph_batch_create", "csph_batch_add", "csph_batch_advance",
     "csph_batch_poll", "csph_batch_remove", "csph_batch_destroy", "csph_profile_enable",
-    "csph_profile_read",
+    "csph_profile_read", "csph_set_tile_depth", "csph_get_tile_depth", "csph_autotune",
+    "csph_batch_autotune",
 ]
 
 
@@ -80,6 +82,10 @@ def load():
         "csph_batch_destroy": (st, [vp]),
         "csph_profile_enable": (st, [vp, C.c_int32]),
         "csph_profile_read": (st, [vp, vp, vp, C.c_int32]),
+        "csph_set_tile_depth": (st, [vp, C.c_int32]),
+        "csph_get_tile_depth": (st, [vp, C.POINTER(C.c_int32)]),
+        "csph_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
+        "csph_batch_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

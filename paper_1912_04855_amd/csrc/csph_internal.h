@@ -121,7 +121,6 @@ struct Launch {
   static long long ghosts(const GridDev& g);
   static hipError_t totals(const GridDev& g, const double* partials, int nblocks, double* out,
                            hipStream_t s);
-  static int stage_e_blocks(const GridDev& g);
 };
 
 }  // namespace csph

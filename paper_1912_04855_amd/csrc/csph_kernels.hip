@@ -185,6 +185,20 @@ __device__ __forceinline__ void kgrad(const GridDev& g, Real dx, Real dy, Real d
   Kz = -(c * dz);
 }
 
+// FP32 form of the same gradient with the separation in lattice units (d/h):
+// g(q) = (3/4)[(2-q)_+^2 - 4 (1-q)_+^2] covers both spline pieces without a
+// branch, and K = ck (g(q)/q)/(3/4) d with ck = -(3/4) kappa / h.
+__device__ __forceinline__ void kgrad_lat(float ck, float dx, float dy, float dz, float K[3]) {
+  const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 1e-12f);
+  const float rs = __builtin_amdgcn_rsqf(r2);
+  const float q = r2 * rs;
+  const float t = fmaxf(2.0f - q, 0.0f), u = fmaxf(1.0f - q, 0.0f);
+  const float c = ck * rs * fmaf(t, t, -4.0f * u * u);
+  K[0] = c * dx;
+  K[1] = c * dy;
+  K[2] = c * dz;
+}
+
 __device__ __forceinline__ Real minmod(Real a, Real b) {
   if (a * b <= (Real)0) return (Real)0;
   const Real sg = a > (Real)0 ? (Real)1 : (Real)-1;
@@ -696,6 +710,7 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int i = T.x0 + tx, j = T.y0 + ty;
   const bool in = i < g.nx && j < g.ny;
+  const Real ih = (Real)g.inv_h;
 
   auto load = [&](int k) {
     const int s = ring3(k);
@@ -712,9 +727,16 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       S.ux[s][q] = ux;
       S.uy[s][q] = uy;
       S.uz[s][q] = uz;
-      S.xx[s][q] = F.xs[0][c];
-      S.xy[s][q] = F.xs[1][c];
-      S.xz[s][q] = F.xs[2][c];
+      if constexpr (kF64) {
+        S.xx[s][q] = F.xs[0][c];
+        S.xy[s][q] = F.xs[1][c];
+        S.xz[s][q] = F.xs[2][c];
+      } else {
+        // particle offsets in lattice units
+        S.xx[s][q] = F.xs[0][c] * ih;
+        S.xy[s][q] = F.xs[1][c] * ih;
+        S.xz[s][q] = F.xs[2][c] * ih;
+      }
       S.psi[s][q] = F.psis[c];
     }
   };
@@ -741,43 +763,70 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
       Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0;
       const int tb = hidx(tx + 1, ty + 1);
+      if constexpr (kF64) {
 #pragma unroll 1
-      for (int q = 0; q < 13; ++q) {
-        const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
-        // LDS index of the two partners: this thread's cell + a uniform offset
-        const int np = tb + ring3(k + oz) * HP + oy * HX + ox;
-        const int nm = tb + ring3(k - oz) * HP - oy * HX - ox;
-        const Real hx = (Real)g.hoff[q][0], hy = (Real)g.hoff[q][1], hz = (Real)g.hoff[q][2];
-        Real K[2][3], ub[2], fn[2], pn[2];
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int n = side == 0 ? np : nm;
-          // separation r_c - r_n = -h o + (xi_c - xi_n) (o -> -o on the minus side)
-          const Real dx = side == 0 ? hx + (xc[0] - xx_[n]) : (xc[0] - xx_[n]) - hx;
-          const Real dy = side == 0 ? hy + (xc[1] - xy_[n]) : (xc[1] - xy_[n]) - hy;
-          const Real dz = side == 0 ? hz + (xc[2] - xz_[n]) : (xc[2] - xz_[n]) - hz;
-          kgrad(g, dx, dy, dz, K[side][0], K[side][1], K[side][2]);
-          fn[side] = phi_[n];
-          pn[side] = psi_[n];
-          ub[side] = (uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
-                     (uc[2] + uz_[n]) * K[side][2];
-          if constexpr (kF64) ub[side] = 0.5 * ub[side];
-        }
-        if constexpr (kF64) {
-          Acc sp[2], dpsi[2], ff[2];
+        for (int q = 0; q < 13; ++q) {
+          const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
+          // LDS index of the two partners: this thread's cell + a uniform offset
+          const int np = tb + ring3(k + oz) * HP + oy * HX + ox;
+          const int nm = tb + ring3(k - oz) * HP - oy * HX - ox;
+          const Real hx = (Real)g.hoff[q][0], hy = (Real)g.hoff[q][1], hz = (Real)g.hoff[q][2];
+          Real K[2][3], ub[2], fn[2], pn[2];
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
-            ff[side] = fc * fn[side];
-            dpsi[side] = pn[side] - psc;
-            sp[side] = ff[side] + rc * dpsi[side];
+            const int n = side == 0 ? np : nm;
+            // separation r_c - r_n = -h o + (xi_c - xi_n) (o -> -o on the minus side)
+            const Real dx = side == 0 ? hx + (xc[0] - xx_[n]) : (xc[0] - xx_[n]) - hx;
+            const Real dy = side == 0 ? hy + (xc[1] - xy_[n]) : (xc[1] - xy_[n]) - hy;
+            const Real dz = side == 0 ? hz + (xc[2] - xz_[n]) : (xc[2] - xz_[n]) - hz;
+            kgrad(g, dx, dy, dz, K[side][0], K[side][1], K[side][2]);
+            fn[side] = phi_[n];
+            pn[side] = psi_[n];
+            ub[side] = (uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
+                       (uc[2] + uz_[n]) * K[side][2];
+            ub[side] = 0.5 * ub[side];
           }
+          {
+            Acc sp[2], dpsi[2], ff[2];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            a[d] = a[d] + (sp[0] * K[0][d] + sp[1] * K[1][d]);
-            gp[d] = gp[d] + (dpsi[0] * K[0][d] + dpsi[1] * K[1][d]);
+            for (int side = 0; side < 2; ++side) {
+              ff[side] = fc * fn[side];
+              dpsi[side] = pn[side] - psc;
+              sp[side] = ff[side] + rc * dpsi[side];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              a[d] = a[d] + (sp[0] * K[0][d] + sp[1] * K[1][d]);
+              gp[d] = gp[d] + (dpsi[0] * K[0][d] + dpsi[1] * K[1][d]);
+            }
+            be = be + (ff[0] * ub[0] + ff[1] * ub[1]);
           }
-          be = be + (ff[0] * ub[0] + ff[1] * ub[1]);
-        } else {
+        }
+      } else {
+        // the 13 pairs unrolled with their offsets known at compile time; the
+        // separations are in lattice units: d = (xi_c - xi_n)/h -+ o
+        const float ck = (float)(-0.75 * g.kappa_h2 * g.h);
+        const int bm = ring3(k - 1) * HP + tb, b0 = ring3(k) * HP + tb, bp = ring3(k + 1) * HP + tb;
+#pragma unroll
+        for (int q = 0; q < 13; ++q) {
+          const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
+          const int np = (oz == 0 ? b0 : bp) + oy * HX + ox;
+          const int nm = (oz == 0 ? b0 : bm) - oy * HX - ox;
+          float K[2][3], ub[2], fn[2], pn[2];
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int n = side == 0 ? np : nm;
+            const int sg = side == 0 ? 1 : -1;
+            float d[3] = {(float)(xc[0] - xx_[n]), (float)(xc[1] - xy_[n]), (float)(xc[2] - xz_[n])};
+            if (ox != 0) d[0] -= (float)(sg * ox);
+            if (oy != 0) d[1] -= (float)(sg * oy);
+            if (oz != 0) d[2] -= (float)(sg * oz);
+            kgrad_lat(ck, d[0], d[1], d[2], K[side]);
+            fn[side] = phi_[n];
+            pn[side] = psi_[n];
+            ub[side] = (uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
+                       (uc[2] + uz_[n]) * K[side][2];
+          }
           // sp+ K+ + sp- K- = (sp+ - sp-) K+ + sp- (K+ + K-).  The difference
           // sp+ - sp- = phi_c (phi+ - phi-) + rho_c (psi+ - psi-) carries the
           // well-balance cancellation: its two FP32 differences are exact for
@@ -824,8 +873,10 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       Real ut[3], pt;
       primitive(g, rc, mt[0], mt[1], mt[2], Et, ut[0], ut[1], ut[2], pt);
       const Real qdt = (Real)(0.25 * dt);
+      // xi^{n+1} = xi*/2 + dt (u^n + u~)/4 (the FP32 LDS holds xi*/h)
+      const Real hx = kF64 ? (Real)0.5 : (Real)(0.5 * g.h);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) F.xt[d][c] = (Real)0.5 * xc[d] + qdt * (un[d] + ut[d]);
+      for (int d = 0; d < 3; ++d) F.xt[d][c] = hx * xc[d] + qdt * (un[d] + ut[d]);
     }
     __syncthreads();
   }
@@ -863,28 +914,74 @@ __device__ __forceinline__ void acoustic_dissipation(const GridDev& g, int axis,
 __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real u4[5][4],
                                           const Real bL[5], const Real bR[5], Real xL, Real xR,
                                           Real dt, Real Fo[5]) {
-  const Real nuL = xL * (Real)g.inv_h;
-  const Real nuR = xR * (Real)g.inv_h;
-  Real UL[5], UR[5];
+  if constexpr (kF64) {
+    const Real nuL = xL * (Real)g.inv_h;
+    const Real nuR = xR * (Real)g.inv_h;
+    Real UL[5], UR[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const Real sL = minmod(u4[v][2] - u4[v][1], u4[v][1] - u4[v][0]);
-    const Real sR = minmod(u4[v][3] - u4[v][2], u4[v][2] - u4[v][1]);
-    UL[v] = bL[v] + (Real)0.5 * ((Real)1 - nuL) * sL;
-    UR[v] = bR[v] - (Real)0.5 * ((Real)1 + nuR) * sR;
-    Fo[v] = fmax(xL, (Real)0) * UL[v] + fmin(xR, (Real)0) * UR[v];
+    for (int v = 0; v < 5; ++v) {
+      const Real sL = minmod(u4[v][2] - u4[v][1], u4[v][1] - u4[v][0]);
+      const Real sR = minmod(u4[v][3] - u4[v][2], u4[v][2] - u4[v][1]);
+      UL[v] = bL[v] + (Real)0.5 * ((Real)1 - nuL) * sL;
+      UR[v] = bR[v] - (Real)0.5 * ((Real)1 + nuR) * sR;
+      Fo[v] = fmax(xL, (Real)0) * UL[v] + fmin(xR, (Real)0) * UR[v];
+    }
+    Real D[5];
+    acoustic_dissipation(g, axis, UL, UR, D);
+#pragma unroll
+    for (int v = 1; v < 5; ++v) Fo[v] = Fo[v] + dt * D[v];
+  } else {
+    // minmod(a, b) is the median of (a, b, 0); the reconstruction weights
+    // (1 -+ xi/h)/2 and the swept fractions are formed once per face
+    const float hh = 0.5f * (float)g.inv_h;
+    const float wL = fmaf(xL, -hh, 0.5f), wR = fmaf(xR, hh, 0.5f);
+    const float pL = fmaxf(xL, 0.0f), pR = fminf(xR, 0.0f);
+    float UL[5], UR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const float d0 = u4[v][1] - u4[v][0], d1 = u4[v][2] - u4[v][1], d2 = u4[v][3] - u4[v][2];
+      UL[v] = fmaf(wL, __builtin_amdgcn_fmed3f(d1, d0, 0.0f), bL[v]);
+      UR[v] = fmaf(-wR, __builtin_amdgcn_fmed3f(d2, d1, 0.0f), bR[v]);
+      Fo[v] = fmaf(pL, UL[v], pR * UR[v]);
+    }
+    // damping of the velocity jump: vacuum sides get a zero reciprocal density,
+    // which zeroes their velocity and sound speed without a branch
+    const float rv = (float)g.rho_vac, gm1 = (float)g.gm1, gam = (float)g.gamma;
+    const float irL = UL[0] > rv ? __builtin_amdgcn_rcpf(UL[0]) : 0.0f;
+    const float irR = UR[0] > rv ? __builtin_amdgcn_rcpf(UR[0]) : 0.0f;
+    float uL[3], uR[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uL[c] = UL[1 + c] * irL;
+      uR[c] = UR[1 + c] * irR;
+    }
+    const float mL = UL[1] * uL[0] + UL[2] * uL[1] + UL[3] * uL[2];
+    const float mR = UR[1] * uR[0] + UR[2] * uR[1] + UR[3] * uR[2];
+    const float pLp = fmaxf(gm1 * fmaf(-0.5f, mL, UL[4]), 0.0f);
+    const float pRp = fmaxf(gm1 * fmaf(-0.5f, mR, UR[4]), 0.0f);
+    const float cL = __builtin_amdgcn_sqrtf(gam * pLp * irL);
+    const float cR = __builtin_amdgcn_sqrtf(gam * pRp * irR);
+    const float a = fmaxf(fabsf(uL[axis]) + cL, fabsf(uR[axis]) + cR);
+    const float kk = -0.5f * dt * a * fminf(UL[0], UR[0]);
+    float Dm[3], de = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Dm[c] = (c == axis ? kk : 0.5f * kk) * (uR[c] - uL[c]);
+      de = fmaf(uL[c] + uR[c], Dm[c], de);
+      Fo[1 + c] += Dm[c];
+    }
+    Fo[4] = fmaf(0.5f, de, Fo[4]);
   }
-  Real D[5];
-  acoustic_dissipation(g, axis, UL, UR, D);
-#pragma unroll
-  for (int v = 1; v < 5; ++v) Fo[v] = Fo[v] + dt * D[v];
 }
 
 // The FP64 build computes every x and y face of a plane once and shares it
 // through LDS (its faces are expensive: correctly rounded divisions and square
 // roots); the FP32 build, latency-bound rather than ALU-bound here, lets each
 // cell evaluate its own four x-y faces and keeps the higher occupancy.
-constexpr bool kShareFaces = kF64;
+#ifndef CSPH_SHARE_FACES
+#define CSPH_SHARE_FACES CSPH_IS_DOUBLE
+#endif
+constexpr bool kShareFaces = CSPH_SHARE_FACES;
 constexpr int NFXS = kShareFaces ? NFX : 1, NFYS = kShareFaces ? NFY : 1;
 
 struct PlaneE {
@@ -1226,11 +1323,6 @@ dim3 cell_grid(const GridDev& g) {
 
 using CSPH_TAG::Real;
 using namespace CSPH_TAG;
-
-template <>
-int Launch<Real>::stage_e_blocks(const GridDev& g) {
-  return sweep_tiles(g, pick_tz(g));
-}
 
 template <>
 int Launch<Real>::tiles(const GridDev& g, int tz) {

@@ -7,9 +7,13 @@
 // completion flag every few steps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +43,19 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kNumFields = 26;  // U[2][5], psi, ms[4], xs[3], psis, mt[4], xt[3]
+
+// tile depths (z-planes per workgroup of the stencil sweeps) the autotuner tries
+constexpr int kTzMin = 2, kTzMax = 64;
+constexpr int kTzCand[] = {2, 4, 8, 16, 32, 64};
+
+// tile depths chosen by csph_autotune, per (device, dtype, nx, ny, nz): later
+// simulations of the same shape start from them
+std::mutex g_tune_mu;
+std::map<std::array<int, 5>, int> g_tune;
+
+std::array<int, 5> tune_key(int device, const csph_grid_desc& d) {
+  return {device, (int)d.dtype, d.nx, d.ny, d.nz};
+}
 
 // kernel normalisation: kappa = 1 / (2 sum_{a,b in {-1,0,1}} g(q_ab)/q_ab),
 // q_ab = sqrt(1 + a^2 + b^2), g(q)/q of the M4 spline (27-point sum exact for
@@ -149,7 +166,8 @@ Layout make_layout(const csph_grid_desc* d) {
   L.field_bytes = align_up((size_t)g.ncell * es);
   L.fields_off = 0;
   L.ctrl_off = L.fields_off + (size_t)kNumFields * L.field_bytes;
-  L.nblocks = d->dtype == CSPH_F64 ? Launch<double>::stage_e_blocks(g) : Launch<float>::stage_e_blocks(g);
+  // per-tile totals of stage E, sized for the shallowest tile depth a sim may use
+  L.nblocks = d->dtype == CSPH_F64 ? Launch<double>::tiles(g, kTzMin) : Launch<float>::tiles(g, kTzMin);
   L.partials_off = L.ctrl_off + align_up(sizeof(Ctrl));
   L.totals_off = L.partials_off + align_up((size_t)L.nblocks * 5 * sizeof(double));
   L.total = L.totals_off + align_up(5 * sizeof(double));
@@ -176,6 +194,7 @@ struct csph_sim {
   bool psi_dirty = true;
   bool need_smax = true;
   int tz = 0;            // z-planes per workgroup of the stencil sweeps
+  int tz_last = 0;       // tile depth of the last stage E launched (its per-tile totals)
   bool in_batch = false;
   bool stepped = false;  // partials describe the current state
   std::vector<double> psi_host;  // interior psi, kept to refill ghosts after BC changes
@@ -328,6 +347,7 @@ csph_status launch_steps(csph_sim* s, int n, double dt_max, double t_end) {
                                ev));
   }
   s->stepped = true;
+  s->tz_last = s->tz;
   return CSPH_OK;
 }
 
@@ -345,6 +365,12 @@ bool periodic_pairs_ok(const csph_sim* s) {
 csph_status init_sim(csph_sim* s) {
   s->g = make_grid(&s->desc);
   s->tz = s->is_f64() ? Launch<double>::default_tz(s->g) : Launch<float>::default_tz(s->g);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(s->device, s->desc));
+    if (it != g_tune.end()) s->tz = it->second;
+  }
+  s->tz_last = s->tz;
   for (int f = 0; f < 6; ++f) s->bc.kind[f] = kPeriodic;
   if (s->is_f64())
     bind_fields<double>(s, s->f64);
@@ -647,8 +673,9 @@ csph_status csph_totals(const csph_sim* s, double out[5]) {
     }
     return CSPH_OK;
   }
-  HIP_TRY(s->is_f64() ? Launch<double>::totals(s->g, s->partials, s->L.nblocks, s->totals_dev, s->stream)
-                   : Launch<float>::totals(s->g, s->partials, s->L.nblocks, s->totals_dev, s->stream));
+  const int nt = s->is_f64() ? Launch<double>::tiles(s->g, s->tz_last) : Launch<float>::tiles(s->g, s->tz_last);
+  HIP_TRY(s->is_f64() ? Launch<double>::totals(s->g, s->partials, nt, s->totals_dev, s->stream)
+                   : Launch<float>::totals(s->g, s->partials, nt, s->totals_dev, s->stream));
   HIP_TRY(hipMemcpyAsync(out, s->totals_dev, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return CSPH_OK;
@@ -698,7 +725,166 @@ csph_status csph_profile_read(csph_sim* s, double* avg_ms, int64_t* launches, in
   return CSPH_OK;
 }
 
-// batches are implemented in csph_batch.hip
+csph_status csph_set_tile_depth(csph_sim* s, int32_t tz) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (tz < kTzMin || tz > kTzMax) return fail(CSPH_ERR_ARG, "tile depth must be in [2, 64]");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
+  s->tz = tz;
+  return CSPH_OK;
+}
+
+csph_status csph_get_tile_depth(const csph_sim* s, int32_t* tz) {
+  if (!s || !tz) return fail(CSPH_ERR_ARG, "sim or tz is NULL");
+  *tz = s->tz;
+  return CSPH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// event-timed wall of `fn` on `stream`, in milliseconds
+template <typename Fn>
+csph_status time_on(hipStream_t stream, Fn fn, double* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(CSPH_ERR_DEVICE, "hipEventCreate failed");
+  }
+  csph_status st = CSPH_OK;
+  if (hipEventRecord(e0, stream) != hipSuccess) st = fail(CSPH_ERR_DEVICE, "hipEventRecord failed");
+  if (!st) st = fn();
+  if (!st && hipEventRecord(e1, stream) != hipSuccess) st = fail(CSPH_ERR_DEVICE, "hipEventRecord failed");
+  if (!st && hipEventSynchronize(e1) != hipSuccess) st = fail(CSPH_ERR_DEVICE, "hipEventSynchronize failed");
+  float f = 0.0f;
+  if (!st && hipEventElapsedTime(&f, e0, e1) != hipSuccess) st = fail(CSPH_ERR_DEVICE, "hipEventElapsedTime failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = f;
+  return st;
+}
+
+// a library-owned copy of `s` (same description, boundaries, potential, state
+// and time), for trial runs that must not disturb `s`
+csph_status clone_sim(const csph_sim* s, csph_sim** out) {
+  *out = nullptr;
+  csph_sim* t = new (std::nothrow) csph_sim();
+  if (!t) return fail(CSPH_ERR_NOMEM, "host allocation failed");
+  t->desc = s->desc;
+  t->stream = s->stream;
+  t->L = s->L;
+  t->device = s->device;
+  t->g = s->g;
+  t->bc = s->bc;
+  std::memcpy(t->inflow_prim, s->inflow_prim, sizeof(t->inflow_prim));
+  t->psi_dirty = s->psi_dirty;
+  t->need_smax = s->need_smax;
+  t->tz = s->tz;
+  t->tz_last = s->tz_last;
+  t->has_psi = s->has_psi;
+  void* p = nullptr;
+  if (hipMalloc(&p, s->L.total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete t;
+    return fail(CSPH_ERR_NOMEM, "hipMalloc of the trial copy failed");
+  }
+  t->buf = (char*)p;
+  t->owned = true;
+  if (t->is_f64())
+    bind_fields<double>(t, t->f64);
+  else
+    bind_fields<float>(t, t->f32);
+  t->ctrl = (Ctrl*)(t->buf + t->L.ctrl_off);
+  t->partials = (double*)(t->buf + t->L.partials_off);
+  t->totals_dev = (double*)(t->buf + t->L.totals_off);
+  if (hipMemcpyAsync(t->buf, s->buf, s->L.total, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess) {
+    (void)hipFree(t->buf);
+    delete t;
+    return fail(CSPH_ERR_DEVICE, "copy of the state for the trial runs failed");
+  }
+  *out = t;
+  return CSPH_OK;
+}
+
+// candidate depths worth trying on a grid of nz planes (deeper tiles than the
+// grid add nothing)
+std::vector<int> tz_candidates(int nz) {
+  std::vector<int> c;
+  for (int tz : kTzCand) {
+    c.push_back(tz);
+    if (tz >= nz) break;
+  }
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+csph_status csph_autotune(csph_sim* s, int32_t trial_steps, int32_t* tz_out, double* ms_per_step) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: tune the batch");
+  if (trial_steps < 1 || trial_steps > 1000) return fail(CSPH_ERR_ARG, "trial_steps must be in [1, 1000]");
+  if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
+  Ctrl c{};
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  if (c.status) return fail(CSPH_ERR_STATE, "sticky error: call csph_set_state");
+  // ghosts of psi and the first dt are made once on the original, then copied
+  st = s->is_f64() ? prepare<double>(s) : prepare<float>(s);
+  if (st) return st;
+  csph_sim* t = nullptr;
+  st = clone_sim(s, &t);
+  if (st) return st;
+  Ctrl c0{};
+  st = read_ctrl(t, &c0);
+  c0.done = 0;
+  int best = s->tz;
+  double best_ms = INFINITY;
+  for (int tz : tz_candidates(s->g.nz)) {
+    if (st) break;
+    t->tz = tz;
+    // one untimed step (first use of this launch shape), then the timed ones,
+    // each from the same starting state
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && !st; ++rep) {
+      if (hipMemcpyAsync(t->buf, s->buf, s->L.total, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
+        st = fail(CSPH_ERR_DEVICE, "copy of the state for a trial run failed");
+        break;
+      }
+      st = write_ctrl(t, c0);
+      if (st) break;
+      const int n = rep == 0 ? 1 : trial_steps;
+      st = time_on(t->stream, [&]() { return launch(t, n, 0.0, INFINITY); }, &ms);
+    }
+    if (st) break;
+    Ctrl ct{};
+    st = read_ctrl(t, &ct);
+    if (st) break;
+    if (ct.status) continue;  // an invalid trial (the state failed) does not count
+    const double per = ms / trial_steps;
+    if (per < best_ms) {
+      best_ms = per;
+      best = tz;
+    }
+  }
+  (void)hipStreamSynchronize(t->stream);
+  (void)hipFree(t->buf);
+  delete t;
+  if (st) return st;
+  s->tz = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(s->device, s->desc)] = best;
+  }
+  if (tz_out) *tz_out = best;
+  if (ms_per_step) *ms_per_step = best_ms;
+  return CSPH_OK;
+}
+
+// batches are implemented below
 
 }  // extern "C"
 
@@ -781,6 +967,7 @@ csph_status build_table(csph_batch* b) {
     I.ctrl = s->ctrl;
     I.partials = s->partials;
     I.tz = s->tz;
+    s->tz_last = s->tz;
     tp[r + 1] = tp[r] + Launch<Real>::tiles(s->g, s->tz);
     gp[r + 1] = gp[r] + Launch<Real>::ghosts(s->g);
   }
@@ -947,6 +1134,78 @@ csph_status csph_batch_remove(csph_batch* b, int32_t slot) {
   b->used_bytes -= s->L.total;
   b->slots[slot] = Member{};
   b->dirty = true;
+  return CSPH_OK;
+}
+
+csph_status csph_batch_autotune(csph_batch* b, int32_t trial_steps, int32_t* tz_out,
+                                double* ms_per_step) {
+  if (!b) return fail(CSPH_ERR_ARG, "batch is NULL");
+  if (trial_steps < 1 || trial_steps > 1000) return fail(CSPH_ERR_ARG, "trial_steps must be in [1, 1000]");
+  std::vector<csph_sim*> mem;
+  for (auto& m : b->slots)
+    if (m.used) mem.push_back(m.sim);
+  if (mem.empty()) return fail(CSPH_ERR_ARG, "batch has no members");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  // snapshot every member's buffer; each trial starts from it and it is
+  // restored at the end, so tuning leaves the members as they were
+  std::vector<void*> snap(mem.size(), nullptr);
+  std::vector<int> tz0(mem.size());
+  csph_status st = CSPH_OK;
+  for (size_t q = 0; q < mem.size() && !st; ++q) {
+    tz0[q] = mem[q]->tz;
+    if (hipMalloc(&snap[q], mem[q]->L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      snap[q] = nullptr;
+      st = fail(CSPH_ERR_NOMEM, "hipMalloc of a member snapshot failed");
+      break;
+    }
+    if (hipMemcpyAsync(snap[q], mem[q]->buf, mem[q]->L.total, hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+      st = fail(CSPH_ERR_DEVICE, "member snapshot copy failed");
+  }
+  auto restore = [&]() -> csph_status {
+    for (size_t q = 0; q < mem.size(); ++q)
+      if (snap[q])
+        HIP_TRY(hipMemcpyAsync(mem[q]->buf, snap[q], mem[q]->L.total, hipMemcpyDeviceToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return CSPH_OK;
+  };
+  int nzmax = 0;
+  for (csph_sim* m : mem) nzmax = std::max(nzmax, m->g.nz);
+  int best = -1;
+  double best_ms = INFINITY;
+  for (int tz : tz_candidates(nzmax)) {
+    if (st) break;
+    for (csph_sim* m : mem) m->tz = tz;
+    b->dirty = true;
+    st = b->dtype == CSPH_F64 ? build_table<double>(b) : build_table<float>(b);
+    if (st) break;
+    double ms = 0.0;
+    // the first call captures the k-step graph; the second replays it
+    for (int rep = 0; rep < 2 && !st; ++rep) {
+      st = restore();
+      if (st) break;
+      st = time_on(b->stream,
+                   [&]() { return b->dtype == CSPH_F64 ? batch_launch<double>(b, trial_steps)
+                                                       : batch_launch<float>(b, trial_steps); },
+                   &ms);
+    }
+    if (st) break;
+    const double per = ms / trial_steps;
+    if (per < best_ms) {
+      best_ms = per;
+      best = tz;
+    }
+  }
+  csph_status st2 = restore();
+  for (size_t q = 0; q < mem.size(); ++q) {
+    mem[q]->tz = (st || best < 0) ? tz0[q] : best;
+    if (snap[q]) (void)hipFree(snap[q]);
+  }
+  b->dirty = true;
+  if (st) return st;
+  if (st2) return st2;
+  if (tz_out) *tz_out = best;
+  if (ms_per_step) *ms_per_step = best_ms;
   return CSPH_OK;
 }
 

@@ -176,6 +176,25 @@ class Sim:
         check(_lib.load().csph_profile_read(self._h, _ptr(ms), _ptr(n), 5), "csph_profile_read")
         return {g: (float(ms[q]), int(n[q])) for q, g in enumerate(self.PROFILE_GROUPS)}
 
+    # ------------------------------------------------------------------ tiling
+    @property
+    def tile_depth(self) -> int:
+        tz = C.c_int32()
+        check(_lib.load().csph_get_tile_depth(self._h, C.byref(tz)), "csph_get_tile_depth")
+        return tz.value
+
+    @tile_depth.setter
+    def tile_depth(self, tz: int):
+        check(_lib.load().csph_set_tile_depth(self._h, int(tz)), "csph_set_tile_depth")
+
+    def autotune(self, trial_steps=3):
+        """Pick the fastest tile depth by timing trial steps on a copy of this
+        simulation (which is not advanced).  Returns (depth, ms per step)."""
+        tz, ms = C.c_int32(), C.c_double()
+        check(_lib.load().csph_autotune(self._h, int(trial_steps), C.byref(tz), C.byref(ms)),
+              "csph_autotune")
+        return tz.value, ms.value
+
     STAGE_FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
                     "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz"]
 
@@ -231,6 +250,15 @@ class Batch:
         check(_lib.load().csph_batch_advance(self._h, int(k), C.byref(n) if sync else None),
               "csph_batch_advance")
         return n.value
+
+    def autotune(self, trial_steps=3):
+        """Pick the fastest tile depth for every member by timing trial steps of
+        the whole batch; members are restored afterwards.  Returns (depth, ms per
+        batch step)."""
+        tz, ms = C.c_int32(), C.c_double()
+        check(_lib.load().csph_batch_autotune(self._h, int(trial_steps), C.byref(tz),
+                                              C.byref(ms)), "csph_batch_autotune")
+        return tz.value, ms.value
 
     def poll(self):
         cap = max(1, len(self.members))

@@ -28,3 +28,16 @@ def l1_rel_per_var(a, b):
 
 def orders(errs):
     return [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+
+
+def golden(name):
+    """Values of a fixture under tests/golden/ (``key value`` lines, '#' comments)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = line.split()
+            out[k] = float(v)
+    return out
