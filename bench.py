@@ -253,6 +253,8 @@ def main():
                     help="use this tile depth (z-planes per workgroup) instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched workload (for profiling it)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -278,6 +280,10 @@ def main():
         return
     from paper_1912_04855_amd import problems as P
 
+    if args.batch_only:
+        r = run_batch(count=args.batch_count, steps=args.steps)
+        print(json.dumps({"batched": r}), flush=True)
+        return
     pr = P.well_flow(args.n, steps=args.steps)
     cells = pr.cells
     log(f"[bench] potential-well flow {args.n}^3 {args.dtype}: warmup {args.warmup}, "

@@ -171,7 +171,8 @@ csph_status csph_autotune(csph_sim* sim, int32_t trial_steps, int32_t* tz_out, d
  * must outlive its membership.  Every member keeps its own dt, t and step
  * target; members of different sizes are flattened into one tile list, and one
  * launch per stage advances all of them.  hbm_budget bounds the summed
- * csph_required_bytes of the members (0 = unbounded). */
+ * csph_required_bytes of the members (0 = unbounded).  Reads of a member
+ * (state, time, totals, stage fields) first wait for the batch's stream. */
 csph_status csph_batch_create(csph_dtype dtype, void* hip_stream, size_t hbm_budget,
                               csph_batch** out);
 /* Add a member that stops after `steps` more steps or at t_end (first reached).

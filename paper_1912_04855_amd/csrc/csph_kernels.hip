@@ -132,6 +132,15 @@ __device__ __forceinline__ Real rsqrt_(Real x) {
   }
 }
 
+// square root: correctly rounded in FP64; the hardware approximation in FP32
+__device__ __forceinline__ Real sqrt_fast(Real x) {
+  if constexpr (kF64) {
+    return sqrt(x);
+  } else {
+    return __builtin_amdgcn_sqrtf(x);
+  }
+}
+
 // p = (gamma-1)(E - m.u/2), u = m/rho; vacuum (rho <= rho_vac): u = 0; p >= 0.
 __device__ __forceinline__ void primitive(const GridDev& g, Real rho, Real mx, Real my, Real mz,
                                           Real E, Real& ux, Real& uy, Real& uz, Real& p) {
@@ -550,7 +559,7 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
       Real ux, uy, uz, p;
       primitive(g, r, MX[c], MY[c], MZ[c], EE[c], ux, uy, uz, p);
       S.rho[s][q] = r;
-      S.phi[s][q] = sqrt((Real)2 * p);
+      S.phi[s][q] = sqrt_fast((Real)2 * p);
       S.ux[s][q] = ux;
       S.uy[s][q] = uy;
       S.uz[s][q] = uz;
@@ -723,7 +732,7 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       Real ux, uy, uz, p;
       primitive(g, r, MSX[c], MSY[c], MSZ[c], ES[c], ux, uy, uz, p);
       S.rho[s][q] = r;
-      S.phi[s][q] = sqrt((Real)2 * p);
+      S.phi[s][q] = sqrt_fast((Real)2 * p);
       S.ux[s][q] = ux;
       S.uy[s][q] = uy;
       S.uz[s][q] = uz;
@@ -974,12 +983,11 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
   }
 }
 
-// The FP64 build computes every x and y face of a plane once and shares it
-// through LDS (its faces are expensive: correctly rounded divisions and square
-// roots); the FP32 build, latency-bound rather than ALU-bound here, lets each
-// cell evaluate its own four x-y faces and keeps the higher occupancy.
+// Every x and y face of a plane is computed once and shared by its two cells
+// through LDS (2.2 face evaluations per cell and plane instead of 4); the z face
+// is carried in registers from one plane to the next.
 #ifndef CSPH_SHARE_FACES
-#define CSPH_SHARE_FACES CSPH_IS_DOUBLE
+#define CSPH_SHARE_FACES 1
 #endif
 constexpr bool kShareFaces = CSPH_SHARE_FACES;
 constexpr int NFXS = kShareFaces ? NFX : 1, NFYS = kShareFaces ? NFY : 1;

@@ -196,6 +196,7 @@ struct csph_sim {
   int tz = 0;            // z-planes per workgroup of the stencil sweeps
   int tz_last = 0;       // tile depth of the last stage E launched (its per-tile totals)
   bool in_batch = false;
+  hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool stepped = false;  // partials describe the current state
   std::vector<double> psi_host;  // interior psi, kept to refill ghosts after BC changes
   bool has_psi = false;
@@ -226,7 +227,16 @@ void bind_fields(csph_sim* s, Fields<Real>& F) {
   for (int v = 0; v < 3; ++v) F.xt[v] = (Real*)s->field_ptr(k++);
 }
 
+// a batch member's device state is written on the batch's stream: reads of it
+// wait for that stream first
+csph_status wait_batch(const csph_sim* s) {
+  if (s->in_batch && s->batch_stream) HIP_TRY(hipStreamSynchronize(s->batch_stream));
+  return CSPH_OK;
+}
+
 csph_status read_ctrl(const csph_sim* s, Ctrl* out) {
+  csph_status st = wait_batch(s);
+  if (st) return st;
   HIP_TRY(hipMemcpyAsync(out, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return CSPH_OK;
@@ -263,6 +273,8 @@ csph_status upload_field(csph_sim* s, Real* dst, const double* interior) {
 
 template <typename Real>
 csph_status download_field(const csph_sim* s, const Real* src, double* interior) {
+  csph_status st = wait_batch(s);
+  if (st) return st;
   const GridDev& g = s->g;
   std::vector<Real> pad((size_t)g.ncell);
   HIP_TRY(hipMemcpyAsync(pad.data(), src, pad.size() * sizeof(Real), hipMemcpyDeviceToHost, s->stream));
@@ -673,6 +685,8 @@ csph_status csph_totals(const csph_sim* s, double out[5]) {
     }
     return CSPH_OK;
   }
+  csph_status stw = wait_batch(s);
+  if (stw) return stw;
   const int nt = s->is_f64() ? Launch<double>::tiles(s->g, s->tz_last) : Launch<float>::tiles(s->g, s->tz_last);
   HIP_TRY(s->is_f64() ? Launch<double>::totals(s->g, s->partials, nt, s->totals_dev, s->stream)
                    : Launch<float>::totals(s->g, s->partials, nt, s->totals_dev, s->stream));
@@ -1075,6 +1089,7 @@ csph_status csph_batch_add(csph_batch* b, csph_sim* s, int64_t steps, double t_e
   b->slots[q].sim = s;
   b->slots[q].used = true;
   s->in_batch = true;
+  s->batch_stream = b->stream;
   s->stepped = true;
   b->used_bytes += need;
   b->dirty = true;
@@ -1131,6 +1146,7 @@ csph_status csph_batch_remove(csph_batch* b, int32_t slot) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   csph_sim* s = b->slots[slot].sim;
   s->in_batch = false;
+  s->batch_stream = nullptr;
   b->used_bytes -= s->L.total;
   b->slots[slot] = Member{};
   b->dirty = true;
@@ -1213,7 +1229,10 @@ csph_status csph_batch_destroy(csph_batch* b) {
   if (!b) return CSPH_OK;
   (void)hipStreamSynchronize(b->stream);
   for (auto& m : b->slots)
-    if (m.used) m.sim->in_batch = false;
+    if (m.used) {
+      m.sim->in_batch = false;
+      m.sim->batch_stream = nullptr;
+    }
   drop_graph(b);
   if (b->table) (void)hipFree(b->table);
   if (b->tile_prefix) (void)hipFree(b->tile_prefix);
