@@ -140,7 +140,7 @@ def roofline(prof, cells, dtype):
     return out
 
 
-def run_batch(count=512, steps=100, seed=0, chunk=10):
+def run_batch(count=512, steps=100, seed=0, chunk=10, tile_depth=0):
     """The batched workload: `count` independent simulations of uneven sizes
     (edges in {32, 48, 64, 96} per axis, a Sod tube or a Sedov blast each), FP32,
     advanced together `steps` steps each; one launch per stage for the whole
@@ -157,9 +157,14 @@ def run_batch(count=512, steps=100, seed=0, chunk=10):
         s = from_problem(pr, dtype="f32")
         sims.append(s)
         cells += pr.cells
+        if tile_depth:
+            s.tile_depth = tile_depth
         b.add(s, steps)
     setup = time.perf_counter() - t0
-    tz, _ = b.autotune(trial_steps=3)
+    if tile_depth:
+        tz = tile_depth
+    else:
+        tz, _ = b.autotune(trial_steps=3)
     # the batch runs on a stream of its own: the timed region is bracketed by
     # device synchronisations and measured on the host clock
     torch.cuda.synchronize()
@@ -256,6 +261,8 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched workload (for profiling it)")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-tile-depth", type=int, default=0,
+                    help="tile depth of every batch member instead of autotuning it")
     ap.add_argument("--serve-count", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for the HBM "
@@ -281,7 +288,7 @@ def main():
     from paper_1912_04855_amd import problems as P
 
     if args.batch_only:
-        r = run_batch(count=args.batch_count, steps=args.steps)
+        r = run_batch(count=args.batch_count, steps=args.steps, tile_depth=args.batch_tile_depth)
         print(json.dumps({"batched": r}), flush=True)
         return
     pr = P.well_flow(args.n, steps=args.steps)
@@ -318,7 +325,7 @@ def main():
     if not args.no_batch:
         log(f"[bench] batched workload: {args.batch_count} instances")
         try:
-            out["batched"] = run_batch(count=args.batch_count)
+            out["batched"] = run_batch(count=args.batch_count, tile_depth=args.batch_tile_depth)
             log(f"[bench] batched: {out['batched']['value']:.3e} cell-updates/s")
         except Exception as e:  # the headline stands without it
             out["batched"] = {"error": repr(e)}

@@ -268,80 +268,115 @@ __device__ __forceinline__ int map_index(int x, int n, int kind) {
   return x < 0 ? 0 : n - 1;  // outflow (and psi at inflow faces)
 }
 
-// decode ghost cell number t into (i, j, k); false beyond the last ghost cell
-__device__ __forceinline__ bool ghost_cell(const GridDev& g, long long t, int& i, int& j, int& k) {
-  const long long zone_z = 4LL * g.sx * g.sy;
-  const long long zone_y = (long long)g.nz * 4 * g.sx;
-  const long long zone_x = (long long)g.nz * g.ny * 4;
+// decode ghost cell number t into (i, j, k); false beyond the last ghost cell.
+// Ghost cells are numbered in three zones: the 4 z-planes (full x-y extent),
+// then the 4 y-rows of every interior z-plane (full x extent), then the 4
+// x-cells of every interior row.  Counts fit in 32 bits for any grid the
+// library accepts.
+__device__ __forceinline__ bool ghost_cell(const GridDev& g, unsigned t, int& i, int& j, int& k) {
+  const unsigned sx = (unsigned)g.sx, sxy = (unsigned)g.sx * (unsigned)g.sy;
+  const unsigned zone_z = 4u * sxy;
+  const unsigned zone_y = (unsigned)g.nz * 4u * sx;
+  const unsigned zone_x = (unsigned)g.nz * (unsigned)g.ny * 4u;
   if (t < zone_z) {
-    const int kk = (int)(t / ((long long)g.sx * g.sy));
-    const long long r = t - (long long)kk * g.sx * g.sy;
-    j = (int)(r / g.sx) - kGhost;
-    i = (int)(r % g.sx) - kGhost;
-    k = kk < 2 ? kk - 2 : g.nz + (kk - 2);
+    const unsigned kk = t / sxy, r = t - kk * sxy;
+    const unsigned jj = r / sx;
+    j = (int)jj - kGhost;
+    i = (int)(r - jj * sx) - kGhost;
+    k = kk < 2 ? (int)kk - 2 : g.nz + ((int)kk - 2);
   } else if (t < zone_z + zone_y) {
-    const long long u = t - zone_z;
-    k = (int)(u / (4LL * g.sx));
-    const long long r = u - (long long)k * 4 * g.sx;
-    const int jj = (int)(r / g.sx);
-    i = (int)(r % g.sx) - kGhost;
-    j = jj < 2 ? jj - 2 : g.ny + (jj - 2);
+    const unsigned u = t - zone_z, row = 4u * sx;
+    const unsigned kq = u / row, r = u - kq * row;
+    const unsigned jj = r / sx;
+    k = (int)kq;
+    i = (int)(r - jj * sx) - kGhost;
+    j = jj < 2 ? (int)jj - 2 : g.ny + ((int)jj - 2);
   } else if (t < zone_z + zone_y + zone_x) {
-    const long long u = t - zone_z - zone_y;
-    k = (int)(u / (4LL * g.ny));
-    const long long r = u - (long long)k * 4 * g.ny;
-    j = (int)(r / 4);
-    const int ii = (int)(r % 4);
-    i = ii < 2 ? ii - 2 : g.nx + (ii - 2);
+    const unsigned u = t - zone_z - zone_y, row = 4u * (unsigned)g.ny;
+    const unsigned kq = u / row, r = u - kq * row;
+    const unsigned jj = r >> 2, ii = r & 3u;
+    k = (int)kq;
+    j = (int)jj;
+    i = ii < 2 ? (int)ii - 2 : g.nx + ((int)ii - 2);
   } else {
     return false;
   }
   return true;
 }
 
-// Value of ghost cell (i,j,k) of a field with the given role: the last axis
-// filled (z) decides first, then y, then x, which composes the per-face rules
-// applied in x, y, z order.
-__device__ __forceinline__ Real ghost_value(const GridDev& g, const BcDev& bc, const Real* f, int role,
-                                            int i, int j, int k, double dt) {
+// Where ghost cell (i, j, k) takes its values from.  The per-face rules are
+// composed in x, y, z order, so the last axis (z) decides first: walking z, y,
+// x, each out-of-range coordinate is mapped by its face's rule until an inflow
+// face is met, whose Dirichlet state then gives the value (except for psi,
+// which inflow faces copy like outflow).  flip holds the reflected axes met on
+// the way: the normal momentum and particle offset of such an axis change sign.
+struct GhostSrc {
+  long long src;   // padded index of the source cell (when inflow < 0)
+  int inflow;      // inflow face giving the value, or -1
+  int flip;        // bit a: axis a reflected
+};
+
+__device__ __forceinline__ GhostSrc ghost_src(const GridDev& g, const BcDev& bc, int i, int j, int k,
+                                              bool psi) {
   const int n[3] = {g.nx, g.ny, g.nz};
   int c[3] = {i, j, k};
-  Real sign = (Real)1;
+  GhostSrc r{0, -1, 0};
   for (int ax = 2; ax >= 0; --ax) {
     if (c[ax] >= 0 && c[ax] < n[ax]) continue;
     const int face = 2 * ax + (c[ax] < 0 ? 0 : 1);
     const int kind = bc.kind[face];
-    if (kind == kInflow && role != kPsi) {
-      const Real v = role <= kE ? (Real)bc.cons[face][role] : (Real)(dt * bc.vel[face][role - kXx]);
-      return sign * v;
+    if (kind == kInflow && !psi) {
+      r.inflow = face;
+      return r;
     }
     c[ax] = map_index(c[ax], n[ax], kind);
-    if (kind == kReflect && (role == kMx + ax || role == kXx + ax)) sign = -sign;
+    if (kind == kReflect) r.flip ^= 1 << ax;
   }
-  return sign * f[cell(g, c[0], c[1], c[2])];
+  r.src = cell(g, c[0], c[1], c[2]);
+  return r;
+}
+
+// value of a field with the given role at a ghost cell
+__device__ __forceinline__ Real ghost_get(const BcDev& bc, const GhostSrc& m, const Real* f, int role,
+                                          double dt) {
+  int axis = -1;
+  if (role >= kMx && role <= kMz) axis = role - kMx;
+  if (role >= kXx && role <= kXz) axis = role - kXx;
+  const Real sign = (axis >= 0 && ((m.flip >> axis) & 1)) ? (Real)-1 : (Real)1;
+  if (m.inflow >= 0) {
+    const Real v = role <= kE ? (Real)bc.cons[m.inflow][role] : (Real)(dt * bc.vel[m.inflow][role - kXx]);
+    return sign * v;
+  }
+  return sign * f[m.src];
 }
 
 __device__ __forceinline__ void fill_body(const FillSet<Real>& fs, const GridDev& g, const BcDev& bc,
-                                          const Ctrl* ctrl, long long t) {
+                                          const Ctrl* ctrl, unsigned t) {
   int i, j, k;
   if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
-  for (int q = 0; q < fs.n; ++q) fs.f[q][cg] = ghost_value(g, bc, fs.f[q], fs.role[q], i, j, k, dt);
+  for (int q = 0; q < fs.n; ++q) {
+    const GhostSrc m = ghost_src(g, bc, i, j, k, fs.role[q] == kPsi);
+    fs.f[q][cg] = ghost_get(bc, m, fs.f[q], fs.role[q], dt);
+  }
 }
 
 // ghosts of the predicted particles, then psi at their displaced positions for
 // the first ghost layer (the corrector reads psi* of index neighbours only)
 __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
-                                               const Ctrl* ctrl, long long t) {
+                                               const Ctrl* ctrl, unsigned t) {
   int i, j, k;
   if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
-  for (int q = 0; q < 4; ++q) F.ms[q][cg] = ghost_value(g, bc, F.ms[q], kMx + q, i, j, k, dt);
+  const GhostSrc m = ghost_src(g, bc, i, j, k, false);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) F.ms[q][cg] = ghost_get(bc, m, F.ms[q], kMx + q, dt);
   Real xi[3];
+#pragma unroll
   for (int q = 0; q < 3; ++q) {
-    xi[q] = ghost_value(g, bc, F.xs[q], kXx + q, i, j, k, dt);
+    xi[q] = ghost_get(bc, m, F.xs[q], kXx + q, dt);
     F.xs[q][cg] = xi[q];
   }
   if (i >= -1 && i <= g.nx && j >= -1 && j <= g.ny && k >= -1 && k <= g.nz) {
@@ -353,59 +388,64 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
 
 // ghosts of the post-Lagrange particles
 __device__ __forceinline__ void fill_corr_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
-                                               const Ctrl* ctrl, long long t) {
+                                               const Ctrl* ctrl, unsigned t) {
   int i, j, k;
   if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
-  for (int q = 0; q < 4; ++q) F.mt[q][cg] = ghost_value(g, bc, F.mt[q], kMx + q, i, j, k, dt);
-  for (int q = 0; q < 3; ++q) F.xt[q][cg] = ghost_value(g, bc, F.xt[q], kXx + q, i, j, k, dt);
+  const GhostSrc m = ghost_src(g, bc, i, j, k, false);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) F.mt[q][cg] = ghost_get(bc, m, F.mt[q], kMx + q, dt);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) F.xt[q][cg] = ghost_get(bc, m, F.xt[q], kXx + q, dt);
 }
 
 __device__ __forceinline__ void fill_state_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
-                                                const Ctrl* ctrl, long long t) {
+                                                const Ctrl* ctrl, unsigned t) {
   int i, j, k;
   if (!ghost_cell(g, t, i, j, k)) return;
   const int par = ctrl->par;
   const long long cg = cell(g, i, j, k);
-  for (int role = 0; role < 5; ++role)
-    F.U[par][role][cg] = ghost_value(g, bc, F.U[par][role], role, i, j, k, 0.0);
+  const GhostSrc m = ghost_src(g, bc, i, j, k, false);
+#pragma unroll
+  for (int role = 0; role < 5; ++role) F.U[par][role][cg] = ghost_get(bc, m, F.U[par][role], role, 0.0);
 }
 
 __global__ void __launch_bounds__(256) k_fill(FillSet<Real> fs, GridDev g, BcDev bc,
                                               const Ctrl* __restrict__ ctrl, int check_active) {
   if (check_active && !ctrl->active) return;
-  fill_body(fs, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  fill_body(fs, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_fill_pred(Fields<Real> F, GridDev g, BcDev bc,
                                                    const Ctrl* __restrict__ ctrl) {
   if (!ctrl->active) return;
-  fill_pred_body(F, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  fill_pred_body(F, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_fill_corr(Fields<Real> F, GridDev g, BcDev bc,
                                                    const Ctrl* __restrict__ ctrl) {
   if (!ctrl->active) return;
-  fill_corr_body(F, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  fill_corr_body(F, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_fill_state(Fields<Real> F, GridDev g, BcDev bc,
                                                     const Ctrl* __restrict__ ctrl) {
   if (!ctrl->active) return;
-  fill_state_body(F, g, bc, ctrl, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  fill_state_body(F, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// batched ghost fills: thread -> (instance, ghost cell) through the ghost prefix
+// batched ghost fills: every instance's ghost range is padded to whole blocks
+// of 256, so a block belongs to one instance and finds it once
 template <int kWhich>
 __global__ void __launch_bounds__(256) k_fill_batch(const Inst<Real>* __restrict__ tab,
                                                     const long long* __restrict__ prefix, int n) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = find_inst(prefix, n, gid);
+  const long long b0 = (long long)blockIdx.x * blockDim.x;
+  const int q = find_inst(prefix, n, b0);
   if (q < 0) return;
   const Inst<Real>& I = tab[q];
   if (!I.ctrl->active) return;
-  const long long t = gid - prefix[q];
+  const unsigned t = (unsigned)(b0 - prefix[q]) + threadIdx.x;
   if (kWhich == 0) fill_state_body(I.F, I.g, I.bc, I.ctrl, t);
   else if (kWhich == 1) fill_pred_body(I.F, I.g, I.bc, I.ctrl, t);
   else fill_corr_body(I.F, I.g, I.bc, I.ctrl, t);

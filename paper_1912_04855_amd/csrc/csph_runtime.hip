@@ -983,7 +983,8 @@ csph_status build_table(csph_batch* b) {
     I.tz = s->tz;
     s->tz_last = s->tz;
     tp[r + 1] = tp[r] + Launch<Real>::tiles(s->g, s->tz);
-    gp[r + 1] = gp[r] + Launch<Real>::ghosts(s->g);
+    // each member's ghost range padded to whole fill blocks (one instance per block)
+    gp[r + 1] = gp[r] + (Launch<Real>::ghosts(s->g) + 255) / 256 * 256;
   }
   b->total_tiles = tp[n];
   b->total_ghosts = gp[n];
