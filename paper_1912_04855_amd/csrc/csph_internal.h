@@ -113,9 +113,10 @@ struct Launch {
                          double* partials, double dt_max, double t_end, int tz, hipStream_t s,
                          hipEvent_t* ev);
   // one step of every active member of a batch, one launch per stage
-  static hipError_t batch_step(const Inst<Real>* tab, const int* tile_prefix,
-                               const long long* ghost_prefix, int n, int total_tiles,
-                               long long total_ghosts, int* flags, hipStream_t s);
+  // tile_map[t] = (member, tile of that member); fill_map[b] = (member, first
+  // ghost cell of fill block b)
+  static hipError_t batch_step(const Inst<Real>* tab, const int2* tile_map, const int2* fill_map,
+                               int n, int total_tiles, int fill_blocks, int* flags, hipStream_t s);
   static int tiles(const GridDev& g, int tz);
   static int default_tz(const GridDev& g);
   static long long ghosts(const GridDev& g);

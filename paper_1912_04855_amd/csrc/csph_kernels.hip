@@ -111,18 +111,6 @@ __device__ __forceinline__ bool single_tile(const GridDev& g, int tz, Tile& t, i
   return true;
 }
 
-// instance owning flattened item `gid` (prefix[q] <= gid < prefix[q+1])
-template <typename I>
-__device__ __forceinline__ int find_inst(const I* __restrict__ prefix, int n, I gid) {
-  int lo = 0, hi = n;  // prefix[lo] <= gid < prefix[hi]
-  if (gid < prefix[0] || gid >= prefix[n]) return -1;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (prefix[mid] <= gid) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 // ------------------------------------------------------------------ arithmetic
 __device__ __forceinline__ Real rsqrt_(Real x) {
   if constexpr (kF64) {
@@ -233,6 +221,16 @@ __device__ __forceinline__ Real psi_at(const GridDev& g, At P, Real ox, Real oy,
   const Real b0 = lerp(a00, a10, ty);
   const Real b1 = lerp(a01, a11, ty);
   return lerp(b0, b1, tz);
+}
+
+// Workgroup barrier that orders LDS only.  The stencil sweeps share data
+// between threads through LDS alone (global inputs come from earlier launches,
+// outputs are read by later ones), so their barriers need not wait for
+// outstanding global loads or stores, which stay in flight across them.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -436,16 +434,15 @@ __global__ void __launch_bounds__(256) k_fill_state(Fields<Real> F, GridDev g, B
 }
 
 // batched ghost fills: every instance's ghost range is padded to whole blocks
-// of 256, so a block belongs to one instance and finds it once
+// of 256, and a host-built map gives each block its (instance, first ghost)
 template <int kWhich>
 __global__ void __launch_bounds__(256) k_fill_batch(const Inst<Real>* __restrict__ tab,
-                                                    const long long* __restrict__ prefix, int n) {
-  const long long b0 = (long long)blockIdx.x * blockDim.x;
-  const int q = find_inst(prefix, n, b0);
-  if (q < 0) return;
-  const Inst<Real>& I = tab[q];
+                                                    const int2* __restrict__ map, int nblocks) {
+  if ((int)blockIdx.x >= nblocks) return;
+  const int2 w = map[blockIdx.x];
+  const Inst<Real>& I = tab[w.x];
   if (!I.ctrl->active) return;
-  const unsigned t = (unsigned)(b0 - prefix[q]) + threadIdx.x;
+  const unsigned t = (unsigned)w.y + threadIdx.x;
   if (kWhich == 0) fill_state_body(I.F, I.g, I.bc, I.ctrl, t);
   else if (kWhich == 1) fill_pred_body(I.F, I.g, I.bc, I.ctrl, t);
   else fill_corr_body(I.F, I.g, I.bc, I.ctrl, t);
@@ -611,7 +608,7 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
   load(T.z0);
   for (int k = T.z0; k < T.z1; ++k) {
     load(k + 1);
-    __syncthreads();
+    lds_barrier();
     if (in) {
       const int s0 = ring3(k), c0 = hidx(tx + 1, ty + 1);
       auto nb = [&](int ox, int oy, int oz) { return ring3(k + oz) * HP + hidx(tx + 1 + ox, ty + 1 + oy); };
@@ -733,7 +730,7 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
       auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
       F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -794,7 +791,7 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
   load(T.z0);
   for (int k = T.z0; k < T.z1; ++k) {
     load(k + 1);
-    __syncthreads();
+    lds_barrier();
     if (in) {
       const int s0 = ring3(k), c0 = hidx(tx + 1, ty + 1);
       auto nb = [&](int ox, int oy, int oz) { return ring3(k + oz) * HP + hidx(tx + 1 + ox, ty + 1 + oy); };
@@ -927,7 +924,7 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
 #pragma unroll
       for (int d = 0; d < 3; ++d) F.xt[d][c] = hx * xc[d] + qdt * (un[d] + ut[d]);
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -1026,18 +1023,13 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
 // Every x and y face of a plane is computed once and shared by its two cells
 // through LDS (2.2 face evaluations per cell and plane instead of 4); the z face
 // is carried in registers from one plane to the next.
-#ifndef CSPH_SHARE_FACES
-#define CSPH_SHARE_FACES 1
-#endif
-constexpr bool kShareFaces = CSPH_SHARE_FACES;
-constexpr int NFXS = kShareFaces ? NFX : 1, NFYS = kShareFaces ? NFY : 1;
 
 struct PlaneE {
   Real u[5][EP];      // U^n of the current plane, two-cell halo
   Real b[4][HP];      // m~, E~ of the current plane, one-cell halo
   Real xx[HP], xy[HP];
-  Real fx[5][NFXS];   // x-face fluxes of the tile row by row: face i+1/2, i = x0-1 .. x0+TX-1
-  Real fy[5][NFYS];   // y-face fluxes: face j+1/2, j = y0-1 .. y0+TY-1
+  Real fx[5][NFX];    // x-face fluxes of the tile row by row: face i+1/2, i = x0-1 .. x0+TX-1
+  Real fy[5][NFY];    // y-face fluxes: face j+1/2, j = y0-1 .. y0+TY-1
 };
 
 
@@ -1141,35 +1133,67 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
       for (int v = 0; v < 5; ++v) bq[0][v] = bq[1][v];
       xq[0] = xq[1];
     }
-    for (int k = T.z0; k < T.z1; ++k) {
-      const int dk = k - T.z0;
-      // current plane into LDS: U^n with a two-cell halo, bases and x/y offsets with one
-      for (int q = tid; q < EP; q += NT) {
+    // The current plane in LDS: U^n with a two-cell halo, the bases and x/y
+    // offsets with one.  In FP32 the next plane is copied global -> LDS by the
+    // DMA path of the vector memory unit (no registers held), issued once the
+    // x-y faces of the current plane are done and in flight during the cell
+    // updates; the barrier that ends the iteration waits for it.  Each wave
+    // stages 64 consecutive plane cells, which land at consecutive LDS words.
+    auto plane_load = [&](int k) {
+      const long long dz = (long long)k * g.sxy;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = tid + h * NT, qb = h * NT + (tid & ~(kWave - 1));
         const int ex = q % EX, ey = q / EX;
         const int ii = T.x0 - 2 + ex, jj = T.y0 - 2 + ey;
-        if (ii > g.nx + 1 || jj > g.ny + 1) continue;
-        const long long c = cell(g, ii, jj, k);
+        if (q < EP && ii <= g.nx + 1 && jj <= g.ny + 1) {
+          const long long c = cell(g, ii, jj, 0) + dz;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) S.u[v][q] = Un[v][c];
-      }
-      for (int q = tid; q < HP; q += NT) {
+          for (int v = 0; v < 5; ++v) {
+            if constexpr (kF64) {
+              S.u[v][q] = Un[v][c];
+            } else {
+              __builtin_amdgcn_global_load_lds(Un[v] + c, &S.u[v][qb], 4, 0, 0);
+            }
+          }
+        }
         const int hx = q % HX, hy = q / HX;
-        const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
-        if (ii > g.nx || jj > g.ny) continue;
-        const long long c = cell(g, ii, jj, k);
+        const int ib = T.x0 - 1 + hx, jb = T.y0 - 1 + hy;
+        if (q < HP && ib <= g.nx && jb <= g.ny) {
+          const long long c = cell(g, ib, jb, 0) + dz;
+          if constexpr (kF64) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) S.b[v][q] = F.mt[v][c];
-        S.xx[q] = F.xt[0][c];
-        S.xy[q] = F.xt[1][c];
+            for (int v = 0; v < 4; ++v) S.b[v][q] = F.mt[v][c];
+            S.xx[q] = F.xt[0][c];
+            S.xy[q] = F.xt[1][c];
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) __builtin_amdgcn_global_load_lds(F.mt[v] + c, &S.b[v][qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(F.xt[0] + c, &S.xx[qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(F.xt[1] + c, &S.xy[qb], 4, 0, 0);
+          }
+        }
       }
+    };
+    // FP64 loads each plane at the top of its iteration; FP32 has it in flight
+    // from the previous one
+    if constexpr (!kF64) {
+      plane_load(T.z0);
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first plane has landed
+    }
+    for (int k = T.z0; k < T.z1; ++k) {
+      const int dk = k - T.z0;
+      if constexpr (kF64) plane_load(k);
+      // own column for the z faces: base and z offset at k+1 (this plane's upper
+      // face) and U^n at k+3 (the next plane's); in flight during the x-y faces
+      Real unext[5];
       if (in) {
-        // base and z-offset of plane k+1 for the upper z face (global loads in flight
-        // while the x-y faces are computed)
         ld_base(dk + 1, bq[1]);
         xq[1] = F.xt[2][cell(g, i, j, k + 1)];
+        if (k + 1 < T.z1) ld_col(dk + 3, unext);
       }
-      __syncthreads();
-      if constexpr (kShareFaces) {
+      lds_barrier();
+      {
         // every x and y face of the tile once: x faces first, then y faces
 #pragma unroll 1
         for (int f = tid; f < NFX + NFY; f += NT) {
@@ -1187,40 +1211,37 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
             }
           }
         }
-        __syncthreads();
+        lds_barrier();
+      }
+      // x faces i+1/2 and i-1/2 of this cell (columns tx+1 and tx of its row) and
+      // y faces j+1/2, j-1/2 (the last LDS reads of the iteration); z faces:
+      // k+1/2 new (its column loads were issued at the top), k-1/2 carried from
+      // the previous plane
+      Real acc[5], Fp[5];
+      if (in) {
+        const int fxp = ty * (TX + 1) + tx + 1, fxm = fxp - 1;
+        const int fyp = (ty + 1) * TX + tx, fym = ty * TX + tx;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] = S.fx[v][fxp] - S.fx[v][fxm];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (S.fy[v][fyp] - S.fy[v][fym]);
+        face_flux(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
+        // advance the U^n column queue to k .. k+3 (its loads are complete)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          uq[v][0] = uq[v][1];
+          uq[v][1] = uq[v][2];
+          uq[v][2] = uq[v][3];
+          if (k + 1 < T.z1) uq[v][3] = unext[v];
+        }
+      }
+      // the plane buffers are free: start the next plane, which lands while the
+      // updates below (no LDS, no pending loads) are computed
+      if constexpr (!kF64) {
+        if (k + 1 < T.z1) plane_load(k + 1);
       }
       if (in) {
         const long long c = c0 + (long long)dk * g.sxy;
-        Real acc[5], Fp[5];
-        if constexpr (kShareFaces) {
-          // x faces i+1/2 and i-1/2 of this cell: columns tx+1 and tx of its row
-          const int fxp = ty * (TX + 1) + tx + 1, fxm = fxp - 1;
-          const int fyp = (ty + 1) * TX + tx, fym = ty * TX + tx;
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] = S.fx[v][fxp] - S.fx[v][fxm];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (S.fy[v][fyp] - S.fy[v][fym]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] = (Real)0;
-          // faces in the order x+, x-, y+, y-; each pair's difference joins the sum
-#pragma unroll 1
-          for (int f = 0; f < 4; ++f) {
-            const int axis = f >> 1, upper = (f & 1) == 0;
-            Real Fo[5];
-            tile_face(g, T, S, axis, (axis == 1 && upper) ? ty + 1 : ty,
-                      (axis == 0 && upper) ? tx + 1 : tx, dt, Fo);
-            if (upper) {
-#pragma unroll
-              for (int v = 0; v < 5; ++v) Fp[v] = Fo[v];
-            } else {
-#pragma unroll
-              for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fo[v]);
-            }
-          }
-        }
-        // z faces: k+1/2 new, k-1/2 carried from the previous plane
-        face_flux(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fz[v]);
         Real nv[5];
@@ -1234,24 +1255,18 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         }
         if ((double)nv[0] < -g.neg_tol) bad |= kBadNegDensity;
         if (!bad) smax = fmax(smax, signal_speed(g, nv[0], nv[1], nv[2], nv[3], nv[4]));
-        // advance the column queues to k+1
+        // advance the carried z face and the base queue to k+1
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           Fz[v] = Fp[v];
-          uq[v][0] = uq[v][1];
-          uq[v][1] = uq[v][2];
-          uq[v][2] = uq[v][3];
           bq[0][v] = bq[1][v];
         }
         xq[0] = xq[1];
-        if (k + 1 < T.z1) {
-          Real t[5];
-          ld_col(dk + 3, t);
-#pragma unroll
-          for (int v = 0; v < 5; ++v) uq[v][3] = t[v];
-        }
       }
-      __syncthreads();
+      // the next plane's LDS copy must have landed before the barrier (vmcnt(0);
+      // a workgroup barrier alone does not wait for global -> LDS transfers)
+      if constexpr (!kF64) __builtin_amdgcn_s_waitcnt(0x0F70);
+      lds_barrier();
     }
   }
   // block epilogue: FP64 totals to a per-block slot, max signal speed, flags
@@ -1259,14 +1274,14 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
 #pragma unroll
   for (int v = 0; v < 5; ++v) tot[v] = wave_sum(tot[v]);
   smax = wave_max(smax);
-  __syncthreads();
+  lds_barrier();
   if (bad) atomicOr(&redb, bad);
   if (lane == 0) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) red[v][w] = tot[v];
     red[5][w] = smax;
   }
-  __syncthreads();
+  lds_barrier();
   if (tid == 0) {
     double m = red[5][0];
     for (int q = 1; q < NT / kWave; ++q) m = fmax(m, red[5][q]);
@@ -1309,23 +1324,21 @@ __global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ct
   stage_e_body(F, g, ctrl, T, partials + (long long)id * 5);
 }
 
-// batched sweeps: workgroup -> (instance, tile) through the tile prefix; the XCD
-// inversion runs over the whole flattened list
+// batched sweeps: workgroup -> (instance, tile) through a host-built map of the
+// flattened tile list; the XCD inversion runs over the whole list
 template <int kStage>
 __global__ void __launch_bounds__(NT, 2) k_stage_batch(const Inst<Real>* __restrict__ tab,
-                                                       const int* __restrict__ prefix, int n) {
+                                                       const int2* __restrict__ map, int ntiles) {
   const int gid = xcd_tile(blockIdx.x, gridDim.x);
-  if (gid < 0) return;
-  const int q = find_inst(prefix, n, gid);
-  if (q < 0) return;
-  const Inst<Real>& I = tab[q];
+  if (gid < 0 || gid >= ntiles) return;
+  const int2 w = map[gid];
+  const Inst<Real>& I = tab[w.x];
   if (!I.ctrl->active) return;
   Tile T;
-  const int id = gid - prefix[q];
-  tile_at(I.g, I.tz, id, T);
+  tile_at(I.g, I.tz, w.y, T);
   if (kStage == 0) stage_p_body(I.F, I.g, I.ctrl, T);
   else if (kStage == 1) stage_c_body(I.F, I.g, I.ctrl, T);
-  else stage_e_body(I.F, I.g, I.ctrl, T, I.partials + (long long)id * 5);
+  else stage_e_body(I.F, I.g, I.ctrl, T, I.partials + (long long)w.y * 5);
 }
 
 // fixed-order sum of the per-block totals
@@ -1388,19 +1401,17 @@ long long Launch<Real>::ghosts(const GridDev& g) {
 }
 
 template <>
-hipError_t Launch<Real>::batch_step(const Inst<Real>* tab, const int* tile_prefix,
-                                    const long long* ghost_prefix, int n, int total_tiles,
-                                    long long total_ghosts, int* flags, hipStream_t s) {
+hipError_t Launch<Real>::batch_step(const Inst<Real>* tab, const int2* tile_map, const int2* fill_map,
+                                    int n, int total_tiles, int fill_blocks, int* flags, hipStream_t s) {
   const unsigned nb = (unsigned)((total_tiles + kXcd - 1) / kXcd * kXcd);
-  const unsigned gb = (unsigned)((total_ghosts + 255) / 256);
   const unsigned ib = (unsigned)((n + 63) / 64);
   k_begin_batch<<<ib, 64, 0, s>>>(tab, n);
-  k_fill_batch<0><<<gb, 256, 0, s>>>(tab, ghost_prefix, n);
-  k_stage_batch<0><<<nb, NT, 0, s>>>(tab, tile_prefix, n);
-  k_fill_batch<1><<<gb, 256, 0, s>>>(tab, ghost_prefix, n);
-  k_stage_batch<1><<<nb, NT, 0, s>>>(tab, tile_prefix, n);
-  k_fill_batch<2><<<gb, 256, 0, s>>>(tab, ghost_prefix, n);
-  k_stage_batch<2><<<nb, NT, 0, s>>>(tab, tile_prefix, n);
+  k_fill_batch<0><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
+  k_stage_batch<0><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  k_fill_batch<1><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
+  k_stage_batch<1><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  k_fill_batch<2><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
+  k_stage_batch<2><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
   k_end_batch<<<ib, 64, 0, s>>>(tab, n, flags);
   return hipGetLastError();
 }

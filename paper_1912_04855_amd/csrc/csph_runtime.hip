@@ -919,13 +919,13 @@ struct csph_batch {
   std::vector<Member> slots;
   // device table of the members in slot order (built on change)
   void* table = nullptr;
-  int* tile_prefix = nullptr;
-  long long* ghost_prefix = nullptr;
+  int2* tile_map = nullptr;   // flattened tile -> (table row, tile of that member)
+  int2* fill_map = nullptr;   // ghost-fill block -> (table row, first ghost cell)
   int* flags = nullptr;
-  size_t cap = 0;
+  size_t cap = 0, tile_cap = 0, fill_cap = 0;
   std::vector<int> order;  // table row -> slot
   int total_tiles = 0;
-  long long total_ghosts = 0;
+  int fill_blocks = 0;
   bool dirty = true;
   // a captured k-step graph, replayed while membership does not change
   hipGraph_t graph = nullptr;
@@ -944,25 +944,35 @@ void drop_graph(csph_batch* b) {
   b->graph_k = 0;
 }
 
+// grow a device array to at least `need` elements (contents not kept)
+template <typename T>
+csph_status ensure(T** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return CSPH_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  const size_t c = std::max<size_t>(64, 2 * need);
+  if (hipMalloc((void**)p, c * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *cap = 0;
+    return fail(CSPH_ERR_NOMEM, "batch table allocation failed");
+  }
+  *cap = c;
+  return CSPH_OK;
+}
+
 template <typename Real>
 csph_status build_table(csph_batch* b) {
   b->order.clear();
   for (size_t q = 0; q < b->slots.size(); ++q)
     if (b->slots[q].used) b->order.push_back((int)q);
   const size_t n = b->order.size();
-  if (n > b->cap) {
+  if (n > b->cap || !b->table) {
     if (b->table) (void)hipFree(b->table);
-    if (b->tile_prefix) (void)hipFree(b->tile_prefix);
-    if (b->ghost_prefix) (void)hipFree(b->ghost_prefix);
     if (b->flags) (void)hipFree(b->flags);
     b->table = nullptr;
-    b->tile_prefix = nullptr;
-    b->ghost_prefix = nullptr;
     b->flags = nullptr;
     size_t cap = std::max<size_t>(64, 2 * n);
     if (hipMalloc(&b->table, cap * sizeof(Inst<Real>)) != hipSuccess ||
-        hipMalloc((void**)&b->tile_prefix, (cap + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&b->ghost_prefix, (cap + 1) * sizeof(long long)) != hipSuccess ||
         hipMalloc((void**)&b->flags, cap * sizeof(int)) != hipSuccess) {
       (void)hipGetLastError();
       return fail(CSPH_ERR_NOMEM, "batch table allocation failed");
@@ -970,8 +980,7 @@ csph_status build_table(csph_batch* b) {
     b->cap = cap;
   }
   std::vector<Inst<Real>> tab(n);
-  std::vector<int> tp(n + 1, 0);
-  std::vector<long long> gp(n + 1, 0);
+  std::vector<int2> tmap, fmap;
   for (size_t r = 0; r < n; ++r) {
     csph_sim* s = b->slots[b->order[r]].sim;
     Inst<Real>& I = tab[r];
@@ -982,16 +991,22 @@ csph_status build_table(csph_batch* b) {
     I.partials = s->partials;
     I.tz = s->tz;
     s->tz_last = s->tz;
-    tp[r + 1] = tp[r] + Launch<Real>::tiles(s->g, s->tz);
-    // each member's ghost range padded to whole fill blocks (one instance per block)
-    gp[r + 1] = gp[r] + (Launch<Real>::ghosts(s->g) + 255) / 256 * 256;
+    const int nt = Launch<Real>::tiles(s->g, s->tz);
+    for (int t = 0; t < nt; ++t) tmap.push_back(make_int2((int)r, t));
+    // each member's ghost cells in whole fill blocks (one member per block)
+    const long long ng = Launch<Real>::ghosts(s->g);
+    for (long long g0 = 0; g0 < ng; g0 += 256) fmap.push_back(make_int2((int)r, (int)g0));
   }
-  b->total_tiles = tp[n];
-  b->total_ghosts = gp[n];
+  b->total_tiles = (int)tmap.size();
+  b->fill_blocks = (int)fmap.size();
+  csph_status st = ensure(&b->tile_map, &b->tile_cap, tmap.size());
+  if (!st) st = ensure(&b->fill_map, &b->fill_cap, fmap.size());
+  if (st) return st;
   if (n) {
     HIP_TRY(hipMemcpyAsync(b->table, tab.data(), n * sizeof(Inst<Real>), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->tile_prefix, tp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->ghost_prefix, gp.data(), (n + 1) * sizeof(long long), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(b->tile_map, tmap.data(), tmap.size() * sizeof(int2), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->fill_map, fmap.data(), fmap.size() * sizeof(int2), hipMemcpyHostToDevice,
                            b->stream));
     const std::vector<int> zero(n, 0);
     HIP_TRY(hipMemcpyAsync(b->flags, zero.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream));
@@ -1012,8 +1027,8 @@ csph_status batch_launch(csph_batch* b, int k) {
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int q = 0; q < k && e == hipSuccess; ++q)
-      e = Launch<Real>::batch_step((const Inst<Real>*)b->table, b->tile_prefix, b->ghost_prefix, n,
-                                   b->total_tiles, b->total_ghosts, b->flags, b->stream);
+      e = Launch<Real>::batch_step((const Inst<Real>*)b->table, b->tile_map, b->fill_map, n,
+                                   b->total_tiles, b->fill_blocks, b->flags, b->stream);
     hipGraph_t gr = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1236,8 +1251,8 @@ csph_status csph_batch_destroy(csph_batch* b) {
     }
   drop_graph(b);
   if (b->table) (void)hipFree(b->table);
-  if (b->tile_prefix) (void)hipFree(b->tile_prefix);
-  if (b->ghost_prefix) (void)hipFree(b->ghost_prefix);
+  if (b->tile_map) (void)hipFree(b->tile_map);
+  if (b->fill_map) (void)hipFree(b->fill_map);
   if (b->flags) (void)hipFree(b->flags);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
