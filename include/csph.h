@@ -52,6 +52,21 @@ enum {
 typedef enum { CSPH_F32 = 0, CSPH_F64 = 1 } csph_dtype;
 typedef enum { CSPH_PERIODIC = 0, CSPH_OUTFLOW = 1, CSPH_INFLOW = 2, CSPH_REFLECT = 3 } csph_bc;
 typedef enum { CSPH_CONSERVED = 0, CSPH_PRIMITIVE = 1 } csph_vars;
+/* Eulerian-stage options (Sec. 2.2 leaves the TVD limiter and the Riemann-solver
+ * style flux open; Sec. 4 lists them as options).  Slopes are limited from the
+ * forward and backward differences a, b of U^n:
+ *   MINMOD    0 if ab <= 0, else sign(a) min(|a|, |b|)              (default)
+ *   MC        0 if ab <= 0, else sign(a) min(2|a|, 2|b|, (|a|+|b|)/2)
+ *   VANLEER   0 if ab <= 0, else 2ab/(a+b)
+ *   SUPERBEE  0 if ab <= 0, else sign(a) max(min(2|a|,|b|), min(|a|,2|b|))
+ * Face flux (times dt) from the reconstructed states U^L, U^R and the particle
+ * offsets xi_L, xi_R along the face normal:
+ *   SWEPT     max(xi_L,0) U^L + min(xi_R,0) U^R (HLL with the advective speeds)
+ *   LF        (xi_L U^L + xi_R U^R)/2 - max(|xi_L|,|xi_R|)(U^R - U^L)/2
+ *   SWEPT_AV  SWEPT plus the acoustic (Rusanov) damping of the face velocity
+ *             jump, which vanishes for a gas at rest and for uniform flow (default) */
+typedef enum { CSPH_LIM_MINMOD = 0, CSPH_LIM_MC = 1, CSPH_LIM_VANLEER = 2, CSPH_LIM_SUPERBEE = 3 } csph_limiter;
+typedef enum { CSPH_FLUX_SWEPT = 0, CSPH_FLUX_LF = 1, CSPH_FLUX_SWEPT_AV = 2 } csph_flux;
 
 /* Grid and gas.  One spacing h on all three axes (Sec. 2.2: x_i = x_{i-1} + h,
  * likewise y and z).  nx, ny, nz >= 4; h > 0; gamma > 1; 0 < cfl <= 0.5;
@@ -148,6 +163,12 @@ const char* csph_last_error(void);
  * begin/end bookkeeping launches.  n is the capacity of both arrays (<= 5). */
 csph_status csph_profile_enable(csph_sim* sim, int32_t on);
 csph_status csph_profile_read(csph_sim* sim, double* avg_ms, int64_t* launches, int32_t n);
+
+/* Choose the Eulerian-stage limiter and flux (see csph_limiter / csph_flux);
+ * applies from the next step.  CSPH_ERR_ARG for unknown values or a batch
+ * member.  csph_get_scheme returns the current pair (either pointer may be NULL). */
+csph_status csph_set_scheme(csph_sim* sim, csph_limiter limiter, csph_flux flux);
+csph_status csph_get_scheme(const csph_sim* sim, int32_t* limiter, int32_t* flux);
 
 /* Tile depth: the stencil sweeps give each workgroup a 32 x 8 tile of an x-y
  * plane and march it through tz planes along z.  Deeper tiles reuse more of the

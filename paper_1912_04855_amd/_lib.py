@@ -15,6 +15,8 @@ OK, ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_NONFINITE, ERR_NEG_DENSITY, E
 F32, F64 = 0, 1
 PERIODIC, OUTFLOW, INFLOW, REFLECT = 0, 1, 2, 3
 CONSERVED, PRIMITIVE = 0, 1
+LIM_MINMOD, LIM_MC, LIM_VANLEER, LIM_SUPERBEE = 0, 1, 2, 3
+FLUX_SWEPT, FLUX_LF, FLUX_SWEPT_AV = 0, 1, 2
 
 STATUS_NAMES = {0: "CSPH_OK", 1: "CSPH_ERR_ARG", 2: "CSPH_ERR_NOMEM", 3: "CSPH_ERR_DEVICE",
                 4: "CSPH_ERR_STATE", 5: "CSPH_ERR_NONFINITE", 6: "CSPH_ERR_NEG_DENSITY",
@@ -28,7 +30,7 @@ EXPORTS = [
     "csph_last_error", "csph_batch_create", "csph_batch_add", "csph_batch_advance",
     "csph_batch_poll", "csph_batch_remove", "csph_batch_destroy", "csph_profile_enable",
     "csph_profile_read", "csph_set_tile_depth", "csph_get_tile_depth", "csph_autotune",
-    "csph_batch_autotune",
+    "csph_batch_autotune", "csph_set_scheme", "csph_get_scheme",
 ]
 
 
@@ -86,6 +88,8 @@ def load():
         "csph_get_tile_depth": (st, [vp, C.POINTER(C.c_int32)]),
         "csph_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
         "csph_batch_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
+        "csph_set_scheme": (st, [vp, C.c_int32, C.c_int32]),
+        "csph_get_scheme": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -41,7 +41,17 @@ struct GridDev {
   double klat[13][3];
   // -h o for the same 13 offsets (the lattice part of a pair separation)
   double hoff[13][3];
+  // Eulerian-stage scheme: TVD limiter and face flux (kLim*, kFlux*)
+  int limiter, flux;
 };
+
+enum : int { kLimMinmod = 0, kLimMC = 1, kLimVanLeer = 2, kLimSuperbee = 3 };
+enum : int { kFluxSwept = 0, kFluxLF = 1, kFluxSweptAV = 2 };
+
+// the default scheme runs the specialised stage-E kernel; others the generic one
+inline __host__ __device__ bool default_scheme(const GridDev& g) {
+  return g.limiter == kLimMinmod && g.flux == kFluxSweptAV;
+}
 
 struct BcDev {
   int kind[6];
@@ -114,9 +124,10 @@ struct Launch {
                          hipEvent_t* ev);
   // one step of every active member of a batch, one launch per stage
   // tile_map[t] = (member, tile of that member); fill_map[b] = (member, first
-  // ghost cell of fill block b)
+  // ghost cell of fill block b); generic: some member uses a non-default scheme
   static hipError_t batch_step(const Inst<Real>* tab, const int2* tile_map, const int2* fill_map,
-                               int n, int total_tiles, int fill_blocks, int* flags, hipStream_t s);
+                               int n, int total_tiles, int fill_blocks, int* flags, bool generic,
+                               hipStream_t s);
   static int tiles(const GridDev& g, int tz);
   static int default_tz(const GridDev& g);
   static long long ghosts(const GridDev& g);

@@ -953,14 +953,57 @@ __device__ __forceinline__ void acoustic_dissipation(const GridDev& g, int axis,
   D[4] = (Real)0.5 * ((uL[0] + uR[0]) * D[1] + (uL[1] + uR[1]) * D[2] + (uL[2] + uR[2]) * D[3]);
 }
 
+// TVD limiter of the slope from the forward and backward differences a, b
+// (undivided): minmod, MC, van Leer or superbee (the scheme lists the limiter
+// as a free option, Sec. 4).
+__device__ __forceinline__ Real limit(int kind, Real a, Real b) {
+  if (a * b <= (Real)0) return (Real)0;
+  const Real sg = a > (Real)0 ? (Real)1 : (Real)-1;
+  const Real aa = fabs(a), ab = fabs(b);
+  if (kind == kLimMC) {
+    const Real m = fmin((Real)2 * aa, (Real)2 * ab);
+    return sg * fmin(m, (Real)0.5 * (aa + ab));
+  }
+  if (kind == kLimVanLeer) return (Real)2 * a * b / (a + b);
+  if (kind == kLimSuperbee) return sg * fmax(fmin((Real)2 * aa, ab), fmin(aa, (Real)2 * ab));
+  return sg * fmin(aa, ab);
+}
+
 // Swept content of one face (Eq. (8) shifted reconstruction, HLL with the
 // advective speeds = max(xi_L,0) U^L + min(xi_R,0) U^R, plus the damping).
+// kGen: the limiter and flux of the grid's scheme (g.limiter, g.flux) instead of
+// the default minmod + swept volume with damping.
 // u4[v][0..3]: component v of U^n at cells L-1, L, L+1 (= R), R+1;
 // bL, bR: post-Lagrange bases of L and R; xL, xR: particle offsets along axis.
+template <bool kGen>
 __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real u4[5][4],
                                           const Real bL[5], const Real bR[5], Real xL, Real xR,
                                           Real dt, Real Fo[5]) {
-  if constexpr (kF64) {
+  if constexpr (kGen) {
+    const Real nuL = xL * (Real)g.inv_h;
+    const Real nuR = xR * (Real)g.inv_h;
+    Real UL[5], UR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const Real sL = limit(g.limiter, u4[v][2] - u4[v][1], u4[v][1] - u4[v][0]);
+      const Real sR = limit(g.limiter, u4[v][3] - u4[v][2], u4[v][2] - u4[v][1]);
+      UL[v] = bL[v] + (Real)0.5 * ((Real)1 - nuL) * sL;
+      UR[v] = bR[v] - (Real)0.5 * ((Real)1 + nuR) * sR;
+      if (g.flux == kFluxLF) {
+        // Lax-Friedrichs with the advective speeds xi/dt (times dt)
+        const Real a = fmax(fabs(xL), fabs(xR));
+        Fo[v] = (Real)0.5 * (xL * UL[v] + xR * UR[v]) - (Real)0.5 * a * (UR[v] - UL[v]);
+      } else {
+        Fo[v] = fmax(xL, (Real)0) * UL[v] + fmin(xR, (Real)0) * UR[v];
+      }
+    }
+    if (g.flux == kFluxSweptAV) {
+      Real D[5];
+      acoustic_dissipation(g, axis, UL, UR, D);
+#pragma unroll
+      for (int v = 1; v < 5; ++v) Fo[v] = Fo[v] + dt * D[v];
+    }
+  } else if constexpr (kF64) {
     const Real nuL = xL * (Real)g.inv_h;
     const Real nuR = xR * (Real)g.inv_h;
     Real UL[5], UR[5];
@@ -1035,6 +1078,7 @@ struct PlaneE {
 
 __device__ __forceinline__ int eidx(int ex, int ey) { return ey * EX + ex; }
 
+template <bool kGen>
 __device__ __forceinline__ bool tile_face(const GridDev& g, const Tile& T, const PlaneE& S,
                                           int axis, int row, int col, Real dt, Real Fo[5]) {
   Real u4[5][4], bl[5], br[5];
@@ -1067,10 +1111,11 @@ __device__ __forceinline__ bool tile_face(const GridDev& g, const Tile& T, const
   }
   const Real xl = axis == 0 ? S.xx[hl] : S.xy[hl];
   const Real xr = axis == 0 ? S.xx[hr] : S.xy[hr];
-  face_flux(g, axis, u4, bl, br, xl, xr, dt, Fo);
+  face_flux<kGen>(g, axis, u4, bl, br, xl, xr, dt, Fo);
   return true;
 }
 
+template <bool kGen>
 __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
                                              const Tile& T, double* __restrict__ slot) {
   const bool have = true;
@@ -1118,7 +1163,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
       ld_base(0, bq[1]);
       xq[0] = F.xt[2][c0 - g.sxy];
       xq[1] = F.xt[2][c0];
-      face_flux(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fz);
+      face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fz);
       // shift so that uq holds U^n at z0-1 .. z0+2
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -1199,13 +1244,13 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         for (int f = tid; f < NFX + NFY; f += NT) {
           Real Fo[5];
           if (f < NFX) {
-            if (tile_face(g, T, S, 0, f / (TX + 1), f % (TX + 1), dt, Fo)) {
+            if (tile_face<kGen>(g, T, S, 0, f / (TX + 1), f % (TX + 1), dt, Fo)) {
 #pragma unroll
               for (int v = 0; v < 5; ++v) S.fx[v][f] = Fo[v];
             }
           } else {
             const int fy = f - NFX;
-            if (tile_face(g, T, S, 1, fy / TX, fy % TX, dt, Fo)) {
+            if (tile_face<kGen>(g, T, S, 1, fy / TX, fy % TX, dt, Fo)) {
 #pragma unroll
               for (int v = 0; v < 5; ++v) S.fy[v][fy] = Fo[v];
             }
@@ -1225,7 +1270,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         for (int v = 0; v < 5; ++v) acc[v] = S.fx[v][fxp] - S.fx[v][fxm];
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (S.fy[v][fyp] - S.fy[v][fym]);
-        face_flux(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
+        face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
         // advance the U^n column queue to k .. k+3 (its loads are complete)
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -1315,18 +1360,19 @@ __global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g,
   stage_c_body(F, g, ctrl, T);
 }
 
+template <bool kGen>
 __global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ctrl* ctrl,
                                                    double* __restrict__ partials, int tz) {
   if (!ctrl->active) return;
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  stage_e_body(F, g, ctrl, T, partials + (long long)id * 5);
+  stage_e_body<kGen>(F, g, ctrl, T, partials + (long long)id * 5);
 }
 
 // batched sweeps: workgroup -> (instance, tile) through a host-built map of the
 // flattened tile list; the XCD inversion runs over the whole list
-template <int kStage>
+template <int kStage, bool kGen>
 __global__ void __launch_bounds__(NT, 2) k_stage_batch(const Inst<Real>* __restrict__ tab,
                                                        const int2* __restrict__ map, int ntiles) {
   const int gid = xcd_tile(blockIdx.x, gridDim.x);
@@ -1338,7 +1384,10 @@ __global__ void __launch_bounds__(NT, 2) k_stage_batch(const Inst<Real>* __restr
   tile_at(I.g, I.tz, w.y, T);
   if (kStage == 0) stage_p_body(I.F, I.g, I.ctrl, T);
   else if (kStage == 1) stage_c_body(I.F, I.g, I.ctrl, T);
-  else stage_e_body(I.F, I.g, I.ctrl, T, I.partials + (long long)w.y * 5);
+  else if (!kGen || default_scheme(I.g))
+    stage_e_body<false>(I.F, I.g, I.ctrl, T, I.partials + (long long)w.y * 5);
+  else
+    stage_e_body<true>(I.F, I.g, I.ctrl, T, I.partials + (long long)w.y * 5);
 }
 
 // fixed-order sum of the per-block totals
@@ -1402,16 +1451,20 @@ long long Launch<Real>::ghosts(const GridDev& g) {
 
 template <>
 hipError_t Launch<Real>::batch_step(const Inst<Real>* tab, const int2* tile_map, const int2* fill_map,
-                                    int n, int total_tiles, int fill_blocks, int* flags, hipStream_t s) {
+                                    int n, int total_tiles, int fill_blocks, int* flags, bool generic,
+                                    hipStream_t s) {
   const unsigned nb = (unsigned)((total_tiles + kXcd - 1) / kXcd * kXcd);
   const unsigned ib = (unsigned)((n + 63) / 64);
   k_begin_batch<<<ib, 64, 0, s>>>(tab, n);
   k_fill_batch<0><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
-  k_stage_batch<0><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  k_stage_batch<0, false><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
   k_fill_batch<1><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
-  k_stage_batch<1><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  k_stage_batch<1, false><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
   k_fill_batch<2><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
-  k_stage_batch<2><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  if (generic)
+    k_stage_batch<2, true><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  else
+    k_stage_batch<2, false><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
   k_end_batch<<<ib, 64, 0, s>>>(tab, n, flags);
   return hipGetLastError();
 }
@@ -1465,7 +1518,10 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   mark(4);
   k_fill_corr<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(5);
-  k_stage_e<<<nb, NT, 0, s>>>(F, g, ctrl, partials, tz);
+  if (default_scheme(g))
+    k_stage_e<false><<<nb, NT, 0, s>>>(F, g, ctrl, partials, tz);
+  else
+    k_stage_e<true><<<nb, NT, 0, s>>>(F, g, ctrl, partials, tz);
   mark(6);
   k_end<<<1, 64, 0, s>>>(ctrl);
   mark(7);

@@ -155,6 +155,8 @@ GridDev make_grid(const csph_grid_desc* d) {
     g.hoff[q][1] = dy;
     g.hoff[q][2] = dz;
   }
+  g.limiter = kLimMinmod;
+  g.flux = kFluxSweptAV;
   return g;
 }
 
@@ -739,6 +741,23 @@ csph_status csph_profile_read(csph_sim* s, double* avg_ms, int64_t* launches, in
   return CSPH_OK;
 }
 
+csph_status csph_set_scheme(csph_sim* s, csph_limiter limiter, csph_flux flux) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (limiter < CSPH_LIM_MINMOD || limiter > CSPH_LIM_SUPERBEE) return fail(CSPH_ERR_ARG, "bad limiter");
+  if (flux < CSPH_FLUX_SWEPT || flux > CSPH_FLUX_SWEPT_AV) return fail(CSPH_ERR_ARG, "bad flux");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
+  s->g.limiter = (int)limiter;
+  s->g.flux = (int)flux;
+  return CSPH_OK;
+}
+
+csph_status csph_get_scheme(const csph_sim* s, int32_t* limiter, int32_t* flux) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (limiter) *limiter = s->g.limiter;
+  if (flux) *flux = s->g.flux;
+  return CSPH_OK;
+}
+
 csph_status csph_set_tile_depth(csph_sim* s, int32_t tz) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
   if (tz < kTzMin || tz > kTzMax) return fail(CSPH_ERR_ARG, "tile depth must be in [2, 64]");
@@ -926,6 +945,7 @@ struct csph_batch {
   std::vector<int> order;  // table row -> slot
   int total_tiles = 0;
   int fill_blocks = 0;
+  bool generic = false;  // a member uses a non-default scheme (generic stage-E kernel)
   bool dirty = true;
   // a captured k-step graph, replayed while membership does not change
   hipGraph_t graph = nullptr;
@@ -981,6 +1001,7 @@ csph_status build_table(csph_batch* b) {
   }
   std::vector<Inst<Real>> tab(n);
   std::vector<int2> tmap, fmap;
+  b->generic = false;
   for (size_t r = 0; r < n; ++r) {
     csph_sim* s = b->slots[b->order[r]].sim;
     Inst<Real>& I = tab[r];
@@ -991,6 +1012,7 @@ csph_status build_table(csph_batch* b) {
     I.partials = s->partials;
     I.tz = s->tz;
     s->tz_last = s->tz;
+    if (!default_scheme(s->g)) b->generic = true;
     const int nt = Launch<Real>::tiles(s->g, s->tz);
     for (int t = 0; t < nt; ++t) tmap.push_back(make_int2((int)r, t));
     // each member's ghost cells in whole fill blocks (one member per block)
@@ -1028,7 +1050,7 @@ csph_status batch_launch(csph_batch* b, int k) {
     hipError_t e = hipSuccess;
     for (int q = 0; q < k && e == hipSuccess; ++q)
       e = Launch<Real>::batch_step((const Inst<Real>*)b->table, b->tile_map, b->fill_map, n,
-                                   b->total_tiles, b->fill_blocks, b->flags, b->stream);
+                                   b->total_tiles, b->fill_blocks, b->flags, b->generic, b->stream);
     hipGraph_t gr = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
     if (e != hipSuccess || e2 != hipSuccess) {

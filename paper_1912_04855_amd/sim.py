@@ -176,6 +176,16 @@ class Sim:
         check(_lib.load().csph_profile_read(self._h, _ptr(ms), _ptr(n), 5), "csph_profile_read")
         return {g: (float(ms[q]), int(n[q])) for q, g in enumerate(self.PROFILE_GROUPS)}
 
+    # ------------------------------------------------------------------ scheme
+    def set_scheme(self, limiter=_lib.LIM_MINMOD, flux=_lib.FLUX_SWEPT_AV):
+        """TVD limiter and face flux of the Eulerian stage (``_lib.LIM_*``, ``_lib.FLUX_*``)."""
+        check(_lib.load().csph_set_scheme(self._h, int(limiter), int(flux)), "csph_set_scheme")
+
+    def scheme(self):
+        lim, flux = C.c_int32(), C.c_int32()
+        check(_lib.load().csph_get_scheme(self._h, C.byref(lim), C.byref(flux)), "csph_get_scheme")
+        return lim.value, flux.value
+
     # ------------------------------------------------------------------ tiling
     @property
     def tile_depth(self) -> int:
