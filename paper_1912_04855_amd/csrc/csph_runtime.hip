@@ -393,12 +393,8 @@ csph_status init_sim(csph_sim* s) {
   s->ctrl = (Ctrl*)(s->buf + s->L.ctrl_off);
   s->partials = (double*)(s->buf + s->L.partials_off);
   s->totals_dev = (double*)(s->buf + s->L.totals_off);
-  // zero fields (psi = 0, state = 0) and the control block
-  std::vector<char> zeros(std::min<size_t>(s->L.total, (size_t)64 << 20), 0);
-  for (size_t off = 0; off < s->L.total; off += zeros.size()) {
-    const size_t n = std::min(zeros.size(), s->L.total - off);
-    HIP_TRY(hipMemcpyAsync(s->buf + off, zeros.data(), n, hipMemcpyHostToDevice, s->stream));
-  }
+  // zero fields (psi = 0, state = 0) and the control block, on the device
+  HIP_TRY(hipMemsetAsync(s->buf, 0, s->L.total, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return CSPH_OK;
 }

@@ -5,7 +5,9 @@ Each is admitted as soon as the device-memory budget allows, as a new member of
 the running batch of its dtype: its state stays resident on the device, and it
 advances together with whatever else is in flight (one launch per stage for the
 whole batch, two batches -- FP32 and FP64 -- on two streams).  Finished members
-are read back, removed and freed, which makes room for waiting requests.
+are read back, removed and freed, which makes room for waiting requests.  Host
+work per request (building the initial state, reading the result) runs on
+worker threads so that it overlaps the device work of the others.
 Latency is measured from arrival to the result being on the host.
 """
 import math
@@ -28,8 +30,9 @@ class Record:
     steps: int
     cells: int
     arrival: float
-    admitted: float = 0.0
-    finished: float = 0.0
+    admitted: float = 0.0     # initial state on the device, joined its batch
+    done: float = 0.0         # last step finished on the device
+    finished: float = 0.0     # result on the host
     state: Optional[np.ndarray] = None
 
     @property
@@ -47,8 +50,16 @@ class ServeStats:
     def summary(self):
         lat = np.array([r.latency for r in self.records])
         work = sum(r.cells * r.steps for r in self.records)
+        def mean(xs):
+            return float(np.mean(xs)) if len(xs) else None
+
         return {
             "requests": len(self.records),
+            # where the time goes, mean per request: building the initial state on the
+            # device (from arrival), stepping in the batch, reading the result back
+            "mean_build_s": mean([r.admitted - r.arrival for r in self.records]),
+            "mean_device_s": mean([r.done - r.admitted for r in self.records]),
+            "mean_readback_s": mean([r.finished - r.done for r in self.records]),
             "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "mean_s": float(lat.mean()) if len(lat) else None,
@@ -59,40 +70,83 @@ class ServeStats:
         }
 
 
+def _build(problem, req):
+    """Initial state of one request on the device (runs on a worker thread)."""
+    pr = problem(req)
+    sim = from_problem(pr, dtype=req.dtype)
+    return pr.cells, sim
+
+
+def _read(sim, keep):
+    """Result of a finished request to the host, then free it (worker thread)."""
+    st = sim.conserved()
+    sim.close()
+    return st if keep else None
+
+
 def serve(requests, budget_bytes=64 << 30, k_steps=8, keep_states=False, problem=None,
-          clock=time.perf_counter, log=None) -> ServeStats:
-    """Run the request stream ``requests`` (``problems.Request``, arrival-ordered)."""
+          clock=time.perf_counter, log=None, workers=4) -> ServeStats:
+    """Run the request stream ``requests`` (``problems.Request``, arrival-ordered).
+
+    The loop thread only admits, advances and polls.  Building a request's
+    initial state on the device and reading a finished result back run on
+    ``workers`` threads, so the GPU keeps advancing the batch meanwhile.  Device
+    memory is reserved against the budget when a request is handed to a worker
+    and released when its result has been read back."""
+    from concurrent.futures import ThreadPoolExecutor
+
     problem = problem or P.serve_problem
     pending = sorted(requests, key=lambda r: r.arrival)
     batches: Dict[str, Batch] = {"f32": Batch("f32"), "f64": Batch("f64")}
     active: Dict[tuple, tuple] = {}  # (dtype, slot) -> (record, sim, bytes)
+    building: List[tuple] = []       # (record, future, bytes), arrival order
+    reading: List[tuple] = []        # (record, future, bytes)
     used = 0
     stats = ServeStats()
+    pool = ThreadPoolExecutor(max_workers=workers)
     t0 = clock()
     qi = 0
     try:
-        while qi < len(pending) or active:
+        while qi < len(pending) or active or building or reading:
             now = clock() - t0
-            # admit every arrived request the memory budget allows, in arrival order
+            # hand arrived requests to the workers while the memory budget allows
             while qi < len(pending) and pending[qi].arrival <= now:
                 req = pending[qi]
-                pr = problem(req)
-                need = required_bytes(pr.shape, pr.h, dtype=req.dtype, gamma=pr.gamma,
-                                      cfl=pr.cfl, rho_vac=pr.rho_vac)
-                if used + need > budget_bytes and active:
+                e = req.edge
+                need = required_bytes((e, e, e), 1.0 / e, dtype=req.dtype)
+                if used + need > budget_bytes and (active or building or reading):
                     break
-                sim = from_problem(pr, dtype=req.dtype)
-                slot = batches[req.dtype].add(sim, req.steps)
-                rec = Record(req.rid, req.kind, req.dtype, req.edge, req.steps, pr.cells,
-                             req.arrival, admitted=clock() - t0)
-                active[(req.dtype, slot)] = (rec, sim, need)
+                rec = Record(req.rid, req.kind, req.dtype, req.edge, req.steps, 0, req.arrival)
+                building.append((rec, pool.submit(_build, problem, req), need))
                 used += need
                 stats.peak_bytes = max(stats.peak_bytes, used)
-                stats.peak_members = max(stats.peak_members, len(active))
                 qi += 1
+            # members whose state is on the device join their batch, in arrival order
+            while building and building[0][1].done():
+                rec, fut, need = building.pop(0)
+                rec.cells, sim = fut.result()
+                slot = batches[rec.dtype].add(sim, rec.steps)
+                rec.admitted = clock() - t0
+                active[(rec.dtype, slot)] = (rec, sim, need)
+                stats.peak_members = max(stats.peak_members, len(active))
+            # results read back: the request is complete
+            still = []
+            for rec, fut, need in reading:
+                if fut.done():
+                    rec.state = fut.result()
+                    rec.finished = clock() - t0
+                    used -= need
+                    stats.records.append(rec)
+                    if log:
+                        log(f"[serve] request {rec.rid} {rec.kind} {rec.edge}^3 {rec.dtype} "
+                            f"{rec.steps} steps: {rec.latency * 1e3:.1f} ms")
+                else:
+                    still.append((rec, fut, need))
+            reading = still
             if not active:
-                if qi < len(pending):
-                    time.sleep(max(0.0, min(0.05, pending[qi].arrival - (clock() - t0))))
+                time.sleep(0.002 if (building or reading) else
+                           max(0.0, min(0.05, pending[qi].arrival - (clock() - t0)))
+                           if qi < len(pending) else 0.002)
                 continue
             # one graph replay of k steps per batch; the two batches run on their own
             # streams, so their work overlaps on the device
@@ -105,17 +159,10 @@ def serve(requests, budget_bytes=64 << 30, k_steps=8, keep_states=False, problem
                 for slot in b.poll():
                     rec, sim, need = active.pop((dt, slot))
                     b.remove(slot)
-                    st = sim.conserved()
-                    rec.finished = clock() - t0
-                    if keep_states:
-                        rec.state = st
-                    sim.close()
-                    used -= need
-                    stats.records.append(rec)
-                    if log:
-                        log(f"[serve] request {rec.rid} {rec.kind} {rec.edge}^3 {rec.dtype} "
-                            f"{rec.steps} steps: {rec.latency * 1e3:.1f} ms")
+                    rec.done = clock() - t0
+                    reading.append((rec, pool.submit(_read, sim, keep_states), need))
     finally:
+        pool.shutdown(wait=True)
         for b in batches.values():
             b.close()
     stats.wall_s = clock() - t0
