@@ -111,7 +111,8 @@ struct FillSet {
 // launchers, instantiated for float and double by the kernel translation units
 template <typename Real>
 struct Launch {
-  static hipError_t fill_state(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+  // every ghost cell of U[par] (all zones): after a new state or new boundaries
+  static hipError_t fill_state(const Fields<Real>& F, const GridDev& g, const BcDev& bc, int par,
                                Ctrl* ctrl, hipStream_t s);
   static hipError_t fill_psi(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                              Ctrl* ctrl, hipStream_t s);

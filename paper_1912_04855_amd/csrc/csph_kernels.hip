@@ -52,6 +52,9 @@ namespace CSPH_TAG {
 using Real = CSPH_REAL;
 using Acc = double;
 constexpr bool kF64 = std::is_same<Real, double>::value;
+// The FP32 build pushes the x-face ghost cells from the stage that writes a
+// field; the FP64 build fills every ghost zone in the fill kernels.
+constexpr bool kPushX = !kF64;
 
 constexpr int kWave = 64;
 constexpr int kXcd = 8;
@@ -360,6 +363,10 @@ __device__ __forceinline__ void fill_body(const FillSet<Real>& fs, const GridDev
   }
 }
 
+__device__ __forceinline__ bool in_x_zone(const GridDev& g, unsigned t) {
+  return t >= 4u * (unsigned)g.sx * (unsigned)g.sy + (unsigned)g.nz * 4u * (unsigned)g.sx;
+}
+
 // ghosts of the predicted particles, then psi at their displaced positions for
 // the first ghost layer (the corrector reads psi* of index neighbours only)
 __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
@@ -368,14 +375,21 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
   if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
-  const GhostSrc m = ghost_src(g, bc, i, j, k, false);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) F.ms[q][cg] = ghost_get(bc, m, F.ms[q], kMx + q, dt);
   Real xi[3];
+  if (kPushX && in_x_zone(g, t)) {
+    // stage P wrote this x ghost's state and offset; psi at its position is left
+    if (i != -1 && i != g.nx) return;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    xi[q] = ghost_get(bc, m, F.xs[q], kXx + q, dt);
-    F.xs[q][cg] = xi[q];
+    for (int q = 0; q < 3; ++q) xi[q] = F.xs[q][cg];
+  } else {
+    const GhostSrc m = ghost_src(g, bc, i, j, k, false);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) F.ms[q][cg] = ghost_get(bc, m, F.ms[q], kMx + q, dt);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      xi[q] = ghost_get(bc, m, F.xs[q], kXx + q, dt);
+      F.xs[q][cg] = xi[q];
+    }
   }
   if (i >= -1 && i <= g.nx && j >= -1 && j <= g.ny && k >= -1 && k <= g.nz) {
     const Real* P = F.psi;
@@ -389,6 +403,7 @@ __device__ __forceinline__ void fill_corr_body(const Fields<Real>& F, const Grid
                                                const Ctrl* ctrl, unsigned t) {
   int i, j, k;
   if (!ghost_cell(g, t, i, j, k)) return;
+  if (kPushX && in_x_zone(g, t)) return;  // written by stage C
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
   const GhostSrc m = ghost_src(g, bc, i, j, k, false);
@@ -402,6 +417,7 @@ __device__ __forceinline__ void fill_state_body(const Fields<Real>& F, const Gri
                                                 const Ctrl* ctrl, unsigned t) {
   int i, j, k;
   if (!ghost_cell(g, t, i, j, k)) return;
+  if (kPushX && in_x_zone(g, t)) return;  // written by stage E of the previous step
   const int par = ctrl->par;
   const long long cg = cell(g, i, j, k);
   const GhostSrc m = ghost_src(g, bc, i, j, k, false);
@@ -446,6 +462,34 @@ __global__ void __launch_bounds__(256) k_fill_batch(const Inst<Real>* __restrict
   if (kWhich == 0) fill_state_body(I.F, I.g, I.bc, I.ctrl, t);
   else if (kWhich == 1) fill_pred_body(I.F, I.g, I.bc, I.ctrl, t);
   else fill_corr_body(I.F, I.g, I.bc, I.ctrl, t);
+}
+
+// Ghost columns of the x faces written by the stage that produces a field:
+// interior cell i of an interior row calls put(gi, flip, face) for every ghost
+// column gi at depth 1..D whose rule reads it (periodic wrap, outflow copy,
+// reflect mirror -- flip: the x components change sign); at an inflow face the
+// boundary cell writes the face's Dirichlet state (face >= 0).  Together with the
+// y and z ghost zones, which the fill kernels still compute (their rows are
+// contiguous, the x ghosts are not), this gives every ghost the value of the
+// rules in x, y, z order.
+template <int D, typename Put>
+__device__ __forceinline__ void x_push(const GridDev& g, const BcDev& bc, int i, Put&& put) {
+  const int n = g.nx, kl = bc.kind[0], ku = bc.kind[1];
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    const int sl = kl == kPeriodic ? n - d : (kl == kReflect ? d - 1 : 0);
+    if (sl == i) put(-d, kl == kReflect, kl == kInflow ? 0 : -1);
+    const int su = ku == kPeriodic ? d - 1 : (ku == kReflect ? n - d : n - 1);
+    if (su == i) put(n - 1 + d, ku == kReflect, ku == kInflow ? 1 : -1);
+  }
+}
+
+// value of a pushed x ghost: the cell's own value v (sign-flipped for the x
+// components at a reflecting face) or the inflow face's state
+__device__ __forceinline__ Real x_ghost_value(const BcDev& bc, Real v, int role, bool flip, int face,
+                                              double dt) {
+  if (face >= 0) return role <= kE ? (Real)bc.cons[face][role] : (Real)(dt * bc.vel[face][role - kXx]);
+  return (flip && (role == kMx || role == kXx)) ? -v : v;
 }
 
 long long ghost_count(const GridDev& g) {
@@ -570,7 +614,7 @@ struct PlaneP {
   Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP], psi[3][HP];
 };
 
-__device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDev& g,
+__device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              const Ctrl* __restrict__ ctrl, const Tile& T) {
   __shared__ PlaneP S;
   const int par = ctrl->par;
@@ -729,6 +773,19 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
       }
       auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
       F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
+      if (kPushX && (i < 2 || i >= g.nx - 2)) {
+        // x ghosts of the predicted particles (psi at their positions is left to
+        // the fill kernel: it needs loads that would stall this sweep)
+        x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
+          const long long cg = c + (gi - i);
+          F.ms[0][cg] = x_ghost_value(bc, ms[0], kMx, flip, face, dt);
+          F.ms[1][cg] = x_ghost_value(bc, ms[1], kMy, flip, face, dt);
+          F.ms[2][cg] = x_ghost_value(bc, ms[2], kMz, flip, face, dt);
+          F.ms[3][cg] = x_ghost_value(bc, Es, kE, flip, face, dt);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) F.xs[d][cg] = x_ghost_value(bc, xi[d], kXx + d, flip, face, dt);
+        });
+      }
     }
     lds_barrier();
   }
@@ -743,7 +800,7 @@ struct PlaneC {
   Real xx[3][HP], xy[3][HP], xz[3][HP], psi[3][HP];
 };
 
-__device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDev& g,
+__device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              const Ctrl* __restrict__ ctrl, const Tile& T) {
   __shared__ PlaneC S;
   const int par = ctrl->par;
@@ -921,8 +978,24 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       const Real qdt = (Real)(0.25 * dt);
       // xi^{n+1} = xi*/2 + dt (u^n + u~)/4 (the FP32 LDS holds xi*/h)
       const Real hx = kF64 ? (Real)0.5 : (Real)(0.5 * g.h);
+      Real xn[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) F.xt[d][c] = hx * xc[d] + qdt * (un[d] + ut[d]);
+      for (int d = 0; d < 3; ++d) {
+        xn[d] = hx * xc[d] + qdt * (un[d] + ut[d]);
+        F.xt[d][c] = xn[d];
+      }
+      if (kPushX && (i < 2 || i >= g.nx - 2)) {
+        // x ghosts of the post-Lagrange particles
+        x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
+          const long long cg = c + (gi - i);
+          F.mt[0][cg] = x_ghost_value(bc, mt[0], kMx, flip, face, dt);
+          F.mt[1][cg] = x_ghost_value(bc, mt[1], kMy, flip, face, dt);
+          F.mt[2][cg] = x_ghost_value(bc, mt[2], kMz, flip, face, dt);
+          F.mt[3][cg] = x_ghost_value(bc, Et, kE, flip, face, dt);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) F.xt[d][cg] = x_ghost_value(bc, xn[d], kXx + d, flip, face, dt);
+        });
+      }
     }
     lds_barrier();
   }
@@ -1116,7 +1189,8 @@ __device__ __forceinline__ bool tile_face(const GridDev& g, const Tile& T, const
 }
 
 template <bool kGen>
-__device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
+__device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+                                             Ctrl* ctrl,
                                              const Tile& T, double* __restrict__ slot) {
   const bool have = true;
   __shared__ PlaneE S;
@@ -1298,6 +1372,14 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
           if (!isfinite(nv[v])) bad |= kBadNonFinite;
           tot[v] += (double)nv[v];
         }
+        if (kPushX && (i < 2 || i >= g.nx - 2)) {
+          // x ghosts (two deep) of the new state
+          x_push<2>(g, bc, i, [&](int gi, bool flip, int face) {
+            const long long cg = c + (gi - i);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Uo[v][cg] = x_ghost_value(bc, nv[v], v, flip, face, 0.0);
+          });
+        }
         if ((double)nv[0] < -g.neg_tol) bad |= kBadNegDensity;
         if (!bad) smax = fmax(smax, signal_speed(g, nv[0], nv[1], nv[2], nv[3], nv[4]));
         // advance the carried z face and the base queue to k+1
@@ -1342,32 +1424,32 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
 }
 
 // ------------------------------------------------------------------ stage launches
-__global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g,
+__global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev bc,
                                                 const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  stage_p_body(F, g, ctrl, T);
+  stage_p_body(F, g, bc, ctrl, T);
 }
 
-__global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g,
+__global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g, BcDev bc,
                                                    const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  stage_c_body(F, g, ctrl, T);
+  stage_c_body(F, g, bc, ctrl, T);
 }
 
 template <bool kGen>
-__global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Ctrl* ctrl,
+__global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, BcDev bc, Ctrl* ctrl,
                                                    double* __restrict__ partials, int tz) {
   if (!ctrl->active) return;
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  stage_e_body<kGen>(F, g, ctrl, T, partials + (long long)id * 5);
+  stage_e_body<kGen>(F, g, bc, ctrl, T, partials + (long long)id * 5);
 }
 
 // batched sweeps: workgroup -> (instance, tile) through a host-built map of the
@@ -1382,12 +1464,12 @@ __global__ void __launch_bounds__(NT, 2) k_stage_batch(const Inst<Real>* __restr
   if (!I.ctrl->active) return;
   Tile T;
   tile_at(I.g, I.tz, w.y, T);
-  if (kStage == 0) stage_p_body(I.F, I.g, I.ctrl, T);
-  else if (kStage == 1) stage_c_body(I.F, I.g, I.ctrl, T);
+  if (kStage == 0) stage_p_body(I.F, I.g, I.bc, I.ctrl, T);
+  else if (kStage == 1) stage_c_body(I.F, I.g, I.bc, I.ctrl, T);
   else if (!kGen || default_scheme(I.g))
-    stage_e_body<false>(I.F, I.g, I.ctrl, T, I.partials + (long long)w.y * 5);
+    stage_e_body<false>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);
   else
-    stage_e_body<true>(I.F, I.g, I.ctrl, T, I.partials + (long long)w.y * 5);
+    stage_e_body<true>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);
 }
 
 // fixed-order sum of the per-block totals
@@ -1482,10 +1564,16 @@ hipError_t Launch<Real>::fill_psi(const Fields<Real>& F, const GridDev& g, const
 }
 
 template <>
-hipError_t Launch<Real>::fill_state(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+hipError_t Launch<Real>::fill_state(const Fields<Real>& F, const GridDev& g, const BcDev& bc, int par,
                                     Ctrl* ctrl, hipStream_t s) {
+  FillSet<Real> fs{};
+  for (int v = 0; v < 5; ++v) {
+    fs.f[v] = F.U[par][v];
+    fs.role[v] = v;
+  }
+  fs.n = 5;
   const long long n = ghost_count(g);
-  k_fill_state<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(F, g, bc, ctrl);
+  k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fs, g, bc, ctrl, 0);
   return hipGetLastError();
 }
 
@@ -1510,18 +1598,18 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
   k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(1);
-  k_stage_p<<<nb, NT, 0, s>>>(F, g, ctrl, tz);
+  k_stage_p<<<nb, NT, 0, s>>>(F, g, bc, ctrl, tz);
   mark(2);
   k_fill_pred<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(3);
-  k_stage_c<<<nb, NT, 0, s>>>(F, g, ctrl, tz);
+  k_stage_c<<<nb, NT, 0, s>>>(F, g, bc, ctrl, tz);
   mark(4);
   k_fill_corr<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(5);
   if (default_scheme(g))
-    k_stage_e<false><<<nb, NT, 0, s>>>(F, g, ctrl, partials, tz);
+    k_stage_e<false><<<nb, NT, 0, s>>>(F, g, bc, ctrl, partials, tz);
   else
-    k_stage_e<true><<<nb, NT, 0, s>>>(F, g, ctrl, partials, tz);
+    k_stage_e<true><<<nb, NT, 0, s>>>(F, g, bc, ctrl, partials, tz);
   mark(6);
   k_end<<<1, 64, 0, s>>>(ctrl);
   mark(7);

@@ -194,6 +194,7 @@ struct csph_sim {
   double* partials = nullptr;
   double* totals_dev = nullptr;
   bool psi_dirty = true;
+  bool x_stale = true;   // the x ghosts of U^n do not follow the state / boundaries
   bool need_smax = true;
   int tz = 0;            // z-planes per workgroup of the stencil sweeps
   int tz_last = 0;       // tile depth of the last stage E launched (its per-tile totals)
@@ -314,6 +315,15 @@ csph_status prepare(csph_sim* s) {
   if (s->psi_dirty) {
     HIP_TRY(Launch<Real>::fill_psi(F, s->g, s->bc, s->ctrl, s->stream));
     s->psi_dirty = false;
+  }
+  if (s->x_stale) {
+    // the stages push the x ghosts of what they write; a state set from the host
+    // (or new boundaries) needs all its ghost cells once
+    Ctrl c{};
+    csph_status st = read_ctrl(s, &c);
+    if (st) return st;
+    HIP_TRY(Launch<Real>::fill_state(F, s->g, s->bc, c.par, s->ctrl, s->stream));
+    s->x_stale = false;
   }
   if (s->need_smax) {
     HIP_TRY(Launch<Real>::signal_max(F, s->g, s->ctrl, s->stream));
@@ -519,6 +529,7 @@ csph_status csph_set_state(csph_sim* s, csph_vars vars, const double* host) {
   st = write_ctrl(s, c);
   if (st) return st;
   s->need_smax = true;
+  s->x_stale = true;
   s->stepped = false;
   return CSPH_OK;
 }
@@ -557,6 +568,7 @@ csph_status csph_set_boundary(csph_sim* s, int32_t face, csph_bc kind, const dou
     s->bc.vel[face][2] = uz;
   }
   s->psi_dirty = true;
+  s->x_stale = true;
   return CSPH_OK;
 }
 
@@ -809,6 +821,7 @@ csph_status clone_sim(const csph_sim* s, csph_sim** out) {
   std::memcpy(t->inflow_prim, s->inflow_prim, sizeof(t->inflow_prim));
   t->psi_dirty = s->psi_dirty;
   t->need_smax = s->need_smax;
+  t->x_stale = s->x_stale;
   t->tz = s->tz;
   t->tz_last = s->tz_last;
   t->has_psi = s->has_psi;
