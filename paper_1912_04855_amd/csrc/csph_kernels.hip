@@ -511,16 +511,20 @@ __device__ __forceinline__ void block_max_to(double v, unsigned long long* dst) 
   }
 }
 
+// max signal speed of U^n (before the first step; later steps take it from the
+// stage-E epilogue).  Blocks stride over the z planes, so that few blocks meet
+// at the one atomic.
 __global__ void __launch_bounds__(256) k_signal_max(Fields<Real> F, GridDev g, Ctrl* ctrl) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
   const int par = ctrl->par;
   double v = 0.0;
   if (i < g.nx && j < g.ny) {
-    const long long c = cell(g, i, j, k);
-    v = signal_speed(g, F.U[par][0][c], F.U[par][1][c], F.U[par][2][c], F.U[par][3][c],
-                     F.U[par][4][c]);
+    for (int k = blockIdx.z; k < g.nz; k += gridDim.z) {
+      const long long c = cell(g, i, j, k);
+      v = fmax(v, signal_speed(g, F.U[par][0][c], F.U[par][1][c], F.U[par][2][c], F.U[par][3][c],
+                               F.U[par][4][c]));
+    }
   }
   block_max_to(v, &ctrl->smax_bits[ctrl->cur]);
 }
@@ -1508,7 +1512,7 @@ int sweep_blocks(const GridDev& g, int tz) {
 }
 
 dim3 cell_grid(const GridDev& g) {
-  return dim3((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)g.nz);
+  return dim3((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)min(g.nz, 8));
 }
 
 }  // namespace CSPH_TAG

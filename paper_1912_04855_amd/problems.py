@@ -280,6 +280,28 @@ def random_state(shape=(32, 32, 32), seed=1, gamma=1.4, potential=False, bc=None
     return Problem("random", tuple(shape), h, gamma, 0.4, tuple(bc or (PERIODIC,) * 6), prim, psi)
 
 
+def smooth_state(shape=(16, 12, 10), seed=0, gamma=1.4, bc=None, potential=True) -> Problem:
+    """Seeded smooth state: every primitive variable is a constant plus one
+    low-wavenumber sine per axis with seeded phases (rho, p in [0.7, 1.3],
+    |u| <= 0.3); psi likewise (amplitude 0.2) when ``potential``."""
+    nx, ny, nz = shape
+    h = 1.0 / nx
+    x, y, z = centres(shape, h)
+    ph = uniform01(seed, np.arange(24, dtype=np.uint64)) * 2 * math.pi
+
+    def wave(q, amp):
+        return amp * (np.sin(2 * math.pi * x + ph[3 * q]) * np.cos(2 * math.pi * y + ph[3 * q + 1])
+                      * np.cos(2 * math.pi * z + ph[3 * q + 2]))
+    prim = _prim(shape)
+    prim[0] = 1.0 + wave(0, 0.3)
+    prim[1] = wave(1, 0.3)
+    prim[2] = wave(2, 0.2)
+    prim[3] = wave(3, 0.2)
+    prim[4] = 1.0 + wave(4, 0.3)
+    psi = wave(5, 0.2) if potential else None
+    return Problem("smooth", tuple(shape), h, gamma, 0.4, tuple(bc or (PERIODIC,) * 6), prim, psi)
+
+
 # --------------------------------------------------------------------------
 # batched and serving workloads
 # --------------------------------------------------------------------------
