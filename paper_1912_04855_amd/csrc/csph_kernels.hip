@@ -187,13 +187,14 @@ __device__ __forceinline__ void kgrad(const GridDev& g, Real dx, Real dy, Real d
 
 // FP32 form of the same gradient with the separation in lattice units (d/h):
 // g(q) = (3/4)[(2-q)_+^2 - 4 (1-q)_+^2] covers both spline pieces without a
-// branch, and K = ck (g(q)/q)/(3/4) d with ck = -(3/4) kappa / h.
-__device__ __forceinline__ void kgrad_lat(float ck, float dx, float dy, float dz, float K[3]) {
+// branch.  The result is K / ck, with K = ck (g(q)/q)/(3/4) d and ck = -(3/4) kappa / h:
+// every sum the corrector forms is linear in K, so the caller applies ck once per cell.
+__device__ __forceinline__ void kgrad_lat(float dx, float dy, float dz, float K[3]) {
   const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 1e-12f);
   const float rs = __builtin_amdgcn_rsqf(r2);
   const float q = r2 * rs;
   const float t = fmaxf(2.0f - q, 0.0f), u = fmaxf(1.0f - q, 0.0f);
-  const float c = ck * rs * fmaf(t, t, -4.0f * u * u);
+  const float c = rs * fmaf(t, t, -4.0f * u * u);
   K[0] = c * dx;
   K[1] = c * dy;
   K[2] = c * dz;
@@ -799,9 +800,15 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
 // Corrector, Eq. (6): m~ = (m + m*)/2 - (dt/2) A*, E~ likewise, with Q(U*, r*)
 // evaluated at the displaced particles r* = x + xi* (kernel gradients of the
 // displaced pairs, psi at r*); xi = xi*/2 + dt (u^n + u~)/4.
+// Four values of a cell kept as one aligned LDS vector, so that a neighbour's values
+// cost one vector read at an immediate offset from the plane's base.
+struct alignas(4 * sizeof(Real)) Quad {
+  Real x, y, z, w;
+};
+// Per cell of a plane: a = (xi_x, xi_y, xi_z, phi), b = (u_x, u_y, u_z, psi).
 struct PlaneC {
-  Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP];
-  Real xx[3][HP], xy[3][HP], xz[3][HP], psi[3][HP];
+  Quad a[3][HP], b[3][HP];
+  Real rho[3][HP];
 };
 
 __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
@@ -830,21 +837,10 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       Real ux, uy, uz, p;
       primitive(g, r, MSX[c], MSY[c], MSZ[c], ES[c], ux, uy, uz, p);
       S.rho[s][q] = r;
-      S.phi[s][q] = sqrt_fast((Real)2 * p);
-      S.ux[s][q] = ux;
-      S.uy[s][q] = uy;
-      S.uz[s][q] = uz;
-      if constexpr (kF64) {
-        S.xx[s][q] = F.xs[0][c];
-        S.xy[s][q] = F.xs[1][c];
-        S.xz[s][q] = F.xs[2][c];
-      } else {
-        // particle offsets in lattice units
-        S.xx[s][q] = F.xs[0][c] * ih;
-        S.xy[s][q] = F.xs[1][c] * ih;
-        S.xz[s][q] = F.xs[2][c] * ih;
-      }
-      S.psi[s][q] = F.psis[c];
+      // particle offsets in lattice units in FP32
+      const Real sc = kF64 ? (Real)1 : ih;
+      S.a[s][q] = Quad{F.xs[0][c] * sc, F.xs[1][c] * sc, F.xs[2][c] * sc, sqrt_fast((Real)2 * p)};
+      S.b[s][q] = Quad{ux, uy, uz, F.psis[c]};
     }
   };
 
@@ -856,17 +852,12 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
     if (in) {
       const int s0 = ring3(k), c0 = hidx(tx + 1, ty + 1);
       auto nb = [&](int ox, int oy, int oz) { return ring3(k + oz) * HP + hidx(tx + 1 + ox, ty + 1 + oy); };
-      const Real* phi_ = &S.phi[0][0];
-      const Real* ux_ = &S.ux[0][0];
-      const Real* uy_ = &S.uy[0][0];
-      const Real* uz_ = &S.uz[0][0];
-      const Real* xx_ = &S.xx[0][0];
-      const Real* xy_ = &S.xy[0][0];
-      const Real* xz_ = &S.xz[0][0];
-      const Real* psi_ = &S.psi[0][0];
-      const Real rc = S.rho[s0][c0], fc = S.phi[s0][c0], psc = S.psi[s0][c0];
-      const Real uc[3] = {S.ux[s0][c0], S.uy[s0][c0], S.uz[s0][c0]};
-      const Real xc[3] = {S.xx[s0][c0], S.xy[s0][c0], S.xz[s0][c0]};
+      const Quad* A_ = &S.a[0][0];
+      const Quad* B_ = &S.b[0][0];
+      const Quad Ac = S.a[s0][c0], Bc = S.b[s0][c0];
+      const Real rc = S.rho[s0][c0], fc = Ac.w, psc = Bc.w;
+      const Real uc[3] = {Bc.x, Bc.y, Bc.z};
+      const Real xc[3] = {Ac.x, Ac.y, Ac.z};
       Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
       Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0;
       const int tb = hidx(tx + 1, ty + 1);
@@ -882,15 +873,16 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
             const int n = side == 0 ? np : nm;
+            const Quad An = A_[n], Bn = B_[n];
             // separation r_c - r_n = -h o + (xi_c - xi_n) (o -> -o on the minus side)
-            const Real dx = side == 0 ? hx + (xc[0] - xx_[n]) : (xc[0] - xx_[n]) - hx;
-            const Real dy = side == 0 ? hy + (xc[1] - xy_[n]) : (xc[1] - xy_[n]) - hy;
-            const Real dz = side == 0 ? hz + (xc[2] - xz_[n]) : (xc[2] - xz_[n]) - hz;
+            const Real dx = side == 0 ? hx + (xc[0] - An.x) : (xc[0] - An.x) - hx;
+            const Real dy = side == 0 ? hy + (xc[1] - An.y) : (xc[1] - An.y) - hy;
+            const Real dz = side == 0 ? hz + (xc[2] - An.z) : (xc[2] - An.z) - hz;
             kgrad(g, dx, dy, dz, K[side][0], K[side][1], K[side][2]);
-            fn[side] = phi_[n];
-            pn[side] = psi_[n];
-            ub[side] = (uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
-                       (uc[2] + uz_[n]) * K[side][2];
+            fn[side] = An.w;
+            pn[side] = Bn.w;
+            ub[side] = (uc[0] + Bn.x) * K[side][0] + (uc[1] + Bn.y) * K[side][1] +
+                       (uc[2] + Bn.z) * K[side][2];
             ub[side] = 0.5 * ub[side];
           }
           {
@@ -911,7 +903,8 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
         }
       } else {
         // the 13 pairs unrolled with their offsets known at compile time; the
-        // separations are in lattice units: d = (xi_c - xi_n)/h -+ o
+        // separations are in lattice units: d = (xi_c - xi_n)/h -+ o.  The sums
+        // are formed with K / ck and scaled by ck after the loop.
         const float ck = (float)(-0.75 * g.kappa_h2 * g.h);
         const int bm = ring3(k - 1) * HP + tb, b0 = ring3(k) * HP + tb, bp = ring3(k + 1) * HP + tb;
 #pragma unroll
@@ -924,15 +917,16 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
           for (int side = 0; side < 2; ++side) {
             const int n = side == 0 ? np : nm;
             const int sg = side == 0 ? 1 : -1;
-            float d[3] = {(float)(xc[0] - xx_[n]), (float)(xc[1] - xy_[n]), (float)(xc[2] - xz_[n])};
+            const Quad An = A_[n], Bn = B_[n];
+            float d[3] = {(float)(xc[0] - An.x), (float)(xc[1] - An.y), (float)(xc[2] - An.z)};
             if (ox != 0) d[0] -= (float)(sg * ox);
             if (oy != 0) d[1] -= (float)(sg * oy);
             if (oz != 0) d[2] -= (float)(sg * oz);
-            kgrad_lat(ck, d[0], d[1], d[2], K[side]);
-            fn[side] = phi_[n];
-            pn[side] = psi_[n];
-            ub[side] = (uc[0] + ux_[n]) * K[side][0] + (uc[1] + uy_[n]) * K[side][1] +
-                       (uc[2] + uz_[n]) * K[side][2];
+            kgrad_lat(d[0], d[1], d[2], K[side]);
+            fn[side] = An.w;
+            pn[side] = Bn.w;
+            ub[side] = (uc[0] + Bn.x) * K[side][0] + (uc[1] + Bn.y) * K[side][1] +
+                       (uc[2] + Bn.z) * K[side][2];
           }
           // sp+ K+ + sp- K- = (sp+ - sp-) K+ + sp- (K+ + K-).  The difference
           // sp+ - sp- = phi_c (phi+ - phi-) + rho_c (psi+ - psi-) carries the
@@ -944,15 +938,24 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
           const Real dsp = (Real)((Acc)fc * (Acc)dphi + (Acc)rc * (Acc)dps);
           const Real d0 = pn[0] - psc, d1 = pn[1] - psc;
           const Real spm = fc * fn[1] + rc * d1;
+          // each term goes straight into its accumulator (one fused multiply-add each)
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            af[d] += dsp * K[0][d] + spm * (K[0][d] + K[1][d]);
-            gf[d] += d0 * K[0][d] + d1 * K[1][d];
+            af[d] = fmaf(dsp, K[0][d], af[d]);
+            af[d] = fmaf(spm, K[0][d] + K[1][d], af[d]);
+            gf[d] = fmaf(d0, K[0][d], gf[d]);
+            gf[d] = fmaf(d1, K[1][d], gf[d]);
           }
-          bf += fn[0] * ub[0] + fn[1] * ub[1];
+          bf = fmaf(fn[0], ub[0], bf);
+          bf = fmaf(fn[1], ub[1], bf);
         }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          af[d] *= ck;
+          gf[d] *= ck;
+        }
+        bf *= (Real)0.5 * fc * ck;
       }
-      if constexpr (!kF64) bf *= (Real)0.5 * fc;
       const long long c = cell(g, i, j, k);
       const Real m0[3] = {F.U[par][1][c], F.U[par][2][c], F.U[par][3][c]};
       const Real E0 = F.U[par][4][c];
