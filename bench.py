@@ -63,6 +63,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _depths(text):
+    """--tile-depth: one depth for every stage, or 'p,c,e'."""
+    v = [int(x) for x in str(text).split(",")]
+    if len(v) not in (1, 3):
+        raise argparse.ArgumentTypeError("one depth or three (stage P, C, E)")
+    return v[0] if len(v) == 1 else tuple(v)
+
+
+def _tile(depths):
+    """Tile shape and the z-depth of each stage's sweep."""
+    return "32x8, z-depth P/C/E " + "/".join(str(d) for d in depths)
+
+
 def run_gpu(prob, dtype, steps, warmup, autotune=True, tile_depth=0):
     import torch
     from paper_1912_04855_amd.sim import from_problem
@@ -183,7 +196,7 @@ def run_batch(count=512, steps=100, seed=0, chunk=10, tile_depth=0):
         s.close()
     return {"value": round(cells * steps / wall, 1), "unit": "cell-updates/s", "instances": count,
             "cells": cells, "steps_each": steps, "ms_per_step": round(wall * 1e3 / steps, 4),
-            "tile": f"32x8x{tz}", "setup_s": round(setup, 2), "dtype": "f32",
+            "tile": f"32x8, z-depth {tz}", "setup_s": round(setup, 2), "dtype": "f32",
             "workload": f"{count} instances, edges uniform in {{32,48,64,96}} per axis, "
                         "Sod tube or Sedov blast by seed"}
 
@@ -254,8 +267,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in tile depth instead of autotuning it first")
-    ap.add_argument("--tile-depth", type=int, default=0,
-                    help="use this tile depth (z-planes per workgroup) instead of autotuning")
+    ap.add_argument("--tile-depth", type=_depths, default=0,
+                    help="use this tile depth (z-planes per workgroup; one value, or three "
+                         "comma-separated for stages P,C,E) instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--batch-only", action="store_true",
@@ -310,7 +324,7 @@ def main():
         "config": {"workload": f"potential-well flow {args.n}^3 (Mach-2 inflow, "
                                f"psi=-exp(-r^2/0.01), gamma=5/3)",
                    "cells": cells, "dtype": args.dtype, "parallelism": "single GPU",
-                   "tile": f"32x8x{r['tile_depth']}"},
+                   "tile": _tile(r["tile_depth"])},
         "roofline": rl,
         "algorithmic_hbm_frac": round(value * (44 if args.dtype == "f32" else 88) / HBM_PEAK, 4),
     }
@@ -320,7 +334,7 @@ def main():
         r64 = run_gpu(pr, "f64", k64, args.warmup, autotune=not args.no_autotune)
         v64 = cells * k64 / (r64["event_ms"] * 1e-3)
         out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(r64["event_ms"] / k64, 4),
-                       "steps": k64, "tile": f"32x8x{r64['tile_depth']}",
+                       "steps": k64, "tile": _tile(r64["tile_depth"]),
                        "roofline": roofline(r64["profile"], cells, "f64")}
     if not args.no_batch:
         log(f"[bench] batched workload: {args.batch_count} instances")

@@ -172,20 +172,24 @@ csph_status csph_get_scheme(const csph_sim* sim, int32_t* limiter, int32_t* flux
 
 /* Tile depth: the stencil sweeps give each workgroup a 32 x 8 tile of an x-y
  * plane and march it through tz planes along z.  Deeper tiles reuse more of the
- * halo they stage; shallower ones give more workgroups.  Valid depths are
- * 2..64; a new simulation starts from a built-in rule, or from the depth
- * csph_autotune chose earlier in this process for the same device, dtype and
- * grid shape.  Not allowed on a batch member. */
+ * halo they stage; shallower ones give more workgroups.  Each of the three
+ * sweeps (stage P, stage C, stage E, in that order in tz[3]) has its own depth;
+ * valid depths are 2..64.  A new simulation starts from a built-in rule, or from
+ * the depths csph_autotune chose earlier in this process for the same device,
+ * dtype and grid shape.  csph_set_tile_depth sets all three.  Not allowed on a
+ * batch member (a batch sweeps every stage of a member at its stage-C depth). */
 csph_status csph_set_tile_depth(csph_sim* sim, int32_t tz);
-csph_status csph_get_tile_depth(const csph_sim* sim, int32_t* tz);
+csph_status csph_set_tile_depths(csph_sim* sim, const int32_t tz[3]);
+csph_status csph_get_tile_depths(const csph_sim* sim, int32_t tz[3]);
 
-/* Autotuner: time trial_steps steps (1..1000) at each candidate depth (2, 4,
+/* Autotuner: run trial_steps steps (1..1000) at each candidate depth (2, 4,
  * 8, ... up to the grid's nz) on a library-owned copy of the simulation (its
  * state, potential, boundaries and time; csph_required_bytes of extra device
- * memory while it runs), keep the fastest on `sim` and remember it for the
- * shape.  The simulation itself is not advanced.  tz_out and ms_per_step
- * (the winner's step time) may be NULL.  Synchronises. */
-csph_status csph_autotune(csph_sim* sim, int32_t trial_steps, int32_t* tz_out, double* ms_per_step);
+ * memory while it runs), timing each stage's kernels with HIP events; keep each
+ * stage's fastest depth on `sim` and remember them for the shape.  The
+ * simulation itself is not advanced.  tz_out (three depths) and ms_per_step
+ * (the step time at the chosen depths) may be NULL.  Synchronises. */
+csph_status csph_autotune(csph_sim* sim, int32_t trial_steps, int32_t tz_out[3], double* ms_per_step);
 
 /* ---------------- batches: many simulations advanced together ---------------
  * A batch references simulations of one dtype; it does not own them, and each

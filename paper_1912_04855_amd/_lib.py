@@ -29,7 +29,8 @@ EXPORTS = [
     "csph_get_state", "csph_get_time", "csph_set_time", "csph_totals", "csph_get_stage",
     "csph_last_error", "csph_batch_create", "csph_batch_add", "csph_batch_advance",
     "csph_batch_poll", "csph_batch_remove", "csph_batch_destroy", "csph_profile_enable",
-    "csph_profile_read", "csph_set_tile_depth", "csph_get_tile_depth", "csph_autotune",
+    "csph_profile_read", "csph_set_tile_depth", "csph_set_tile_depths", "csph_get_tile_depths",
+    "csph_autotune",
     "csph_batch_autotune", "csph_set_scheme", "csph_get_scheme",
 ]
 
@@ -85,7 +86,8 @@ def load():
         "csph_profile_enable": (st, [vp, C.c_int32]),
         "csph_profile_read": (st, [vp, vp, vp, C.c_int32]),
         "csph_set_tile_depth": (st, [vp, C.c_int32]),
-        "csph_get_tile_depth": (st, [vp, C.POINTER(C.c_int32)]),
+        "csph_set_tile_depths": (st, [vp, C.POINTER(C.c_int32)]),
+        "csph_get_tile_depths": (st, [vp, C.POINTER(C.c_int32)]),
         "csph_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
         "csph_batch_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
         "csph_set_scheme": (st, [vp, C.c_int32, C.c_int32]),

@@ -121,7 +121,7 @@ struct Launch {
   // one full step: begin, ghosts, stage P, ghosts, stage C, ghosts, stage E, end
   // ev (nullable): 8 events recorded around the launches, for kernel timing
   static hipError_t step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
-                         double* partials, double dt_max, double t_end, int tz, hipStream_t s,
+                         double* partials, double dt_max, double t_end, const int tz[3], hipStream_t s,
                          hipEvent_t* ev);
   // one step of every active member of a batch, one launch per stage
   // tile_map[t] = (member, tile of that member); fill_map[b] = (member, first

@@ -192,8 +192,8 @@ __device__ __forceinline__ void kgrad(const GridDev& g, Real dx, Real dy, Real d
 __device__ __forceinline__ void kgrad_lat(float dx, float dy, float dz, float K[3]) {
   const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 1e-12f);
   const float rs = __builtin_amdgcn_rsqf(r2);
-  const float q = r2 * rs;
-  const float t = fmaxf(2.0f - q, 0.0f), u = fmaxf(1.0f - q, 0.0f);
+  // q = r2 rs = |d|
+  const float t = fmaxf(fmaf(-r2, rs, 2.0f), 0.0f), u = fmaxf(fmaf(-r2, rs, 1.0f), 0.0f);
   const float c = rs * fmaf(t, t, -4.0f * u * u);
   K[0] = c * dx;
   K[1] = c * dy;
@@ -1593,11 +1593,13 @@ hipError_t Launch<Real>::signal_max(const Fields<Real>& F, const GridDev& g, Ctr
 
 template <>
 hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
-                              double* partials, double dt_max, double t_end, int tz, hipStream_t s,
-                              hipEvent_t* ev) {
+                              double* partials, double dt_max, double t_end, const int tz[3],
+                              hipStream_t s, hipEvent_t* ev) {
   const long long ng = ghost_count(g);
   const unsigned gb = (unsigned)((ng + 255) / 256);
-  const unsigned nb = (unsigned)sweep_blocks(g, tz);
+  // each stage has its own tile depth
+  const unsigned nbp = (unsigned)sweep_blocks(g, tz[0]), nbc = (unsigned)sweep_blocks(g, tz[1]),
+                 nbe = (unsigned)sweep_blocks(g, tz[2]);
   auto mark = [&](int q) {
     if (ev) (void)hipEventRecord(ev[q], s);
   };
@@ -1605,18 +1607,18 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
   k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(1);
-  k_stage_p<<<nb, NT, 0, s>>>(F, g, bc, ctrl, tz);
+  k_stage_p<<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
   mark(2);
   k_fill_pred<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(3);
-  k_stage_c<<<nb, NT, 0, s>>>(F, g, bc, ctrl, tz);
+  k_stage_c<<<nbc, NT, 0, s>>>(F, g, bc, ctrl, tz[1]);
   mark(4);
   k_fill_corr<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(5);
   if (default_scheme(g))
-    k_stage_e<false><<<nb, NT, 0, s>>>(F, g, bc, ctrl, partials, tz);
+    k_stage_e<false><<<nbe, NT, 0, s>>>(F, g, bc, ctrl, partials, tz[2]);
   else
-    k_stage_e<true><<<nb, NT, 0, s>>>(F, g, bc, ctrl, partials, tz);
+    k_stage_e<true><<<nbe, NT, 0, s>>>(F, g, bc, ctrl, partials, tz[2]);
   mark(6);
   k_end<<<1, 64, 0, s>>>(ctrl);
   mark(7);

@@ -48,10 +48,11 @@ constexpr int kNumFields = 26;  // U[2][5], psi, ms[4], xs[3], psis, mt[4], xt[3
 constexpr int kTzMin = 2, kTzMax = 64;
 constexpr int kTzCand[] = {2, 4, 8, 16, 32, 64};
 
-// tile depths chosen by csph_autotune, per (device, dtype, nx, ny, nz): later
-// simulations of the same shape start from them
+// tile depths (stages P, C, E) chosen by csph_autotune, per (device, dtype,
+// nx, ny, nz): later simulations of the same shape start from them
+using Depths = std::array<int, 3>;
 std::mutex g_tune_mu;
-std::map<std::array<int, 5>, int> g_tune;
+std::map<std::array<int, 5>, Depths> g_tune;
 
 std::array<int, 5> tune_key(int device, const csph_grid_desc& d) {
   return {device, (int)d.dtype, d.nx, d.ny, d.nz};
@@ -196,8 +197,8 @@ struct csph_sim {
   bool psi_dirty = true;
   bool x_stale = true;   // the x ghosts of U^n do not follow the state / boundaries
   bool need_smax = true;
-  int tz = 0;            // z-planes per workgroup of the stencil sweeps
-  int tz_last = 0;       // tile depth of the last stage E launched (its per-tile totals)
+  int tz[3] = {0, 0, 0};  // z-planes per workgroup of the sweeps of stages P, C, E
+  int tz_last = 0;        // tile depth of the last stage E launched (its per-tile totals)
   bool in_batch = false;
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool stepped = false;  // partials describe the current state
@@ -371,7 +372,7 @@ csph_status launch_steps(csph_sim* s, int n, double dt_max, double t_end) {
                                ev));
   }
   s->stepped = true;
-  s->tz_last = s->tz;
+  s->tz_last = s->tz[2];
   return CSPH_OK;
 }
 
@@ -388,13 +389,15 @@ bool periodic_pairs_ok(const csph_sim* s) {
 
 csph_status init_sim(csph_sim* s) {
   s->g = make_grid(&s->desc);
-  s->tz = s->is_f64() ? Launch<double>::default_tz(s->g) : Launch<float>::default_tz(s->g);
+  const int tz0 = s->is_f64() ? Launch<double>::default_tz(s->g) : Launch<float>::default_tz(s->g);
+  for (int q = 0; q < 3; ++q) s->tz[q] = tz0;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(s->device, s->desc));
-    if (it != g_tune.end()) s->tz = it->second;
+    if (it != g_tune.end())
+      for (int q = 0; q < 3; ++q) s->tz[q] = it->second[q];
   }
-  s->tz_last = s->tz;
+  s->tz_last = s->tz[2];
   for (int f = 0; f < 6; ++f) s->bc.kind[f] = kPeriodic;
   if (s->is_f64())
     bind_fields<double>(s, s->f64);
@@ -766,17 +769,23 @@ csph_status csph_get_scheme(const csph_sim* s, int32_t* limiter, int32_t* flux) 
   return CSPH_OK;
 }
 
-csph_status csph_set_tile_depth(csph_sim* s, int32_t tz) {
-  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
-  if (tz < kTzMin || tz > kTzMax) return fail(CSPH_ERR_ARG, "tile depth must be in [2, 64]");
+csph_status csph_set_tile_depths(csph_sim* s, const int32_t tz[3]) {
+  if (!s || !tz) return fail(CSPH_ERR_ARG, "sim or tz is NULL");
+  for (int q = 0; q < 3; ++q)
+    if (tz[q] < kTzMin || tz[q] > kTzMax) return fail(CSPH_ERR_ARG, "tile depth must be in [2, 64]");
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
-  s->tz = tz;
+  for (int q = 0; q < 3; ++q) s->tz[q] = tz[q];
   return CSPH_OK;
 }
 
-csph_status csph_get_tile_depth(const csph_sim* s, int32_t* tz) {
+csph_status csph_set_tile_depth(csph_sim* s, int32_t tz) {
+  const int32_t all[3] = {tz, tz, tz};
+  return csph_set_tile_depths(s, all);
+}
+
+csph_status csph_get_tile_depths(const csph_sim* s, int32_t tz[3]) {
   if (!s || !tz) return fail(CSPH_ERR_ARG, "sim or tz is NULL");
-  *tz = s->tz;
+  for (int q = 0; q < 3; ++q) tz[q] = s->tz[q];
   return CSPH_OK;
 }
 
@@ -822,7 +831,7 @@ csph_status clone_sim(const csph_sim* s, csph_sim** out) {
   t->psi_dirty = s->psi_dirty;
   t->need_smax = s->need_smax;
   t->x_stale = s->x_stale;
-  t->tz = s->tz;
+  for (int q = 0; q < 3; ++q) t->tz[q] = s->tz[q];
   t->tz_last = s->tz_last;
   t->has_psi = s->has_psi;
   void* p = nullptr;
@@ -865,7 +874,7 @@ std::vector<int> tz_candidates(int nz) {
 
 extern "C" {
 
-csph_status csph_autotune(csph_sim* s, int32_t trial_steps, int32_t* tz_out, double* ms_per_step) {
+csph_status csph_autotune(csph_sim* s, int32_t trial_steps, int32_t tz_out[3], double* ms_per_step) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: tune the batch");
   if (trial_steps < 1 || trial_steps > 1000) return fail(CSPH_ERR_ARG, "trial_steps must be in [1, 1000]");
@@ -883,46 +892,72 @@ csph_status csph_autotune(csph_sim* s, int32_t trial_steps, int32_t* tz_out, dou
   Ctrl c0{};
   st = read_ctrl(t, &c0);
   c0.done = 0;
-  int best = s->tz;
-  double best_ms = INFINITY;
+  // each stage's kernels are timed on their own (HIP events around every
+  // launch), so one sweep over the candidate depths picks each stage's best
+  int best[3] = {s->tz[0], s->tz[1], s->tz[2]};
+  double best_ms[3] = {INFINITY, INFINITY, INFINITY};
+  // trial_steps steps from the starting state at the current depths; with
+  // `stages`, the per-stage average kernel times
+  auto trial = [&](double* ms, double stages[3]) -> csph_status {
+    for (int rep = 0; rep < 2; ++rep) {
+      // one untimed step (first use of this launch shape), then the timed ones,
+      // each from the same starting state
+      if (hipMemcpyAsync(t->buf, s->buf, s->L.total, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+        return fail(CSPH_ERR_DEVICE, "copy of the state for a trial run failed");
+      csph_status e = write_ctrl(t, c0);
+      if (!e && stages && rep == 1) e = csph_profile_enable(t, 1);
+      if (e) return e;
+      const int n = rep == 0 ? 1 : trial_steps;
+      e = time_on(t->stream, [&]() { return launch(t, n, 0.0, INFINITY); }, ms);
+      if (e) return e;
+    }
+    if (stages) {
+      double avg[5];
+      int64_t cnt[5];
+      csph_status e = csph_profile_read(t, avg, cnt, 5);
+      if (!e) e = csph_profile_enable(t, 0);
+      if (e) return e;
+      for (int q = 0; q < 3; ++q) stages[q] = avg[q];
+    }
+    return CSPH_OK;
+  };
   for (int tz : tz_candidates(s->g.nz)) {
     if (st) break;
-    t->tz = tz;
-    // one untimed step (first use of this launch shape), then the timed ones,
-    // each from the same starting state
-    double ms = 0.0;
-    for (int rep = 0; rep < 2 && !st; ++rep) {
-      if (hipMemcpyAsync(t->buf, s->buf, s->L.total, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
-        st = fail(CSPH_ERR_DEVICE, "copy of the state for a trial run failed");
-        break;
-      }
-      st = write_ctrl(t, c0);
-      if (st) break;
-      const int n = rep == 0 ? 1 : trial_steps;
-      st = time_on(t->stream, [&]() { return launch(t, n, 0.0, INFINITY); }, &ms);
-    }
+    for (int q = 0; q < 3; ++q) t->tz[q] = tz;
+    double ms = 0.0, stages[3];
+    st = trial(&ms, stages);
     if (st) break;
     Ctrl ct{};
     st = read_ctrl(t, &ct);
     if (st) break;
     if (ct.status) continue;  // an invalid trial (the state failed) does not count
-    const double per = ms / trial_steps;
-    if (per < best_ms) {
-      best_ms = per;
-      best = tz;
-    }
+    for (int q = 0; q < 3; ++q)
+      if (stages[q] < best_ms[q]) {
+        best_ms[q] = stages[q];
+        best[q] = tz;
+      }
+  }
+  // the step time at the chosen depths
+  double step_ms = INFINITY;
+  if (!st) {
+    for (int q = 0; q < 3; ++q) t->tz[q] = best[q];
+    double ms = 0.0;
+    st = trial(&ms, nullptr);
+    if (!st) step_ms = ms / trial_steps;
   }
   (void)hipStreamSynchronize(t->stream);
+  for (hipEvent_t e : t->prof_ev) (void)hipEventDestroy(e);
   (void)hipFree(t->buf);
   delete t;
   if (st) return st;
-  s->tz = best;
+  for (int q = 0; q < 3; ++q) s->tz[q] = best[q];
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(s->device, s->desc)] = best;
+    g_tune[tune_key(s->device, s->desc)] = Depths{best[0], best[1], best[2]};
   }
-  if (tz_out) *tz_out = best;
-  if (ms_per_step) *ms_per_step = best_ms;
+  if (tz_out)
+    for (int q = 0; q < 3; ++q) tz_out[q] = best[q];
+  if (ms_per_step) *ms_per_step = step_ms;
   return CSPH_OK;
 }
 
@@ -1019,10 +1054,11 @@ csph_status build_table(csph_batch* b) {
     I.bc = s->bc;
     I.ctrl = s->ctrl;
     I.partials = s->partials;
-    I.tz = s->tz;
-    s->tz_last = s->tz;
+    // a batch sweeps every stage of a member at one depth: its stage-C depth
+    I.tz = s->tz[1];
+    s->tz_last = I.tz;
     if (!default_scheme(s->g)) b->generic = true;
-    const int nt = Launch<Real>::tiles(s->g, s->tz);
+    const int nt = Launch<Real>::tiles(s->g, I.tz);
     for (int t = 0; t < nt; ++t) tmap.push_back(make_int2((int)r, t));
     // each member's ghost cells in whole fill blocks (one member per block)
     const long long ng = Launch<Real>::ghosts(s->g);
@@ -1212,10 +1248,10 @@ csph_status csph_batch_autotune(csph_batch* b, int32_t trial_steps, int32_t* tz_
   // snapshot every member's buffer; each trial starts from it and it is
   // restored at the end, so tuning leaves the members as they were
   std::vector<void*> snap(mem.size(), nullptr);
-  std::vector<int> tz0(mem.size());
+  std::vector<Depths> tz0(mem.size());
   csph_status st = CSPH_OK;
   for (size_t q = 0; q < mem.size() && !st; ++q) {
-    tz0[q] = mem[q]->tz;
+    tz0[q] = Depths{mem[q]->tz[0], mem[q]->tz[1], mem[q]->tz[2]};
     if (hipMalloc(&snap[q], mem[q]->L.total) != hipSuccess) {
       (void)hipGetLastError();
       snap[q] = nullptr;
@@ -1238,7 +1274,8 @@ csph_status csph_batch_autotune(csph_batch* b, int32_t trial_steps, int32_t* tz_
   double best_ms = INFINITY;
   for (int tz : tz_candidates(nzmax)) {
     if (st) break;
-    for (csph_sim* m : mem) m->tz = tz;
+    for (csph_sim* m : mem)
+      for (int q = 0; q < 3; ++q) m->tz[q] = tz;
     b->dirty = true;
     st = b->dtype == CSPH_F64 ? build_table<double>(b) : build_table<float>(b);
     if (st) break;
@@ -1261,7 +1298,7 @@ csph_status csph_batch_autotune(csph_batch* b, int32_t trial_steps, int32_t* tz_
   }
   csph_status st2 = restore();
   for (size_t q = 0; q < mem.size(); ++q) {
-    mem[q]->tz = (st || best < 0) ? tz0[q] : best;
+    for (int r = 0; r < 3; ++r) mem[q]->tz[r] = (st || best < 0) ? tz0[q][r] : best;
     if (snap[q]) (void)hipFree(snap[q]);
   }
   b->dirty = true;

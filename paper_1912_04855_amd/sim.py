@@ -188,22 +188,30 @@ class Sim:
 
     # ------------------------------------------------------------------ tiling
     @property
-    def tile_depth(self) -> int:
-        tz = C.c_int32()
-        check(_lib.load().csph_get_tile_depth(self._h, C.byref(tz)), "csph_get_tile_depth")
-        return tz.value
+    def tile_depth(self) -> tuple:
+        """Tile depths of the stage P, C and E sweeps."""
+        tz = (C.c_int32 * 3)()
+        check(_lib.load().csph_get_tile_depths(self._h, tz), "csph_get_tile_depths")
+        return tuple(int(v) for v in tz)
 
     @tile_depth.setter
-    def tile_depth(self, tz: int):
-        check(_lib.load().csph_set_tile_depth(self._h, int(tz)), "csph_set_tile_depth")
+    def tile_depth(self, tz):
+        """One depth for every stage, or three (stage P, C, E)."""
+        if np.ndim(tz) == 0:
+            check(_lib.load().csph_set_tile_depth(self._h, int(tz)), "csph_set_tile_depth")
+            return
+        v = [int(x) for x in tz]
+        if len(v) != 3:
+            raise ValueError("tile depth: one value or three (stage P, C, E)")
+        check(_lib.load().csph_set_tile_depths(self._h, (C.c_int32 * 3)(*v)), "csph_set_tile_depths")
 
     def autotune(self, trial_steps=3):
-        """Pick the fastest tile depth by timing trial steps on a copy of this
-        simulation (which is not advanced).  Returns (depth, ms per step)."""
-        tz, ms = C.c_int32(), C.c_double()
-        check(_lib.load().csph_autotune(self._h, int(trial_steps), C.byref(tz), C.byref(ms)),
-              "csph_autotune")
-        return tz.value, ms.value
+        """Pick each stage's fastest tile depth by timing trial steps on a copy
+        of this simulation (which is not advanced).  Returns ((P, C, E) depths,
+        ms per step at those depths)."""
+        tz, ms = (C.c_int32 * 3)(), C.c_double()
+        check(_lib.load().csph_autotune(self._h, int(trial_steps), tz, C.byref(ms)), "csph_autotune")
+        return tuple(int(v) for v in tz), ms.value
 
     STAGE_FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
                     "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz"]

@@ -1,6 +1,7 @@
-"""Tile-depth autotuner: the tile depth changes the schedule, never the result;
-tuning a simulation or a batch leaves its state and time untouched; the chosen
-depth is remembered for later simulations of the same shape."""
+"""Tile-depth autotuner: the tile depths (one per stage sweep) change the
+schedule, never the result; tuning a simulation or a batch leaves its state and
+time untouched; the chosen depths are remembered for later simulations of the
+same shape."""
 import math
 
 import numpy as np
@@ -23,11 +24,12 @@ def test_tile_depth_changes_schedule_not_result(dtype):
     need_gpu()
     pr = _problem()
     ref = None
-    for tz in (2, 4, 16, 64):
+    # one depth for all stages, and mixed per-stage depths (stage P, C, E)
+    for tz in (2, 4, 16, 64, (2, 64, 16), (64, 4, 2), (16, 2, 64)):
         announce("tile_depth", dtype, tz, pr.shape)
         s = gpu_sim(pr, dtype)
         s.tile_depth = tz
-        assert s.tile_depth == tz
+        assert s.tile_depth == (tuple(tz) if isinstance(tz, tuple) else (tz, tz, tz))
         assert s.advance(math.inf, 12) == 12
         U = s.conserved()
         # the FP64 totals of the last stage E cover exactly this depth's tiles
@@ -47,9 +49,11 @@ def test_tile_depth_rejects_bad_values():
     need_gpu()
     from paper_1912_04855_amd import _lib
     s = gpu_sim(P.sod(16), "f64")
-    for bad in (0, 1, 65, -3):
+    for bad in (0, 1, 65, -3, (2, 2, 65), (1, 8, 8)):
         with pytest.raises(_lib.CsphError):
             s.tile_depth = bad
+    with pytest.raises(ValueError):
+        s.tile_depth = (8, 8)
     s.close()
 
 
@@ -62,7 +66,7 @@ def test_autotune_leaves_sim_untouched_and_is_remembered(dtype):
     s.advance(math.inf, 3)
     U0, t0 = s.conserved(), s.time()
     tz, ms = s.autotune(trial_steps=2)
-    assert tz in (2, 4, 8, 16, 32, 64) and ms > 0
+    assert len(tz) == 3 and all(d in (2, 4, 8, 16, 32, 64) for d in tz) and ms > 0
     assert s.tile_depth == tz
     assert s.time() == t0
     assert np.array_equal(s.conserved(), U0)
@@ -70,7 +74,7 @@ def test_autotune_leaves_sim_untouched_and_is_remembered(dtype):
     # a fresh simulation of the same shape starts from the tuned depth
     r = gpu_sim(pr, dtype)
     assert r.tile_depth == tz
-    r.tile_depth = 2 if tz != 2 else 4
+    r.tile_depth = 2 if tz != (2, 2, 2) else 4
     r.advance(math.inf, 8)
     assert np.array_equal(s.conserved(), r.conserved())
     s.close()
@@ -101,7 +105,7 @@ def test_batch_autotune_restores_members():
     for s, (U, t) in zip(sims, before):
         assert s.time() == t
         assert np.array_equal(s.conserved(), U)
-        assert s.tile_depth == tz
+        assert s.tile_depth == (tz, tz, tz)
     b.advance(20)
     assert sorted(b.poll()) == sorted(slots)
     for q, s in enumerate(sims):
