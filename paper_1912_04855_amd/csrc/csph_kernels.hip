@@ -55,6 +55,10 @@ constexpr bool kF64 = std::is_same<Real, double>::value;
 // The FP32 build pushes the x-face ghost cells from the stage that writes a
 // field; the FP64 build fills every ghost zone in the fill kernels.
 constexpr bool kPushX = !kF64;
+// The FP64 build stores the predicted offset xi* = (dt/2)(u^n + u*); the FP32
+// build recomputes it from rho, m^n and m* wherever it is needed, which saves
+// stage P three of its eight output fields.
+constexpr bool kKeepXiStar = kF64;
 
 constexpr int kWave = 64;
 constexpr int kXcd = 8;
@@ -154,6 +158,18 @@ __device__ __forceinline__ void primitive(const GridDev& g, Real rho, Real mx, R
   const Real ke = (Real)0.5 * (mx * ux + my * uy + mz * uz);
   const Real pp = (Real)g.gm1 * (E - ke);
   p = pp > (Real)0 ? pp : (Real)0;
+}
+
+// velocity m / rho as primitive() forms it (0 in vacuum)
+__device__ __forceinline__ void velocity(const GridDev& g, Real rho, Real mx, Real my, Real mz, Real u[3]) {
+  Real p_unused;
+  primitive(g, rho, mx, my, mz, (Real)0, u[0], u[1], u[2], p_unused);
+}
+
+// predicted particle offset xi* = (dt/2)(u^n + u*) of a cell, Eq. (5)
+__device__ __forceinline__ void xi_star(const Real un[3], const Real us[3], Real hdt, Real xi[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) xi[d] = hdt * (un[d] + us[d]);
 }
 
 // M4 cubic spline with support 2h: K(d) = -(kappa/h^2) (g(q)/q) d, q = |d|/h,
@@ -376,23 +392,40 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
   if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
-  Real xi[3];
+  const bool first = i >= -1 && i <= g.nx && j >= -1 && j <= g.ny && k >= -1 && k <= g.nz;
+  Real xi[3], ms[3];
   if (kPushX && in_x_zone(g, t)) {
-    // stage P wrote this x ghost's state and offset; psi at its position is left
+    // stage P wrote this x ghost's predicted state; psi at its position is left
     if (i != -1 && i != g.nx) return;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) xi[q] = F.xs[q][cg];
+    for (int q = 0; q < 3; ++q) ms[q] = F.ms[q][cg];
   } else {
     const GhostSrc m = ghost_src(g, bc, i, j, k, false);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) F.ms[q][cg] = ghost_get(bc, m, F.ms[q], kMx + q, dt);
-#pragma unroll
     for (int q = 0; q < 3; ++q) {
-      xi[q] = ghost_get(bc, m, F.xs[q], kXx + q, dt);
-      F.xs[q][cg] = xi[q];
+      ms[q] = ghost_get(bc, m, F.ms[q], kMx + q, dt);
+      F.ms[q][cg] = ms[q];
+    }
+    F.ms[3][cg] = ghost_get(bc, m, F.ms[3], kE, dt);
+    if constexpr (kKeepXiStar) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        xi[q] = ghost_get(bc, m, F.xs[q], kXx + q, dt);
+        F.xs[q][cg] = xi[q];
+      }
     }
   }
-  if (i >= -1 && i <= g.nx && j >= -1 && j <= g.ny && k >= -1 && k <= g.nz) {
+  if (!first) return;
+  if constexpr (!kKeepXiStar) {
+    // the ghost's offset from its own (already filled) rho, m^n and m*
+    const int par = ctrl->par;
+    const Real r = F.U[par][0][cg];
+    Real un[3], us[3];
+    velocity(g, r, F.U[par][1][cg], F.U[par][2][cg], F.U[par][3][cg], un);
+    velocity(g, r, ms[0], ms[1], ms[2], us);
+    xi_star(un, us, (Real)(0.5 * dt), xi);
+  }
+  {
     const Real* P = F.psi;
     auto at = [&](int a, int b, int c) { return P[cg + a + (long long)b * g.sx + (long long)c * g.sxy]; };
     F.psis[cg] = psi_at(g, at, xi[0], xi[1], xi[2]);
@@ -769,12 +802,11 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
       F.ms[3][c] = Es;
       Real us[3], ps;
       primitive(g, rc, ms[0], ms[1], ms[2], Es, us[0], us[1], us[2], ps);
-      const Real hdt = (Real)(0.5 * dt);
       Real xi[3];
+      xi_star(uc, us, (Real)(0.5 * dt), xi);
+      if constexpr (kKeepXiStar) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xi[d] = hdt * (uc[d] + us[d]);
-        F.xs[d][c] = xi[d];
+        for (int d = 0; d < 3; ++d) F.xs[d][c] = xi[d];
       }
       auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
       F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
@@ -787,8 +819,6 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
           F.ms[1][cg] = x_ghost_value(bc, ms[1], kMy, flip, face, dt);
           F.ms[2][cg] = x_ghost_value(bc, ms[2], kMz, flip, face, dt);
           F.ms[3][cg] = x_ghost_value(bc, Es, kE, flip, face, dt);
-#pragma unroll
-          for (int d = 0; d < 3; ++d) F.xs[d][cg] = x_ghost_value(bc, xi[d], kXx + d, flip, face, dt);
         });
       }
     }
@@ -837,9 +867,21 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
       Real ux, uy, uz, p;
       primitive(g, r, MSX[c], MSY[c], MSZ[c], ES[c], ux, uy, uz, p);
       S.rho[s][q] = r;
-      // particle offsets in lattice units in FP32
-      const Real sc = kF64 ? (Real)1 : ih;
-      S.a[s][q] = Quad{F.xs[0][c] * sc, F.xs[1][c] * sc, F.xs[2][c] * sc, sqrt_fast((Real)2 * p)};
+      Real xi[3];
+      if constexpr (kKeepXiStar) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xi[d] = F.xs[d][c];
+      } else {
+        // xi* from rho, m^n and m* (u* = (ux, uy, uz) above), as stage P formed it;
+        // kept in lattice units
+        Real un[3];
+        const Real us[3] = {ux, uy, uz};
+        velocity(g, r, F.U[par][1][c], F.U[par][2][c], F.U[par][3][c], un);
+        xi_star(un, us, (Real)(0.5 * dt), xi);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xi[d] *= ih;
+      }
+      S.a[s][q] = Quad{xi[0], xi[1], xi[2], sqrt_fast((Real)2 * p)};
       S.b[s][q] = Quad{ux, uy, uz, F.psis[c]};
     }
   };
