@@ -59,6 +59,9 @@ constexpr bool kPushX = !kF64;
 // build recomputes it from rho, m^n and m* wherever it is needed, which saves
 // stage P three of its eight output fields.
 constexpr bool kKeepXiStar = kF64;
+// Likewise for the final offset xi^{n+1}: the FP32 build forms it in stage E
+// from rho, m^n, m* and m~, which saves stage C three of its seven outputs.
+constexpr bool kKeepXi = kF64;
 
 constexpr int kWave = 64;
 constexpr int kXcd = 8;
@@ -170,6 +173,32 @@ __device__ __forceinline__ void velocity(const GridDev& g, Real rho, Real mx, Re
 __device__ __forceinline__ void xi_star(const Real un[3], const Real us[3], Real hdt, Real xi[3]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) xi[d] = hdt * (un[d] + us[d]);
+}
+
+// One component of the final particle offset, Eq. (6),
+// xi = xi*/2 + dt (u^n + u~)/4 with xi* = (dt/2)(u^n + u*), from a cell's rho and
+// the component of m^n, m*, m~, in the operations and order that stage C uses
+// (FP32 build: it is not stored there).  c = {dt/2, dt/4, h/2, 1/h}.
+__device__ __forceinline__ Real xi_final(const GridDev& g, Real rho, Real mn, Real ms, Real mt,
+                                         const Real c[4]) {
+  Real un = (Real)0, us = (Real)0, ut = (Real)0;
+  if (rho > (Real)g.rho_vac) {
+    // the velocities exactly as primitive() forms them
+    if constexpr (kF64) {
+      un = mn / rho;
+      us = ms / rho;
+      ut = mt / rho;
+    } else {
+      const Real ir = __builtin_amdgcn_rcpf(rho);
+      un = mn * ir;
+      us = ms * ir;
+      ut = mt * ir;
+    }
+  }
+  const Real hdt = c[0], qdt = c[1], hx = c[2], ih = c[3];
+  Real xc = hdt * (un + us);
+  xc *= ih;
+  return hx * xc + qdt * (un + ut);
 }
 
 // M4 cubic spline with support 2h: K(d) = -(kappa/h^2) (g(q)/q) d, q = |d|/h,
@@ -443,8 +472,10 @@ __device__ __forceinline__ void fill_corr_body(const Fields<Real>& F, const Grid
   const GhostSrc m = ghost_src(g, bc, i, j, k, false);
 #pragma unroll
   for (int q = 0; q < 4; ++q) F.mt[q][cg] = ghost_get(bc, m, F.mt[q], kMx + q, dt);
+  if constexpr (kKeepXi) {
 #pragma unroll
-  for (int q = 0; q < 3; ++q) F.xt[q][cg] = ghost_get(bc, m, F.xt[q], kXx + q, dt);
+    for (int q = 0; q < 3; ++q) F.xt[q][cg] = ghost_get(bc, m, F.xt[q], kXx + q, dt);
+  }
 }
 
 __device__ __forceinline__ void fill_state_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
@@ -1031,7 +1062,7 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         xn[d] = hx * xc[d] + qdt * (un[d] + ut[d]);
-        F.xt[d][c] = xn[d];
+        if constexpr (kKeepXi) F.xt[d][c] = xn[d];
       }
       if (kPushX && (i < 2 || i >= g.nx - 2)) {
         // x ghosts of the post-Lagrange particles
@@ -1041,8 +1072,6 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
           F.mt[1][cg] = x_ghost_value(bc, mt[1], kMy, flip, face, dt);
           F.mt[2][cg] = x_ghost_value(bc, mt[2], kMz, flip, face, dt);
           F.mt[3][cg] = x_ghost_value(bc, Et, kE, flip, face, dt);
-#pragma unroll
-          for (int d = 0; d < 3; ++d) F.xt[d][cg] = x_ghost_value(bc, xn[d], kXx + d, flip, face, dt);
         });
       }
     }
@@ -1192,7 +1221,7 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
 struct PlaneE {
   Real u[5][EP];      // U^n of the current plane, two-cell halo
   Real b[4][HP];      // m~, E~ of the current plane, one-cell halo
-  Real xx[HP], xy[HP];
+  Real xx[HP], xy[HP];  // x/y offsets xi (FP64), or the m*_x, m*_y they are formed from (FP32)
   Real fx[5][NFX];    // x-face fluxes of the tile row by row: face i+1/2, i = x0-1 .. x0+TX-1
   Real fy[5][NFY];    // y-face fluxes: face j+1/2, j = y0-1 .. y0+TY-1
 };
@@ -1202,7 +1231,8 @@ __device__ __forceinline__ int eidx(int ex, int ey) { return ey * EX + ex; }
 
 template <bool kGen>
 __device__ __forceinline__ bool tile_face(const GridDev& g, const Tile& T, const PlaneE& S,
-                                          int axis, int row, int col, Real dt, Real Fo[5]) {
+                                          int axis, int row, int col, Real dt, const Real xc[4],
+                                          Real Fo[5]) {
   Real u4[5][4], bl[5], br[5];
   int hl, hr;
   if (axis == 0) {
@@ -1231,8 +1261,13 @@ __device__ __forceinline__ bool tile_face(const GridDev& g, const Tile& T, const
     bl[1 + v] = S.b[v][hl];
     br[1 + v] = S.b[v][hr];
   }
-  const Real xl = axis == 0 ? S.xx[hl] : S.xy[hl];
-  const Real xr = axis == 0 ? S.xx[hr] : S.xy[hr];
+  Real xl = axis == 0 ? S.xx[hl] : S.xy[hl];
+  Real xr = axis == 0 ? S.xx[hr] : S.xy[hr];
+  if constexpr (!kKeepXi) {
+    // the offsets of the face's two cells from rho, m^n, m* and m~
+    xl = xi_final(g, u4[0][1], u4[1 + axis][1], xl, bl[1 + axis], xc);
+    xr = xi_final(g, u4[0][2], u4[1 + axis][2], xr, br[1 + axis], xc);
+  }
   face_flux<kGen>(g, axis, u4, bl, br, xl, xr, dt, Fo);
   return true;
 }
@@ -1247,6 +1282,8 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
   __shared__ int redb;
   const int par = ctrl->par;
   const Real dt = (Real)ctrl->dt;
+  // dt/2, dt/4, h/2, 1/h for the offsets formed here (FP32)
+  const Real xc[4] = {(Real)(0.5 * ctrl->dt), (Real)(0.25 * ctrl->dt), (Real)(0.5 * g.h), (Real)g.inv_h};
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double smax = 0.0;
@@ -1284,8 +1321,14 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
       }
       ld_base(-1, bq[0]);
       ld_base(0, bq[1]);
-      xq[0] = F.xt[2][c0 - g.sxy];
-      xq[1] = F.xt[2][c0];
+      if constexpr (kKeepXi) {
+        xq[0] = F.xt[2][c0 - g.sxy];
+        xq[1] = F.xt[2][c0];
+      } else {
+        // z offsets at z0-1 and z0 (uq holds U^n at z0-2 .. z0+1)
+        xq[0] = xi_final(g, bq[0][0], uq[3][1], F.ms[2][c0 - g.sxy], bq[0][3], xc);
+        xq[1] = xi_final(g, bq[1][0], uq[3][2], F.ms[2][c0], bq[1][3], xc);
+      }
       face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fz);
       // shift so that uq holds U^n at z0-1 .. z0+2
 #pragma unroll
@@ -1332,13 +1375,13 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
           if constexpr (kF64) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) S.b[v][q] = F.mt[v][c];
-            S.xx[q] = F.xt[0][c];
-            S.xy[q] = F.xt[1][c];
+            S.xx[q] = (kKeepXi ? F.xt : F.ms)[0][c];
+            S.xy[q] = (kKeepXi ? F.xt : F.ms)[1][c];
           } else {
 #pragma unroll
             for (int v = 0; v < 4; ++v) __builtin_amdgcn_global_load_lds(F.mt[v] + c, &S.b[v][qb], 4, 0, 0);
-            __builtin_amdgcn_global_load_lds(F.xt[0] + c, &S.xx[qb], 4, 0, 0);
-            __builtin_amdgcn_global_load_lds(F.xt[1] + c, &S.xy[qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((kKeepXi ? F.xt : F.ms)[0] + c, &S.xx[qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((kKeepXi ? F.xt : F.ms)[1] + c, &S.xy[qb], 4, 0, 0);
           }
         }
       }
@@ -1357,7 +1400,8 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
       Real unext[5];
       if (in) {
         ld_base(dk + 1, bq[1]);
-        xq[1] = F.xt[2][cell(g, i, j, k + 1)];
+        // z offset at k+1 (FP32: its m*_z, the offset is formed below)
+        xq[1] = (kKeepXi ? F.xt : F.ms)[2][cell(g, i, j, k + 1)];
         if (k + 1 < T.z1) ld_col(dk + 3, unext);
       }
       lds_barrier();
@@ -1367,13 +1411,13 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         for (int f = tid; f < NFX + NFY; f += NT) {
           Real Fo[5];
           if (f < NFX) {
-            if (tile_face<kGen>(g, T, S, 0, f / (TX + 1), f % (TX + 1), dt, Fo)) {
+            if (tile_face<kGen>(g, T, S, 0, f / (TX + 1), f % (TX + 1), dt, xc, Fo)) {
 #pragma unroll
               for (int v = 0; v < 5; ++v) S.fx[v][f] = Fo[v];
             }
           } else {
             const int fy = f - NFX;
-            if (tile_face<kGen>(g, T, S, 1, fy / TX, fy % TX, dt, Fo)) {
+            if (tile_face<kGen>(g, T, S, 1, fy / TX, fy % TX, dt, xc, Fo)) {
 #pragma unroll
               for (int v = 0; v < 5; ++v) S.fy[v][fy] = Fo[v];
             }
@@ -1393,6 +1437,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         for (int v = 0; v < 5; ++v) acc[v] = S.fx[v][fxp] - S.fx[v][fxm];
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (S.fy[v][fyp] - S.fy[v][fym]);
+        if constexpr (!kKeepXi) xq[1] = xi_final(g, bq[1][0], uq[3][2], xq[1], bq[1][3], xc);
         face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
         // advance the U^n column queue to k .. k+3 (its loads are complete)
 #pragma unroll

@@ -716,9 +716,9 @@ csph_status csph_get_stage(const csph_sim* s, int32_t which, double* out) {
                       : which < 11 ? s->f64.mt[which - 7] : s->f64.xt[which - 11];
     return download_field<double>(s, src, out);
   }
-  if (which >= 4 && which < 7)
-    return fail(CSPH_ERR_ARG, "the FP32 build does not store xi* (it is recomputed where needed)");
-  const float* src = which < 4 ? s->f32.ms[which] : which < 11 ? s->f32.mt[which - 7] : s->f32.xt[which - 11];
+  if ((which >= 4 && which < 7) || which >= 11)
+    return fail(CSPH_ERR_ARG, "the FP32 build does not store xi* or xi^{n+1} (they are recomputed where needed)");
+  const float* src = which < 4 ? s->f32.ms[which] : s->f32.mt[which - 7];
   return download_field<float>(s, src, out);
 }
 
