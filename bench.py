@@ -37,11 +37,19 @@ ALU_PEAK_NONPACKED = 78.6e12
 VALU_ISSUE = 256 * 4 * 16 * 2.4e9   # lane-instructions/s (one wave64 op per SIMD per 4 clocks)
 
 # Algorithmic bytes per interior cell of each stage kernel, in words (4 B in
-# FP32, 8 B in FP64): every input read once, every output written once.
-#   stage P: read U^n (5) + psi (1);            write m*, E* (4) + xi* (3)
-#   stage C: read rho, m*, E* (5) + xi* (3) + psi (1) + m^n, E^n (4); write m~, E~ (4) + xi (3)
-#   stage E: read U^n (5) + m~, E~ (4) + xi (3); write U^{n+1} (5)
-WORDS = {"stage_p": 13, "stage_c": 20, "stage_e": 17}
+# FP32, 8 B in FP64): every input of the kernel read once, every output written
+# once.  The FP32 build does not store the particle offsets xi*, xi^{n+1}: it
+# forms them from the momenta where they are needed.
+#   stage P: read U^n (5) + psi (1);  write m*, E* (4) + psi(r*) (1)
+#            [FP64 also writes xi* (3)]
+#   stage C: read rho, m*, E* (5) + psi(r*) (1) + m^n, E^n (4);  write m~, E~ (4)
+#            [FP64 reads xi* (3) and writes xi^{n+1} (3)]
+#   stage E: read U^n (5) + m~, E~ (4) + m* (3) [FP64: xi^{n+1} (3)];  write U^{n+1} (5)
+WORDS = {"f32": {"stage_p": 11, "stage_c": 14, "stage_e": 17},
+         "f64": {"stage_p": 14, "stage_c": 20, "stage_e": 17}}
+# What bounds each kernel (rocprofv3 counters): the corrector issues vector-ALU
+# instructions back to back; the predictor and the Eulerian update wait on HBM.
+BOUND = {"stage_p": "hbm", "stage_c": "alu", "stage_e": "hbm"}
 # Algorithmic floating-point operations per interior cell of each stage (each
 # +, -, *, /, sqrt, min, max counted once; a fused multiply-add is two), as the
 # method defines them, not as the kernels happen to issue them:
@@ -124,29 +132,35 @@ def _counters(kernel, dtype, cells):
 
 
 def roofline(prof, cells, dtype):
+    """Roofline of the longest-running stage kernel against the bound it has
+    (HBM bytes or vector-ALU flops), with the other view beside it."""
     word = 8 if dtype == "f64" else 4
-    dom = max(WORDS, key=lambda k: prof[k][0])
+    W = WORDS[dtype]
+    dom = max(W, key=lambda k: prof[k][0])
     sec = prof[dom][0] * 1e-3
-    bytes_per_launch = WORDS[dom] * word * cells
+    bytes_per_launch = W[dom] * word * cells
     flops_per_launch = FLOPS[dom] * cells
     gbps = bytes_per_launch / sec / 1e9
     tflops = flops_per_launch / sec / 1e12
     rec = _counters(KERNEL_NAMES[dom], dtype, cells)
-    per = {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1],
-               "GBps": round(WORDS[k] * word * cells / (prof[k][0] * 1e-3) / 1e9, 1),
+    traffic = rec["bytes_per_launch"] if rec else None
+    per = {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1], "bound": BOUND[k],
+               "GBps": round(W[k] * word * cells / (prof[k][0] * 1e-3) / 1e9, 1),
                "TFLOPs": round(FLOPS[k] * cells / (prof[k][0] * 1e-3) / 1e12, 2)}
-           for k in WORDS}
-    out = {"bound": "alu", "kernel": KERNEL_NAMES[dom], "achieved": round(tflops, 2),
-           "peak": ALU_PEAK[dtype] / 1e12, "unit": "TFLOP/s",
-           "frac": round(tflops * 1e12 / ALU_PEAK[dtype], 4),
-           "traffic": rec["bytes_per_launch"] if rec else None,
-           "flops_per_launch": flops_per_launch,
+           for k in W}
+    alu = {"achieved": round(tflops, 2), "peak": ALU_PEAK[dtype] / 1e12, "unit": "TFLOP/s",
+           "frac": round(tflops * 1e12 / ALU_PEAK[dtype], 4), "flops_per_launch": flops_per_launch,
            "peak_nonpacked": ALU_PEAK_NONPACKED / 1e12,
-           "frac_nonpacked": round(tflops * 1e12 / ALU_PEAK_NONPACKED, 4),
-           "hbm": {"achieved": round(gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                   "frac": round(gbps * 1e9 / HBM_PEAK, 4), "bytes_per_launch": bytes_per_launch,
-                   "traffic": rec["bytes_per_launch"] if rec else None},
-           "kernels": per}
+           "frac_nonpacked": round(tflops * 1e12 / ALU_PEAK_NONPACKED, 4)}
+    hbm = {"achieved": round(gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+           "frac": round(gbps * 1e9 / HBM_PEAK, 4), "bytes_per_launch": bytes_per_launch,
+           "traffic": traffic}
+    if traffic:
+        hbm["traffic_GBps"] = round(traffic / sec / 1e9, 1)
+    main = hbm if BOUND[dom] == "hbm" else alu
+    out = {"bound": BOUND[dom], "kernel": KERNEL_NAMES[dom], "achieved": main["achieved"],
+           "peak": main["peak"], "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
+           "alu": alu, "hbm": hbm, "kernels": per}
     if rec and rec.get("valu_per_cell"):
         # VALU issue utilisation from the counted instructions per cell
         out["valu_issue_frac"] = round(rec["valu_per_cell"] * cells / sec / VALU_ISSUE, 3)
