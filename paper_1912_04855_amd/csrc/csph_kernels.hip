@@ -1330,16 +1330,13 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         xq[1] = xi_final(g, bq[1][0], uq[3][2], F.ms[2][c0], bq[1][3], xc);
       }
       face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fz);
-      // shift so that uq holds U^n at z0-1 .. z0+2
+      // shift so that uq holds U^n at z0-1 .. z0+1 (z0+2 comes in the first plane)
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         uq[v][0] = uq[v][1];
         uq[v][1] = uq[v][2];
         uq[v][2] = uq[v][3];
       }
-      ld_col(2, t);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) uq[v][3] = t[v];
 #pragma unroll
       for (int v = 0; v < 5; ++v) bq[0][v] = bq[1][v];
       xq[0] = xq[1];
@@ -1395,14 +1392,17 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
     for (int k = T.z0; k < T.z1; ++k) {
       const int dk = k - T.z0;
       if constexpr (kF64) plane_load(k);
-      // own column for the z faces: base and z offset at k+1 (this plane's upper
-      // face) and U^n at k+3 (the next plane's); in flight during the x-y faces
-      Real unext[5];
+      // own column for this plane's upper z face: base and z offset at k+1, U^n
+      // at k+2; in flight during the x-y faces.  (Loaded one plane ahead of the
+      // copy of plane k+2, so that the copy finds these lines in L2.)
       if (in) {
         ld_base(dk + 1, bq[1]);
         // z offset at k+1 (FP32: its m*_z, the offset is formed below)
         xq[1] = (kKeepXi ? F.xt : F.ms)[2][cell(g, i, j, k + 1)];
-        if (k + 1 < T.z1) ld_col(dk + 3, unext);
+        Real t[5];
+        ld_col(dk + 2, t);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) uq[v][3] = t[v];
       }
       lds_barrier();
       {
@@ -1439,13 +1439,12 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (S.fy[v][fyp] - S.fy[v][fym]);
         if constexpr (!kKeepXi) xq[1] = xi_final(g, bq[1][0], uq[3][2], xq[1], bq[1][3], xc);
         face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
-        // advance the U^n column queue to k .. k+3 (its loads are complete)
+        // advance the U^n column queue to k .. k+2
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           uq[v][0] = uq[v][1];
           uq[v][1] = uq[v][2];
           uq[v][2] = uq[v][3];
-          if (k + 1 < T.z1) uq[v][3] = unext[v];
         }
       }
       // the plane buffers are free: start the next plane, which lands while the
