@@ -282,6 +282,17 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A 64-bit byte offset kept as one value in a register pair: the compiler would
+// otherwise split base + row + column + plane again for every field it is added to.
+__device__ __forceinline__ long long opaque(long long v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T* at_bytes(T* base, long long bytes) {
+  return (T*)((char*)base + bytes);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -1348,37 +1359,43 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
     // updates; the barrier that ends the iteration waits for it.  Each wave
     // stages 64 consecutive plane cells, which land at consecutive LDS words.
     auto plane_load = [&](int k) {
-      const long long dz = (long long)k * g.sxy;
+      // index of plane k's cell (-2, -2) (a scalar); in-plane offsets fit in 32 bits
+      const long long pz = cell(g, -kGhost, -kGhost, k);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int q = tid + h * NT, qb = h * NT + (tid & ~(kWave - 1));
+        const int q = tid + h * NT;
+        // this wave's 64 consecutive plane cells start at LDS word qb (a scalar)
+        const int qb = __builtin_amdgcn_readfirstlane(h * NT + (tid & ~(kWave - 1)));
         const int ex = q % EX, ey = q / EX;
         const int ii = T.x0 - 2 + ex, jj = T.y0 - 2 + ey;
         if (q < EP && ii <= g.nx + 1 && jj <= g.ny + 1) {
-          const long long c = cell(g, ii, jj, 0) + dz;
+          const int r = (jj + kGhost) * g.sx + (ii + kGhost);
+          const long long ob = opaque((pz + r) * (long long)sizeof(Real));
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
             if constexpr (kF64) {
-              S.u[v][q] = Un[v][c];
+              S.u[v][q] = *at_bytes(Un[v], ob);
             } else {
-              __builtin_amdgcn_global_load_lds(Un[v] + c, &S.u[v][qb], 4, 0, 0);
+              __builtin_amdgcn_global_load_lds(at_bytes(Un[v], ob), &S.u[v][qb], 4, 0, 0);
             }
           }
         }
         const int hx = q % HX, hy = q / HX;
         const int ib = T.x0 - 1 + hx, jb = T.y0 - 1 + hy;
         if (q < HP && ib <= g.nx && jb <= g.ny) {
-          const long long c = cell(g, ib, jb, 0) + dz;
+          const int r = (jb + kGhost) * g.sx + (ib + kGhost);
+          const long long ob = opaque((pz + r) * (long long)sizeof(Real));
+          Real* const* X = kKeepXi ? F.xt : F.ms;
           if constexpr (kF64) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) S.b[v][q] = F.mt[v][c];
-            S.xx[q] = (kKeepXi ? F.xt : F.ms)[0][c];
-            S.xy[q] = (kKeepXi ? F.xt : F.ms)[1][c];
+            for (int v = 0; v < 4; ++v) S.b[v][q] = *at_bytes(F.mt[v], ob);
+            S.xx[q] = *at_bytes(X[0], ob);
+            S.xy[q] = *at_bytes(X[1], ob);
           } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) __builtin_amdgcn_global_load_lds(F.mt[v] + c, &S.b[v][qb], 4, 0, 0);
-            __builtin_amdgcn_global_load_lds((kKeepXi ? F.xt : F.ms)[0] + c, &S.xx[qb], 4, 0, 0);
-            __builtin_amdgcn_global_load_lds((kKeepXi ? F.xt : F.ms)[1] + c, &S.xy[qb], 4, 0, 0);
+            for (int v = 0; v < 4; ++v) __builtin_amdgcn_global_load_lds(at_bytes(F.mt[v], ob), &S.b[v][qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(at_bytes(X[0], ob), &S.xx[qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(at_bytes(X[1], ob), &S.xy[qb], 4, 0, 0);
           }
         }
       }

@@ -110,6 +110,8 @@ bool desc_ok(const csph_grid_desc* d, std::string* why) {
     *why = "dtype must be CSPH_F32 or CSPH_F64";
     return false;
   }
+  // at most 4e9 padded cells; with nz >= 4 a padded x-y plane then holds fewer
+  // than 5e8 cells, so the kernels index within a plane in 32 bits
   const double cells = (double)(d->nx + 4) * (d->ny + 4) * (d->nz + 4);
   if (cells > 4.0e9) {
     *why = "grid too large";
