@@ -85,6 +85,11 @@ def _tile(depths):
 
 
 def run_gpu(prob, dtype, steps, warmup, autotune=True, tile_depth=0):
+    """Warm-up, then two timed passes of `steps` steps each.  The first has HIP
+    events only at its two ends and gives the throughput; the second records
+    events around every kernel (an event between two kernels costs a few
+    microseconds of idle time, so the first pass leaves them out) and gives each
+    kernel's average launch duration."""
     import torch
     from paper_1912_04855_amd.sim import from_problem
 
@@ -98,9 +103,7 @@ def run_gpu(prob, dtype, steps, warmup, autotune=True, tile_depth=0):
     if warmup:
         sim.advance(math.inf, warmup)
     torch.cuda.synchronize()
-    sim.profile(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     n = sim.advance(math.inf, steps)
@@ -108,8 +111,13 @@ def run_gpu(prob, dtype, steps, warmup, autotune=True, tile_depth=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
+    assert n == steps, (n, steps)
+    # kernel durations: the same number of steps with events around each kernel
+    sim.profile(True)
+    n = sim.advance(math.inf, steps)
     prof = sim.profile_read()
     sim.profile(False)
+    torch.cuda.synchronize()
     assert n == steps, (n, steps)
     t, nsteps = sim.time()
     sim.close()

@@ -711,20 +711,23 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
 
   auto load = [&](int k) {
     const int s = ring3(k);
+    const long long pz = cell(g, -kGhost, -kGhost, k);  // plane k's first cell (a scalar)
     for (int q = tid; q < HP; q += NT) {
       const int hx = q % HX, hy = q / HX;
       const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
       if (ii > g.nx || jj > g.ny) continue;
-      const long long c = cell(g, ii, jj, k);
-      const Real r = R[c];
+      // one byte offset for every field of the cell (in-plane part in 32 bits)
+      const long long ob = opaque((pz + (jj + kGhost) * g.sx + (ii + kGhost)) * (long long)sizeof(Real));
+      const Real r = *at_bytes(R, ob);
       Real ux, uy, uz, p;
-      primitive(g, r, MX[c], MY[c], MZ[c], EE[c], ux, uy, uz, p);
+      primitive(g, r, *at_bytes(MX, ob), *at_bytes(MY, ob), *at_bytes(MZ, ob), *at_bytes(EE, ob), ux, uy,
+                uz, p);
       S.rho[s][q] = r;
       S.phi[s][q] = sqrt_fast((Real)2 * p);
       S.ux[s][q] = ux;
       S.uy[s][q] = uy;
       S.uz[s][q] = uz;
-      S.psi[s][q] = PS[c];
+      S.psi[s][q] = *at_bytes(PS, ob);
     }
   };
 
@@ -900,31 +903,35 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
 
   auto load = [&](int k) {
     const int s = ring3(k);
+    const long long pz = cell(g, -kGhost, -kGhost, k);  // plane k's first cell (a scalar)
     for (int q = tid; q < HP; q += NT) {
       const int hx = q % HX, hy = q / HX;
       const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
       if (ii > g.nx || jj > g.ny) continue;
-      const long long c = cell(g, ii, jj, k);
-      const Real r = R[c];
+      // one byte offset for every field of the cell (in-plane part in 32 bits)
+      const long long ob = opaque((pz + (jj + kGhost) * g.sx + (ii + kGhost)) * (long long)sizeof(Real));
+      const Real r = *at_bytes(R, ob);
       Real ux, uy, uz, p;
-      primitive(g, r, MSX[c], MSY[c], MSZ[c], ES[c], ux, uy, uz, p);
+      primitive(g, r, *at_bytes(MSX, ob), *at_bytes(MSY, ob), *at_bytes(MSZ, ob), *at_bytes(ES, ob), ux,
+                uy, uz, p);
       S.rho[s][q] = r;
       Real xi[3];
       if constexpr (kKeepXiStar) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) xi[d] = F.xs[d][c];
+        for (int d = 0; d < 3; ++d) xi[d] = *at_bytes(F.xs[d], ob);
       } else {
         // xi* from rho, m^n and m* (u* = (ux, uy, uz) above), as stage P formed it;
         // kept in lattice units
         Real un[3];
         const Real us[3] = {ux, uy, uz};
-        velocity(g, r, F.U[par][1][c], F.U[par][2][c], F.U[par][3][c], un);
+        velocity(g, r, *at_bytes(F.U[par][1], ob), *at_bytes(F.U[par][2], ob), *at_bytes(F.U[par][3], ob),
+                 un);
         xi_star(un, us, (Real)(0.5 * dt), xi);
 #pragma unroll
         for (int d = 0; d < 3; ++d) xi[d] *= ih;
       }
       S.a[s][q] = Quad{xi[0], xi[1], xi[2], sqrt_fast((Real)2 * p)};
-      S.b[s][q] = Quad{ux, uy, uz, F.psis[c]};
+      S.b[s][q] = Quad{ux, uy, uz, *at_bytes(F.psis, ob)};
     }
   };
 
