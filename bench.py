@@ -168,7 +168,11 @@ def roofline(prof, cells, dtype):
     main = hbm if BOUND[dom] == "hbm" else alu
     out = {"bound": BOUND[dom], "kernel": KERNEL_NAMES[dom], "achieved": main["achieved"],
            "peak": main["peak"], "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
-           "alu": alu, "hbm": hbm, "kernels": per}
+           "alu": alu, "hbm": hbm, "kernels": per,
+           # the step's other launches: three ghost fills (the first timed with the
+           # step's opening launch) and the closing bookkeeping launch
+           "other_kernels": {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1]}
+                             for k in ("ghost_fill", "bookkeeping") if k in prof}}
     if rec and rec.get("valu_per_cell"):
         # VALU issue utilisation from the counted instructions per cell
         out["valu_issue_frac"] = round(rec["valu_per_cell"] * cells / sec / VALU_ISSUE, 3)
