@@ -42,7 +42,11 @@ csph_status fail(csph_status code, const std::string& msg) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-constexpr int kNumFields = 26;  // U[2][5], psi, ms[4], xs[3], psis, mt[4], xt[3]
+// device fields: U[2][5], psi, ms[4], (xs[3]), psis, mt[4], (xt[3]); the FP32
+// build forms the particle offsets xs, xt where it needs them and has no storage
+// for them
+constexpr int kNumFields64 = 26, kNumFields32 = 20;
+int num_fields(int dtype) { return dtype == CSPH_F64 ? kNumFields64 : kNumFields32; }
 
 // tile depths (z-planes per workgroup of the stencil sweeps) the autotuner tries
 constexpr int kTzMin = 2, kTzMax = 64;
@@ -170,7 +174,7 @@ Layout make_layout(const csph_grid_desc* d) {
   L.ncell = g.ncell;
   L.field_bytes = align_up((size_t)g.ncell * es);
   L.fields_off = 0;
-  L.ctrl_off = L.fields_off + (size_t)kNumFields * L.field_bytes;
+  L.ctrl_off = L.fields_off + (size_t)num_fields(d->dtype) * L.field_bytes;
   // per-tile totals of stage E, sized for the shallowest tile depth a sim may use
   L.nblocks = d->dtype == CSPH_F64 ? Launch<double>::tiles(g, kTzMin) : Launch<float>::tiles(g, kTzMin);
   L.partials_off = L.ctrl_off + align_up(sizeof(Ctrl));
@@ -226,11 +230,12 @@ void bind_fields(csph_sim* s, Fields<Real>& F) {
   for (int p = 0; p < 2; ++p)
     for (int v = 0; v < 5; ++v) F.U[p][v] = (Real*)s->field_ptr(k++);
   F.psi = (Real*)s->field_ptr(k++);
+  const bool offsets = s->is_f64();  // only the FP64 build stores xi*, xi^{n+1}
   for (int v = 0; v < 4; ++v) F.ms[v] = (Real*)s->field_ptr(k++);
-  for (int v = 0; v < 3; ++v) F.xs[v] = (Real*)s->field_ptr(k++);
+  for (int v = 0; v < 3; ++v) F.xs[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
   F.psis = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 4; ++v) F.mt[v] = (Real*)s->field_ptr(k++);
-  for (int v = 0; v < 3; ++v) F.xt[v] = (Real*)s->field_ptr(k++);
+  for (int v = 0; v < 3; ++v) F.xt[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
 }
 
 // a batch member's device state is written on the batch's stream: reads of it
