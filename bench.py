@@ -45,8 +45,9 @@ VALU_ISSUE = 256 * 4 * 16 * 2.4e9   # lane-instructions/s (one wave64 op per SIM
 #   stage C: read rho, m*, E* (5) + psi(r*) (1) + m^n, E^n (4);  write m~, E~ (4)
 #            [FP64 reads xi* (3) and writes xi^{n+1} (3)]
 #   stage E: read U^n (5) + m~, E~ (4) + m* (3) [FP64: xi^{n+1} (3)];  write U^{n+1} (5)
-WORDS = {"f32": {"stage_p": 11, "stage_c": 14, "stage_e": 17},
-         "f64": {"stage_p": 14, "stage_c": 20, "stage_e": 17}}
+RW = {"f32": {"stage_p": (6, 5), "stage_c": (10, 4), "stage_e": (12, 5)},
+      "f64": {"stage_p": (6, 8), "stage_c": (13, 7), "stage_e": (12, 5)}}
+WORDS = {t: {k: r + w for k, (r, w) in m.items()} for t, m in RW.items()}
 # What bounds each kernel (rocprofv3 counters): the corrector issues vector-ALU
 # instructions back to back; the predictor and the Eulerian update wait on HBM.
 BOUND = {"stage_p": "hbm", "stage_c": "alu", "stage_e": "hbm"}
@@ -139,12 +140,35 @@ def _counters(kernel, dtype, cells):
     return None
 
 
-def roofline(prof, cells, dtype):
+def dominant(prof, dtype):
+    """The stage kernel with the longest average launch."""
+    return max(WORDS[dtype], key=lambda k: prof[k][0])
+
+
+def stream_ceiling(kernel, dtype, cells, reps=10):
+    """GB/s of a plain streaming kernel with `kernel`'s mix of read and write
+    streams over the interior cells (no halos, address order): the rate HBM
+    gives that mix of bytes."""
+    import ctypes as C
+    import torch
+    from paper_1912_04855_amd import _lib
+    r, w = RW[dtype][kernel]
+    words = cells * (2 if dtype == "f64" else 1)
+    ms = C.c_double()
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    st = _lib.load().csph_stream_probe(r, w, words, reps, stream, C.byref(ms))
+    if st != 0:
+        raise RuntimeError(f"csph_stream_probe failed with status {st}")
+    return (r + w) * words * 4 / (ms.value * 1e-3) / 1e9
+
+
+def roofline(prof, cells, dtype, stream_gbps=None):
     """Roofline of the longest-running stage kernel against the bound it has
-    (HBM bytes or vector-ALU flops), with the other view beside it."""
+    (HBM bytes or vector-ALU flops), with the other view beside it; with
+    `stream_gbps`, its HBM rate also against that kernel's streaming reference."""
     word = 8 if dtype == "f64" else 4
     W = WORDS[dtype]
-    dom = max(W, key=lambda k: prof[k][0])
+    dom = dominant(prof, dtype)
     sec = prof[dom][0] * 1e-3
     bytes_per_launch = W[dom] * word * cells
     flops_per_launch = FLOPS[dom] * cells
@@ -165,6 +189,11 @@ def roofline(prof, cells, dtype):
            "traffic": traffic}
     if traffic:
         hbm["traffic_GBps"] = round(traffic / sec / 1e9, 1)
+    if stream_gbps:
+        hbm["stream_reference"] = {
+            "GBps": round(stream_gbps, 1), "frac": round(gbps / stream_gbps, 4),
+            "what": "a plain kernel with the same read/write stream mix over the interior cells "
+                    "(no halos, address order)"}
     main = hbm if BOUND[dom] == "hbm" else alu
     out = {"bound": BOUND[dom], "kernel": KERNEL_NAMES[dom], "achieved": main["achieved"],
            "peak": main["peak"], "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
@@ -341,7 +370,13 @@ def main():
     value = cells * args.steps / (r["event_ms"] * 1e-3)
     log(f"[bench] {ms_step:.3f} ms/step, {value:.3e} cell-updates/s "
         f"(wall {r['wall_s']:.3f} s)")
-    rl = roofline(r["profile"], cells, args.dtype)
+    dom = dominant(r["profile"], args.dtype)
+    try:
+        ref = stream_ceiling(dom, args.dtype, cells)
+    except Exception as e:  # the roofline stands without the reference
+        log(f"[bench] streaming reference failed: {e}")
+        ref = None
+    rl = roofline(r["profile"], cells, args.dtype, ref)
     out = {
         "metric": "cell-updates/s", "value": round(value, 1), "unit": "cell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -167,6 +167,17 @@ const char* csph_last_error(void);
 csph_status csph_profile_enable(csph_sim* sim, int32_t on);
 csph_status csph_profile_read(csph_sim* sim, double* avg_ms, int64_t* launches, int32_t n);
 
+/* Streaming reference (benchmark support, not part of the method): the average
+ * time in milliseconds of one pass of a kernel that reads `reads` (1..16) and
+ * writes `writes` (1..16) device arrays of `words` 4-byte words, each element
+ * once, in address order, on hip_stream (NULL = the default stream), over `reps`
+ * timed passes after one untimed pass.  This is the mix of HBM streams a stage
+ * kernel moves, without its halos; the rate it reaches is a practical ceiling
+ * for that kernel's bytes.  The arrays are allocated and freed inside the call.
+ * Returns CSPH_ERR_ARG, CSPH_ERR_NOMEM or CSPH_ERR_DEVICE (no message is set). */
+csph_status csph_stream_probe(int32_t reads, int32_t writes, int64_t words, int32_t reps,
+                              void* hip_stream, double* ms_per_pass);
+
 /* Choose the Eulerian-stage limiter and flux (see csph_limiter / csph_flux);
  * applies from the next step.  CSPH_ERR_ARG for unknown values or a batch
  * member.  csph_get_scheme returns the current pair (either pointer may be NULL). */

@@ -31,7 +31,7 @@ EXPORTS = [
     "csph_batch_poll", "csph_batch_remove", "csph_batch_destroy", "csph_profile_enable",
     "csph_profile_read", "csph_set_tile_depth", "csph_set_tile_depths", "csph_get_tile_depths",
     "csph_autotune",
-    "csph_batch_autotune", "csph_set_scheme", "csph_get_scheme",
+    "csph_batch_autotune", "csph_set_scheme", "csph_get_scheme", "csph_stream_probe",
 ]
 
 
@@ -88,6 +88,7 @@ def load():
         "csph_set_tile_depth": (st, [vp, C.c_int32]),
         "csph_set_tile_depths": (st, [vp, C.POINTER(C.c_int32)]),
         "csph_get_tile_depths": (st, [vp, C.POINTER(C.c_int32)]),
+        "csph_stream_probe": (st, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, vp, dp]),
         "csph_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
         "csph_batch_autotune": (st, [vp, C.c_int32, C.POINTER(C.c_int32), dp]),
         "csph_set_scheme": (st, [vp, C.c_int32, C.c_int32]),

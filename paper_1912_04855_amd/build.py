@@ -31,6 +31,7 @@ UNITS = [
                                    "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
     ("csph_kernels.hip", "k64.o", ["-DCSPH_REAL=double", "-DCSPH_IS_DOUBLE=1", "-ffp-contract=off"]),
     ("csph_runtime.hip", "runtime.o", ["-ffp-contract=off"]),
+    ("csph_stream.hip", "stream.o", []),
 ]
 
 

@@ -41,3 +41,13 @@ def test_required_bytes_and_argument_errors():
     assert L.csph_create(C.byref(bad), None, C.byref(out)) == _lib.ERR_ARG
     assert b"nx" in L.csph_last_error()
     assert L.csph_destroy(None) == _lib.OK
+
+
+def test_stream_probe_rejects_bad_arguments():
+    import ctypes as C
+    L = _lib.load()
+    ms = C.c_double()
+    for r, w, n, reps in ((0, 1, 1024, 1), (17, 1, 1024, 1), (1, 0, 1024, 1), (1, 17, 1024, 1),
+                          (1, 1, 0, 1), (1, 1, 1024, 0)):
+        assert L.csph_stream_probe(r, w, n, reps, None, C.byref(ms)) == _lib.ERR_ARG
+    assert L.csph_stream_probe(1, 1, 1024, 1, None, None) == _lib.ERR_ARG
