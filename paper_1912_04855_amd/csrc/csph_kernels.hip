@@ -432,7 +432,10 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
   if (!ghost_cell(g, t, i, j, k)) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
+  // the predicted state is read one cell beyond the interior only (stage C's
+  // halo, stage E's one-cell halo): the second ghost layer is left unfilled
   const bool first = i >= -1 && i <= g.nx && j >= -1 && j <= g.ny && k >= -1 && k <= g.nz;
+  if (!first) return;
   Real xi[3], ms[3];
   if (kPushX && in_x_zone(g, t)) {
     // stage P wrote this x ghost's predicted state; psi at its position is left
@@ -455,7 +458,6 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
       }
     }
   }
-  if (!first) return;
   if constexpr (!kKeepXiStar) {
     // the ghost's offset from its own (already filled) rho, m^n and m*
     const int par = ctrl->par;
@@ -478,6 +480,8 @@ __device__ __forceinline__ void fill_corr_body(const Fields<Real>& F, const Grid
   int i, j, k;
   if (!ghost_cell(g, t, i, j, k)) return;
   if (kPushX && in_x_zone(g, t)) return;  // written by stage C
+  // read one cell beyond the interior only (stage E's one-cell halo)
+  if (i < -1 || i > g.nx || j < -1 || j > g.ny || k < -1 || k > g.nz) return;
   const double dt = ctrl->dt;
   const long long cg = cell(g, i, j, k);
   const GhostSrc m = ghost_src(g, bc, i, j, k, false);
