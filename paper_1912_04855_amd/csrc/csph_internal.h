@@ -43,6 +43,9 @@ struct GridDev {
   double hoff[13][3];
   // Eulerian-stage scheme: TVD limiter and face flux (kLim*, kFlux*)
   int limiter, flux;
+  // 1 if a potential was set; 0: psi = 0 everywhere, and psi(r*) stays 0 without
+  // being loaded, interpolated or stored
+  int psi;
 };
 
 enum : int { kLimMinmod = 0, kLimMC = 1, kLimVanLeer = 2, kLimSuperbee = 3 };

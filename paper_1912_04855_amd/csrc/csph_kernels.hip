@@ -440,6 +440,7 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
   if (kPushX && in_x_zone(g, t)) {
     // stage P wrote this x ghost's predicted state; psi at its position is left
     if (i != -1 && i != g.nx) return;
+    if (!g.psi) return;  // psi(r*) stays 0
 #pragma unroll
     for (int q = 0; q < 3; ++q) ms[q] = F.ms[q][cg];
   } else {
@@ -458,6 +459,7 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
       }
     }
   }
+  if (!g.psi) return;  // psi(r*) stays 0
   if constexpr (!kKeepXiStar) {
     // the ghost's offset from its own (already filled) rho, m^n and m*
     const int par = ctrl->par;
@@ -698,9 +700,11 @@ struct PlaneP {
   Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP], psi[3][HP];
 };
 
-__device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+// kPsi: a potential is set (g.psi); without one psi = 0 and psi(r*) stays 0.
+// The plane buffers S belong to the kernel, so both forms share them.
+template <bool kPsi>
+__device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              const Ctrl* __restrict__ ctrl, const Tile& T) {
-  __shared__ PlaneP S;
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
   const Real* __restrict__ MX = F.U[par][1];
@@ -731,7 +735,7 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
       S.ux[s][q] = ux;
       S.uy[s][q] = uy;
       S.uz[s][q] = uz;
-      S.psi[s][q] = *at_bytes(PS, ob);
+      S.psi[s][q] = kPsi ? *at_bytes(PS, ob) : (Real)0;
     }
   };
 
@@ -857,8 +861,10 @@ __device__ __forceinline__ void stage_p_body(const Fields<Real>& F, const GridDe
 #pragma unroll
         for (int d = 0; d < 3; ++d) F.xs[d][c] = xi[d];
       }
-      auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
-      F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
+      if constexpr (kPsi) {
+        auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
+        F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
+      }
       if (kPushX && (i < 2 || i >= g.nx - 2)) {
         // x ghosts of the predicted particles (psi at their positions is left to
         // the fill kernel: it needs loads that would stall this sweep)
@@ -890,9 +896,9 @@ struct PlaneC {
   Real rho[3][HP];
 };
 
-__device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+template <bool kPsi>
+__device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              const Ctrl* __restrict__ ctrl, const Tile& T) {
-  __shared__ PlaneC S;
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
   const Real* __restrict__ MSX = F.ms[0];
@@ -935,7 +941,7 @@ __device__ __forceinline__ void stage_c_body(const Fields<Real>& F, const GridDe
         for (int d = 0; d < 3; ++d) xi[d] *= ih;
       }
       S.a[s][q] = Quad{xi[0], xi[1], xi[2], sqrt_fast((Real)2 * p)};
-      S.b[s][q] = Quad{ux, uy, uz, *at_bytes(F.psis, ob)};
+      S.b[s][q] = Quad{ux, uy, uz, kPsi ? *at_bytes(F.psis, ob) : (Real)0};
     }
   };
 
@@ -1551,7 +1557,9 @@ __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  stage_p_body(F, g, bc, ctrl, T);
+  __shared__ PlaneP S;
+  if (g.psi) stage_p_body<true>(S, F, g, bc, ctrl, T);
+  else stage_p_body<false>(S, F, g, bc, ctrl, T);
 }
 
 __global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g, BcDev bc,
@@ -1560,7 +1568,9 @@ __global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g, Bc
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  stage_c_body(F, g, bc, ctrl, T);
+  __shared__ PlaneC S;
+  if (g.psi) stage_c_body<true>(S, F, g, bc, ctrl, T);
+  else stage_c_body<false>(S, F, g, bc, ctrl, T);
 }
 
 template <bool kGen>
@@ -1585,9 +1595,15 @@ __global__ void __launch_bounds__(NT, 2) k_stage_batch(const Inst<Real>* __restr
   if (!I.ctrl->active) return;
   Tile T;
   tile_at(I.g, I.tz, w.y, T);
-  if (kStage == 0) stage_p_body(I.F, I.g, I.bc, I.ctrl, T);
-  else if (kStage == 1) stage_c_body(I.F, I.g, I.bc, I.ctrl, T);
-  else if (!kGen || default_scheme(I.g))
+  if constexpr (kStage == 0) {
+    __shared__ PlaneP S;
+    if (I.g.psi) stage_p_body<true>(S, I.F, I.g, I.bc, I.ctrl, T);
+    else stage_p_body<false>(S, I.F, I.g, I.bc, I.ctrl, T);
+  } else if constexpr (kStage == 1) {
+    __shared__ PlaneC S;
+    if (I.g.psi) stage_c_body<true>(S, I.F, I.g, I.bc, I.ctrl, T);
+    else stage_c_body<false>(S, I.F, I.g, I.bc, I.ctrl, T);
+  } else if (!kGen || default_scheme(I.g))
     stage_e_body<false>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);
   else
     stage_e_body<true>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);

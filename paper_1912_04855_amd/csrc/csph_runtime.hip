@@ -164,6 +164,7 @@ GridDev make_grid(const csph_grid_desc* d) {
   }
   g.limiter = kLimMinmod;
   g.flux = kFluxSweptAV;
+  g.psi = 0;
   return g;
 }
 
@@ -553,6 +554,12 @@ csph_status csph_set_potential(csph_sim* s, const double* host_psi) {
   csph_status st = s->is_f64() ? upload_field<double>(s, s->f64.psi, s->psi_host.data())
                             : upload_field<float>(s, s->f32.psi, s->psi_host.data());
   if (st) return st;
+  if (!host_psi && s->g.psi) {
+    // without a potential the kernels leave psi(r*) alone: it must be 0 everywhere
+    void* f = s->is_f64() ? (void*)s->f64.psis : (void*)s->f32.psis;
+    HIP_TRY(hipMemsetAsync(f, 0, s->L.field_bytes, s->stream));
+  }
+  s->g.psi = host_psi ? 1 : 0;
   s->psi_dirty = true;
   return CSPH_OK;
 }

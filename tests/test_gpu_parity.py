@@ -235,3 +235,33 @@ def test_torch_memory_and_stream():
         U = g.conserved()
     assert rel_l1_vars(U, o.conserved()) <= 1e-12
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_potential_cleared_equals_never_set(dtype):
+    """Without a potential the kernels leave psi(r*) at 0 instead of interpolating
+    it: a simulation whose potential is cleared after a few steps must then
+    behave exactly like one that never had one."""
+    need_gpu()
+    pr = P.random_state((12, 10, 9), seed=7, potential=True,
+                        bc=(P.OUTFLOW, P.OUTFLOW, P.REFLECT, P.REFLECT, P.PERIODIC, P.PERIODIC))
+    flat = P.random_state((12, 10, 9), seed=7, potential=False,
+                          bc=(P.OUTFLOW, P.OUTFLOW, P.REFLECT, P.REFLECT, P.PERIODIC, P.PERIODIC))
+    announce("potential_cleared", dtype)
+    a = gpu_sim(pr, dtype)
+    a.advance(math.inf, 5)          # psi(r*) now holds nonzero values
+    a.set_potential(None)
+    a.set_primitive(flat.prim)
+    a.set_time(0.0, 0)
+    b = gpu_sim(flat, dtype)
+    assert a.advance(math.inf, 20) == 20
+    assert b.advance(math.inf, 20) == 20
+    assert np.array_equal(a.conserved(), b.conserved())
+    assert a.time() == b.time()
+    if dtype == "f64":
+        o = oracle_sim(flat)
+        for _ in range(20):
+            o.step()
+        assert rel_l1_vars(a.conserved(), o.conserved()) <= 1e-12
+    a.close()
+    b.close()
