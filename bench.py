@@ -7,14 +7,18 @@ dt) of every interior cell; the metric is cell-updates/s = cells * steps / time,
 with the state resident in HBM before the timed region starts.
 
 Prints one JSON line.  Besides the headline it carries:
-  roofline     -- the dominant kernel against the vector-ALU peak that bounds
-                  it: algorithmic flops per launch over its average launch time
-                  (HIP events recorded by the library around each kernel during
-                  the timed steps), with its HBM figures (algorithmic bytes over
-                  the same time against 8 TB/s; counted traffic from rocprofv3);
+  roofline     -- the stage kernel with the longest launches against the bound
+                  it has (HBM for stages P and E, the vector ALU for stage C):
+                  algorithmic bytes (or flops) per launch over its average launch
+                  time (HIP events the library records around each kernel in a
+                  second pass of the timed steps), with the other view beside it,
+                  the HBM traffic counted by rocprofv3, a streaming reference
+                  kernel with the same mix of read and write streams, and the
+                  whole step against the vector-ALU issue rate;
   cpu_baseline -- the FP64 CPU oracle timed on this host (rank 0 only) on a
                   bounded sample of the same workload;
-  fp64         -- the same workload with FP64 state, timed the same way.
+  fp64, batched, serving -- the same workload with FP64 state; 512 uneven
+                  simulations advanced together; a Poisson stream of requests.
 """
 import argparse
 import json
@@ -138,6 +142,24 @@ def _counters(kernel, dtype, cells):
     if rec and rec.get("source_hash") == source_hash():
         return rec
     return None
+
+
+def step_issue_bound(dtype, cells, ms_per_step):
+    """The whole step against the vector-ALU issue rate: the counted VALU
+    instructions per cell of the three stage kernels (rocprofv3 SQ_INSTS_VALU,
+    committed summary of the current kernel source), each a wave64 instruction
+    taking 4 clocks of one of 1024 SIMDs at 2.4 GHz.  None without a summary."""
+    per = {}
+    for k in WORDS[dtype]:
+        rec = _counters(KERNEL_NAMES[k], dtype, cells)
+        if not rec or not rec.get("valu_per_cell"):
+            return None
+        per[k] = rec["valu_per_cell"]
+    total = sum(per.values())
+    issue_ms = total * cells / VALU_ISSUE * 1e3
+    return {"valu_instr_per_cell": {k: round(v, 1) for k, v in per.items()},
+            "valu_instr_per_cell_total": round(total, 1), "issue_bound_ms": round(issue_ms, 4),
+            "frac_of_step": round(issue_ms / ms_per_step, 3)}
 
 
 def dominant(prof, dtype):
@@ -377,6 +399,9 @@ def main():
         log(f"[bench] streaming reference failed: {e}")
         ref = None
     rl = roofline(r["profile"], cells, args.dtype, ref)
+    sib = step_issue_bound(args.dtype, cells, ms_step)
+    if sib:
+        rl["step_valu_issue"] = sib
     out = {
         "metric": "cell-updates/s", "value": round(value, 1), "unit": "cell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
