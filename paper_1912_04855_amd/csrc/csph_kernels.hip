@@ -293,6 +293,31 @@ __device__ __forceinline__ T* at_bytes(T* base, long long bytes) {
   return (T*)((char*)base + bytes);
 }
 
+// Addresses within one z-plane: a scalar plane base (the field pointer plus the
+// index of the plane's first padded cell) and a 32-bit byte offset in the plane.
+// The offset is re-declared opaque in the block that loads or stores, so that
+// the access is issued with the scalar base and the 32-bit vector offset and no
+// 64-bit vector address arithmetic.  A padded plane holds fewer than 5e8 cells,
+// so its byte offsets fit 32 bits in FP64 too.
+__device__ __forceinline__ long long plane0(const GridDev& g, int k) {
+  const long long v = (long long)(k + kGhost) * g.sy * g.sx;
+  // uniform by construction; stated so that it stays in scalar registers
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ uint32_t in_plane(const GridDev& g, int i, int j) {
+  return (uint32_t)((j + kGhost) * g.sx + (i + kGhost)) * (uint32_t)sizeof(Real);
+}
+__device__ __forceinline__ uint32_t opaque32(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T* at_plane(T* base, long long plane, uint32_t bytes) {
+  return (T*)((char*)(base + plane) + (uint64_t)bytes);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -716,26 +741,26 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int i = T.x0 + tx, j = T.y0 + ty;
   const bool in = i < g.nx && j < g.ny;
+  const uint32_t oc = in ? in_plane(g, i, j) : 0u;  // this column's cell in a plane
 
   auto load = [&](int k) {
     const int s = ring3(k);
-    const long long pz = cell(g, -kGhost, -kGhost, k);  // plane k's first cell (a scalar)
+    const long long pz = plane0(g, k);
     for (int q = tid; q < HP; q += NT) {
       const int hx = q % HX, hy = q / HX;
       const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
       if (ii > g.nx || jj > g.ny) continue;
-      // one byte offset for every field of the cell (in-plane part in 32 bits)
-      const long long ob = opaque((pz + (jj + kGhost) * g.sx + (ii + kGhost)) * (long long)sizeof(Real));
-      const Real r = *at_bytes(R, ob);
+      const uint32_t ob = opaque32(in_plane(g, ii, jj));
+      const Real r = *at_plane(R, pz, ob);
       Real ux, uy, uz, p;
-      primitive(g, r, *at_bytes(MX, ob), *at_bytes(MY, ob), *at_bytes(MZ, ob), *at_bytes(EE, ob), ux, uy,
-                uz, p);
+      primitive(g, r, *at_plane(MX, pz, ob), *at_plane(MY, pz, ob), *at_plane(MZ, pz, ob), *at_plane(EE, pz, ob),
+                ux, uy, uz, p);
       S.rho[s][q] = r;
       S.phi[s][q] = sqrt_fast((Real)2 * p);
       S.ux[s][q] = ux;
       S.uy[s][q] = uy;
       S.uz[s][q] = uz;
-      S.psi[s][q] = kPsi ? *at_bytes(PS, ob) : (Real)0;
+      S.psi[s][q] = kPsi ? *at_plane(PS, pz, ob) : (Real)0;
     }
   };
 
@@ -849,9 +874,8 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
         for (int d = 0; d < 3; ++d) ms[d] = m0[d] - rdt * af[d];
         Es = EE[c] - rdt * B;
       }
-      F.ms[0][c] = ms[0];
-      F.ms[1][c] = ms[1];
-      F.ms[2][c] = ms[2];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) F.ms[d][c] = ms[d];
       F.ms[3][c] = Es;
       Real us[3], ps;
       primitive(g, rc, ms[0], ms[1], ms[2], Es, us[0], us[1], us[2], ps);
@@ -869,7 +893,7 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
         // x ghosts of the predicted particles (psi at their positions is left to
         // the fill kernel: it needs loads that would stall this sweep)
         x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
-          const long long cg = c + (gi - i);
+          const long long cg = cell(g, gi, j, k);
           F.ms[0][cg] = x_ghost_value(bc, ms[0], kMx, flip, face, dt);
           F.ms[1][cg] = x_ghost_value(bc, ms[1], kMy, flip, face, dt);
           F.ms[2][cg] = x_ghost_value(bc, ms[2], kMz, flip, face, dt);
@@ -909,39 +933,39 @@ __device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, c
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int i = T.x0 + tx, j = T.y0 + ty;
   const bool in = i < g.nx && j < g.ny;
+  const uint32_t oc = in ? in_plane(g, i, j) : 0u;  // this column's cell in a plane
   const Real ih = (Real)g.inv_h;
 
   auto load = [&](int k) {
     const int s = ring3(k);
-    const long long pz = cell(g, -kGhost, -kGhost, k);  // plane k's first cell (a scalar)
+    const long long pz = plane0(g, k);
     for (int q = tid; q < HP; q += NT) {
       const int hx = q % HX, hy = q / HX;
       const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
       if (ii > g.nx || jj > g.ny) continue;
-      // one byte offset for every field of the cell (in-plane part in 32 bits)
-      const long long ob = opaque((pz + (jj + kGhost) * g.sx + (ii + kGhost)) * (long long)sizeof(Real));
-      const Real r = *at_bytes(R, ob);
+      const uint32_t ob = opaque32(in_plane(g, ii, jj));
+      const Real r = *at_plane(R, pz, ob);
       Real ux, uy, uz, p;
-      primitive(g, r, *at_bytes(MSX, ob), *at_bytes(MSY, ob), *at_bytes(MSZ, ob), *at_bytes(ES, ob), ux,
-                uy, uz, p);
+      primitive(g, r, *at_plane(MSX, pz, ob), *at_plane(MSY, pz, ob), *at_plane(MSZ, pz, ob),
+                *at_plane(ES, pz, ob), ux, uy, uz, p);
       S.rho[s][q] = r;
       Real xi[3];
       if constexpr (kKeepXiStar) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) xi[d] = *at_bytes(F.xs[d], ob);
+        for (int d = 0; d < 3; ++d) xi[d] = *at_plane(F.xs[d], pz, ob);
       } else {
         // xi* from rho, m^n and m* (u* = (ux, uy, uz) above), as stage P formed it;
         // kept in lattice units
         Real un[3];
         const Real us[3] = {ux, uy, uz};
-        velocity(g, r, *at_bytes(F.U[par][1], ob), *at_bytes(F.U[par][2], ob), *at_bytes(F.U[par][3], ob),
-                 un);
+        velocity(g, r, *at_plane(F.U[par][1], pz, ob), *at_plane(F.U[par][2], pz, ob),
+                 *at_plane(F.U[par][3], pz, ob), un);
         xi_star(un, us, (Real)(0.5 * dt), xi);
 #pragma unroll
         for (int d = 0; d < 3; ++d) xi[d] *= ih;
       }
       S.a[s][q] = Quad{xi[0], xi[1], xi[2], sqrt_fast((Real)2 * p)};
-      S.b[s][q] = Quad{ux, uy, uz, kPsi ? *at_bytes(F.psis, ob) : (Real)0};
+      S.b[s][q] = Quad{ux, uy, uz, kPsi ? *at_plane(F.psis, pz, ob) : (Real)0};
     }
   };
 
@@ -1057,30 +1081,32 @@ __device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, c
         }
         bf *= (Real)0.5 * fc * ck;
       }
-      const long long c = cell(g, i, j, k);
-      const Real m0[3] = {F.U[par][1][c], F.U[par][2][c], F.U[par][3][c]};
-      const Real E0 = F.U[par][4][c];
+      const long long pz = plane0(g, k);
+      const uint32_t o = opaque32(oc);
+      const Real m0[3] = {*at_plane(F.U[par][1], pz, o), *at_plane(F.U[par][2], pz, o),
+                          *at_plane(F.U[par][3], pz, o)};
+      const Real E0 = *at_plane(F.U[par][4], pz, o);
       Real un[3], pn;
       primitive(g, rc, m0[0], m0[1], m0[2], E0, un[0], un[1], un[2], pn);
-      const Real msc[3] = {MSX[c], MSY[c], MSZ[c]};
+      const Real msc[3] = {*at_plane(MSX, pz, o), *at_plane(MSY, pz, o), *at_plane(MSZ, pz, o)};
+      const Real Esc = *at_plane(ES, pz, o);
       Real mt[3], Et;
       if constexpr (kF64) {
         const Acc B = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
         const Acc hdt = 0.5 * dt;
 #pragma unroll
         for (int d = 0; d < 3; ++d) mt[d] = 0.5 * (m0[d] + msc[d]) - hdt * a[d];
-        Et = 0.5 * (E0 + ES[c]) - hdt * B;
+        Et = 0.5 * (E0 + Esc) - hdt * B;
       } else {
         const Real B = bf + rc * (uc[0] * gf[0] + uc[1] * gf[1] + uc[2] * gf[2]);
         const Real hdt = (Real)(0.5 * dt);
 #pragma unroll
         for (int d = 0; d < 3; ++d) mt[d] = (Real)0.5 * (m0[d] + msc[d]) - hdt * af[d];
-        Et = (Real)0.5 * (E0 + ES[c]) - hdt * B;
+        Et = (Real)0.5 * (E0 + Esc) - hdt * B;
       }
-      F.mt[0][c] = mt[0];
-      F.mt[1][c] = mt[1];
-      F.mt[2][c] = mt[2];
-      F.mt[3][c] = Et;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) *at_plane(F.mt[d], pz, o) = mt[d];
+      *at_plane(F.mt[3], pz, o) = Et;
       Real ut[3], pt;
       primitive(g, rc, mt[0], mt[1], mt[2], Et, ut[0], ut[1], ut[2], pt);
       const Real qdt = (Real)(0.25 * dt);
@@ -1090,12 +1116,12 @@ __device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, c
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         xn[d] = hx * xc[d] + qdt * (un[d] + ut[d]);
-        if constexpr (kKeepXi) F.xt[d][c] = xn[d];
+        if constexpr (kKeepXi) *at_plane(F.xt[d], pz, o) = xn[d];
       }
       if (kPushX && (i < 2 || i >= g.nx - 2)) {
         // x ghosts of the post-Lagrange particles
         x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
-          const long long cg = c + (gi - i);
+          const long long cg = cell(g, gi, j, k);
           F.mt[0][cg] = x_ghost_value(bc, mt[0], kMx, flip, face, dt);
           F.mt[1][cg] = x_ghost_value(bc, mt[1], kMy, flip, face, dt);
           F.mt[2][cg] = x_ghost_value(bc, mt[2], kMz, flip, face, dt);
@@ -1324,38 +1350,40 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
     Real* const* Uo = F.U[1 - par];
     // own column: U^n at k-1..k+2, bases (U~) at k, k+1, xi_z at k, k+1, z-face flux k-1/2
     Real uq[5][4], bq[2][5], xq[2], Fz[5];
-    const long long c0 = in ? cell(g, i, j, T.z0) : 0;
-    auto ld_col = [&](int dk, Real out[5]) {
-      const long long c = c0 + (long long)dk * g.sxy;
+    // this column's cell in plane k of field f
+    const uint32_t oc = in ? in_plane(g, i, j) : 0u;
+    auto at_col = [&](Real* f, int k) { return at_plane(f, plane0(g, k), opaque32(oc)); };
+    auto ld_col = [&](int k, Real out[5]) {
+      const long long pz = plane0(g, k);
+      const uint32_t o = opaque32(oc);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) out[v] = Un[v][c];
+      for (int v = 0; v < 5; ++v) out[v] = *at_plane(Un[v], pz, o);
     };
-    auto ld_base = [&](int dk, Real out[5]) {
-      const long long c = c0 + (long long)dk * g.sxy;
-      out[0] = Un[0][c];
-      out[1] = F.mt[0][c];
-      out[2] = F.mt[1][c];
-      out[3] = F.mt[2][c];
-      out[4] = F.mt[3][c];
+    auto ld_base = [&](int k, Real out[5]) {
+      const long long pz = plane0(g, k);
+      const uint32_t o = opaque32(oc);
+      out[0] = *at_plane(Un[0], pz, o);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[1 + v] = *at_plane(F.mt[v], pz, o);
     };
     if (in) {
       // face z0 - 1/2 needs U^n at z0-2 .. z0+1 and the bases at z0-1, z0
       Real t[5];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        ld_col(q - 2, t);
+        ld_col(T.z0 + q - 2, t);
 #pragma unroll
         for (int v = 0; v < 5; ++v) uq[v][q] = t[v];
       }
-      ld_base(-1, bq[0]);
-      ld_base(0, bq[1]);
+      ld_base(T.z0 - 1, bq[0]);
+      ld_base(T.z0, bq[1]);
       if constexpr (kKeepXi) {
-        xq[0] = F.xt[2][c0 - g.sxy];
-        xq[1] = F.xt[2][c0];
+        xq[0] = *at_col(F.xt[2], T.z0 - 1);
+        xq[1] = *at_col(F.xt[2], T.z0);
       } else {
         // z offsets at z0-1 and z0 (uq holds U^n at z0-2 .. z0+1)
-        xq[0] = xi_final(g, bq[0][0], uq[3][1], F.ms[2][c0 - g.sxy], bq[0][3], xc);
-        xq[1] = xi_final(g, bq[1][0], uq[3][2], F.ms[2][c0], bq[1][3], xc);
+        xq[0] = xi_final(g, bq[0][0], uq[3][1], *at_col(F.ms[2], T.z0 - 1), bq[0][3], xc);
+        xq[1] = xi_final(g, bq[1][0], uq[3][2], *at_col(F.ms[2], T.z0), bq[1][3], xc);
       }
       face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fz);
       // shift so that uq holds U^n at z0-1 .. z0+1 (z0+2 comes in the first plane)
@@ -1376,8 +1404,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
     // updates; the barrier that ends the iteration waits for it.  Each wave
     // stages 64 consecutive plane cells, which land at consecutive LDS words.
     auto plane_load = [&](int k) {
-      // index of plane k's cell (-2, -2) (a scalar); in-plane offsets fit in 32 bits
-      const long long pz = cell(g, -kGhost, -kGhost, k);
+      const long long pz = plane0(g, k);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int q = tid + h * NT;
@@ -1386,33 +1413,32 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         const int ex = q % EX, ey = q / EX;
         const int ii = T.x0 - 2 + ex, jj = T.y0 - 2 + ey;
         if (q < EP && ii <= g.nx + 1 && jj <= g.ny + 1) {
-          const int r = (jj + kGhost) * g.sx + (ii + kGhost);
-          const long long ob = opaque((pz + r) * (long long)sizeof(Real));
+          const uint32_t ob = opaque32(in_plane(g, ii, jj));
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
             if constexpr (kF64) {
-              S.u[v][q] = *at_bytes(Un[v], ob);
+              S.u[v][q] = *at_plane(Un[v], pz, ob);
             } else {
-              __builtin_amdgcn_global_load_lds(at_bytes(Un[v], ob), &S.u[v][qb], 4, 0, 0);
+              __builtin_amdgcn_global_load_lds(at_plane(Un[v], pz, ob), &S.u[v][qb], 4, 0, 0);
             }
           }
         }
         const int hx = q % HX, hy = q / HX;
         const int ib = T.x0 - 1 + hx, jb = T.y0 - 1 + hy;
         if (q < HP && ib <= g.nx && jb <= g.ny) {
-          const int r = (jb + kGhost) * g.sx + (ib + kGhost);
-          const long long ob = opaque((pz + r) * (long long)sizeof(Real));
+          const uint32_t ob = opaque32(in_plane(g, ib, jb));
           Real* const* X = kKeepXi ? F.xt : F.ms;
           if constexpr (kF64) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) S.b[v][q] = *at_bytes(F.mt[v], ob);
-            S.xx[q] = *at_bytes(X[0], ob);
-            S.xy[q] = *at_bytes(X[1], ob);
+            for (int v = 0; v < 4; ++v) S.b[v][q] = *at_plane(F.mt[v], pz, ob);
+            S.xx[q] = *at_plane(X[0], pz, ob);
+            S.xy[q] = *at_plane(X[1], pz, ob);
           } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) __builtin_amdgcn_global_load_lds(at_bytes(F.mt[v], ob), &S.b[v][qb], 4, 0, 0);
-            __builtin_amdgcn_global_load_lds(at_bytes(X[0], ob), &S.xx[qb], 4, 0, 0);
-            __builtin_amdgcn_global_load_lds(at_bytes(X[1], ob), &S.xy[qb], 4, 0, 0);
+            for (int v = 0; v < 4; ++v)
+              __builtin_amdgcn_global_load_lds(at_plane(F.mt[v], pz, ob), &S.b[v][qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(at_plane(X[0], pz, ob), &S.xx[qb], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(at_plane(X[1], pz, ob), &S.xy[qb], 4, 0, 0);
           }
         }
       }
@@ -1424,17 +1450,16 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first plane has landed
     }
     for (int k = T.z0; k < T.z1; ++k) {
-      const int dk = k - T.z0;
       if constexpr (kF64) plane_load(k);
       // own column for this plane's upper z face: base and z offset at k+1, U^n
       // at k+2; in flight during the x-y faces.  (Loaded one plane ahead of the
       // copy of plane k+2, so that the copy finds these lines in L2.)
       if (in) {
-        ld_base(dk + 1, bq[1]);
+        ld_base(k + 1, bq[1]);
         // z offset at k+1 (FP32: its m*_z, the offset is formed below)
-        xq[1] = (kKeepXi ? F.xt : F.ms)[2][cell(g, i, j, k + 1)];
+        xq[1] = *at_col((kKeepXi ? F.xt : F.ms)[2], k + 1);
         Real t[5];
-        ld_col(dk + 2, t);
+        ld_col(k + 2, t);
 #pragma unroll
         for (int v = 0; v < 5; ++v) uq[v][3] = t[v];
       }
@@ -1487,22 +1512,23 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         if (k + 1 < T.z1) plane_load(k + 1);
       }
       if (in) {
-        const long long c = c0 + (long long)dk * g.sxy;
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fz[v]);
         Real nv[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) nv[v] = bq[0][v] - (Real)g.inv_h * acc[v];
+        const long long pz = plane0(g, k);
+        const uint32_t o = opaque32(oc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          Uo[v][c] = nv[v];
+          *at_plane(Uo[v], pz, o) = nv[v];
           if (!isfinite(nv[v])) bad |= kBadNonFinite;
           tot[v] += (double)nv[v];
         }
         if (kPushX && (i < 2 || i >= g.nx - 2)) {
           // x ghosts (two deep) of the new state
           x_push<2>(g, bc, i, [&](int gi, bool flip, int face) {
-            const long long cg = c + (gi - i);
+            const long long cg = cell(g, gi, j, k);
 #pragma unroll
             for (int v = 0; v < 5; ++v) Uo[v][cg] = x_ghost_value(bc, nv[v], v, flip, face, 0.0);
           });
@@ -1573,9 +1599,13 @@ __global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g, Bc
   else stage_c_body<false>(S, F, g, bc, ctrl, T);
 }
 
+// Workgroups per CU the register allocation must allow: the default scheme's
+// stage E fits 128 registers (four waves per SIMD); the general one keeps two.
+constexpr int e_blocks(bool gen) { return gen ? 2 : 4; }
+
 template <bool kGen>
-__global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, BcDev bc, Ctrl* ctrl,
-                                                   double* __restrict__ partials, int tz) {
+__global__ void __launch_bounds__(NT, e_blocks(kGen)) k_stage_e(Fields<Real> F, GridDev g, BcDev bc, Ctrl* ctrl,
+                                                                double* __restrict__ partials, int tz) {
   if (!ctrl->active) return;
   Tile T;
   int id;
@@ -1586,8 +1616,8 @@ __global__ void __launch_bounds__(NT, 2) k_stage_e(Fields<Real> F, GridDev g, Bc
 // batched sweeps: workgroup -> (instance, tile) through a host-built map of the
 // flattened tile list; the XCD inversion runs over the whole list
 template <int kStage, bool kGen>
-__global__ void __launch_bounds__(NT, 2) k_stage_batch(const Inst<Real>* __restrict__ tab,
-                                                       const int2* __restrict__ map, int ntiles) {
+__global__ void __launch_bounds__(NT, kStage == 2 ? e_blocks(kGen) : 2)
+    k_stage_batch(const Inst<Real>* __restrict__ tab, const int2* __restrict__ map, int ntiles) {
   const int gid = xcd_tile(blockIdx.x, gridDim.x);
   if (gid < 0 || gid >= ntiles) return;
   const int2 w = map[gid];
