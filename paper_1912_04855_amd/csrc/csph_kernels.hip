@@ -1032,6 +1032,10 @@ __device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, c
         // are formed with K / ck and scaled by ck after the loop.
         const float ck = (float)(-0.75 * g.kappa_h2 * g.h);
         const int bm = ring3(k - 1) * HP + tb, b0 = ring3(k) * HP + tb, bp = ring3(k + 1) * HP + tb;
+        // xi_c/h - 1 and xi_c/h + 1 per axis: a partner at s = +-1 along an axis
+        // is then at d = (xi_c/h - s) - xi_n/h there
+        const Real xlo[3] = {xc[0] - (Real)1, xc[1] - (Real)1, xc[2] - (Real)1};
+        const Real xhi[3] = {xc[0] + (Real)1, xc[1] + (Real)1, xc[2] + (Real)1};
 #pragma unroll
         for (int q = 0; q < 13; ++q) {
           const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
@@ -1043,10 +1047,9 @@ __device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, c
             const int n = side == 0 ? np : nm;
             const int sg = side == 0 ? 1 : -1;
             const Quad An = A_[n], Bn = B_[n];
-            float d[3] = {(float)(xc[0] - An.x), (float)(xc[1] - An.y), (float)(xc[2] - An.z)};
-            if (ox != 0) d[0] -= (float)(sg * ox);
-            if (oy != 0) d[1] -= (float)(sg * oy);
-            if (oz != 0) d[2] -= (float)(sg * oz);
+            auto xo = [&](int c, int so) { return so > 0 ? xlo[c] : so < 0 ? xhi[c] : xc[c]; };
+            const float d[3] = {(float)(xo(0, sg * ox) - An.x), (float)(xo(1, sg * oy) - An.y),
+                                (float)(xo(2, sg * oz) - An.z)};
             kgrad_lat(d[0], d[1], d[2], K[side]);
             fn[side] = An.w;
             pn[side] = Bn.w;
@@ -1056,11 +1059,14 @@ __device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, c
           // sp+ K+ + sp- K- = (sp+ - sp-) K+ + sp- (K+ + K-).  The difference
           // sp+ - sp- = phi_c (phi+ - phi-) + rho_c (psi+ - psi-) carries the
           // well-balance cancellation: its two FP32 differences are exact for
-          // neighbours within a factor 2, and their combination is formed in FP64.
-          // K+ + K- vanishes on the lattice, so the large sp- meets only a small
-          // factor.
+          // neighbours within a factor 2, and their combination is a compensated
+          // sum (the first product's rounding error, exact by a fused multiply-add,
+          // is added back), as accurate as forming it in FP64.  K+ + K- vanishes on
+          // the lattice, so the large sp- meets only a small factor.
           const Real dphi = fn[0] - fn[1], dps = pn[0] - pn[1];
-          const Real dsp = (Real)((Acc)fc * (Acc)dphi + (Acc)rc * (Acc)dps);
+          const float pr = fc * dphi;
+          const float pe = fmaf(fc, dphi, -pr);
+          const float dsp = fmaf(rc, dps, pr) + pe;
           const Real d0 = pn[0] - psc, d1 = pn[1] - psc;
           const Real spm = fc * fn[1] + rc * d1;
           // each term goes straight into its accumulator (one fused multiply-add each)
