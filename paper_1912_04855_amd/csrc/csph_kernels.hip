@@ -1354,8 +1354,12 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
     const bool in = i < g.nx && j < g.ny;
     Real* const* Un = F.U[par];
     Real* const* Uo = F.U[1 - par];
-    // own column: U^n at k-1..k+2, bases (U~) at k, k+1, xi_z at k, k+1, z-face flux k-1/2
-    Real uq[5][4], bq[2][5], xq[2], Fz[5];
+    Real* const* X = kKeepXi ? F.xt : F.ms;
+    // Own column, one plane behind the plane in LDS: at iteration k the z face
+    // k-1/2 and the update of cell k-1 are formed, from plane k's values in LDS
+    // and these registers: U^n at k-2, k-1 (uq), the base and z offset of k-1
+    // (bq, xq), the x/y face sums of k-1 (aq) and the z-face flux k-3/2 (Fz).
+    Real uq[5][2], bq[5], xq, aq[5], Fz[5];
     // this column's cell in plane k of field f
     const uint32_t oc = in ? in_plane(g, i, j) : 0u;
     auto at_col = [&](Real* f, int k) { return at_plane(f, plane0(g, k), opaque32(oc)); };
@@ -1372,43 +1376,30 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[1 + v] = *at_plane(F.mt[v], pz, o);
     };
+    // z offset of this column's particle in plane k from its rho, m^n_z, and the
+    // z component of m~ (FP32: with m*_z); FP64 reads the stored offset
+    auto z_offset = [&](Real rho, Real mnz, Real xs, Real mtz) {
+      if constexpr (kKeepXi) return xs;
+      else return xi_final(g, rho, mnz, xs, mtz, xc);
+    };
     if (in) {
-      // face z0 - 1/2 needs U^n at z0-2 .. z0+1 and the bases at z0-1, z0
       Real t[5];
+      ld_col(T.z0 - 2, t);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ld_col(T.z0 + q - 2, t);
+      for (int v = 0; v < 5; ++v) uq[v][0] = t[v];
+      ld_col(T.z0 - 1, t);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) uq[v][q] = t[v];
-      }
-      ld_base(T.z0 - 1, bq[0]);
-      ld_base(T.z0, bq[1]);
-      if constexpr (kKeepXi) {
-        xq[0] = *at_col(F.xt[2], T.z0 - 1);
-        xq[1] = *at_col(F.xt[2], T.z0);
-      } else {
-        // z offsets at z0-1 and z0 (uq holds U^n at z0-2 .. z0+1)
-        xq[0] = xi_final(g, bq[0][0], uq[3][1], *at_col(F.ms[2], T.z0 - 1), bq[0][3], xc);
-        xq[1] = xi_final(g, bq[1][0], uq[3][2], *at_col(F.ms[2], T.z0), bq[1][3], xc);
-      }
-      face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fz);
-      // shift so that uq holds U^n at z0-1 .. z0+1 (z0+2 comes in the first plane)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        uq[v][0] = uq[v][1];
-        uq[v][1] = uq[v][2];
-        uq[v][2] = uq[v][3];
-      }
-#pragma unroll
-      for (int v = 0; v < 5; ++v) bq[0][v] = bq[1][v];
-      xq[0] = xq[1];
+      for (int v = 0; v < 5; ++v) uq[v][1] = t[v];
+      ld_base(T.z0 - 1, bq);
+      xq = z_offset(bq[0], uq[3][1], *at_col(X[2], T.z0 - 1), bq[3]);
     }
     // The current plane in LDS: U^n with a two-cell halo, the bases and x/y
     // offsets with one.  In FP32 the next plane is copied global -> LDS by the
     // DMA path of the vector memory unit (no registers held), issued once the
-    // x-y faces of the current plane are done and in flight during the cell
-    // updates; the barrier that ends the iteration waits for it.  Each wave
-    // stages 64 consecutive plane cells, which land at consecutive LDS words.
+    // current plane's last LDS reads are done and in flight during the z face
+    // and the cell updates; the barrier that ends the iteration waits for it.
+    // Each wave stages 64 consecutive plane cells, which land at consecutive LDS
+    // words.
     auto plane_load = [&](int k) {
       const long long pz = plane0(g, k);
 #pragma unroll
@@ -1433,7 +1424,6 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         const int ib = T.x0 - 1 + hx, jb = T.y0 - 1 + hy;
         if (q < HP && ib <= g.nx && jb <= g.ny) {
           const uint32_t ob = opaque32(in_plane(g, ib, jb));
-          Real* const* X = kKeepXi ? F.xt : F.ms;
           if constexpr (kF64) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) S.b[v][q] = *at_plane(F.mt[v], pz, ob);
@@ -1455,22 +1445,34 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
       plane_load(T.z0);
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first plane has landed
     }
-    for (int k = T.z0; k < T.z1; ++k) {
-      if constexpr (kF64) plane_load(k);
-      // own column for this plane's upper z face: base and z offset at k+1, U^n
-      // at k+2; in flight during the x-y faces.  (Loaded one plane ahead of the
-      // copy of plane k+2, so that the copy finds these lines in L2.)
-      if (in) {
-        ld_base(k + 1, bq[1]);
-        // z offset at k+1 (FP32: its m*_z, the offset is formed below)
-        xq[1] = *at_col((kKeepXi ? F.xt : F.ms)[2], k + 1);
-        Real t[5];
-        ld_col(k + 2, t);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) uq[v][3] = t[v];
+    // iterations z0 .. z1-1 have plane k in LDS; the last one (k = z1) only
+    // closes the column with plane z1's values read from memory
+    for (int k = T.z0; k <= T.z1; ++k) {
+      const bool plane = k < T.z1;
+      if constexpr (kF64) {
+        if (plane) plane_load(k);
       }
-      lds_barrier();
-      {
+      // own column: U^n at k+1 and the z offset's input at k, in flight during
+      // the x-y faces (U^n at k+1 is also what the copy of plane k+1 reads next)
+      Real un1[5], xs = (Real)0;
+      if (in) {
+        ld_col(k + 1, un1);
+        xs = *at_col(X[2], k);
+      }
+      Real ak[5] = {0, 0, 0, 0, 0};
+      Real uk[5], bk[5];
+      if (plane) {
+        lds_barrier();
+        if (in) {
+          // this cell's own plane-k values (read before the faces: once the
+          // faces are done, a wave may start copying the next plane over them)
+          const int ce = eidx(tx + 2, ty + 2), ch = hidx(tx + 1, ty + 1);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) uk[v] = S.u[v][ce];
+          bk[0] = uk[0];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bk[1 + v] = S.b[v][ch];
+        }
         // every x and y face of the tile once: x faces first, then y faces
 #pragma unroll 1
         for (int f = tid; f < NFX + NFY; f += NT) {
@@ -1489,70 +1491,82 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
           }
         }
         lds_barrier();
-      }
-      // x faces i+1/2 and i-1/2 of this cell (columns tx+1 and tx of its row) and
-      // y faces j+1/2, j-1/2 (the last LDS reads of the iteration); z faces:
-      // k+1/2 new (its column loads were issued at the top), k-1/2 carried from
-      // the previous plane
-      Real acc[5], Fp[5];
-      if (in) {
-        const int fxp = ty * (TX + 1) + tx + 1, fxm = fxp - 1;
-        const int fyp = (ty + 1) * TX + tx, fym = ty * TX + tx;
+        if (in) {
+          // x faces i+1/2 and i-1/2 of this cell (columns tx+1 and tx of its
+          // row) and y faces j+1/2, j-1/2: the last LDS reads of the iteration
+          const int fxp = ty * (TX + 1) + tx + 1, fxm = fxp - 1;
+          const int fyp = (ty + 1) * TX + tx, fym = ty * TX + tx;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) acc[v] = S.fx[v][fxp] - S.fx[v][fxm];
+          for (int v = 0; v < 5; ++v) ak[v] = S.fx[v][fxp] - S.fx[v][fxm];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (S.fy[v][fyp] - S.fy[v][fym]);
-        if constexpr (!kKeepXi) xq[1] = xi_final(g, bq[1][0], uq[3][2], xq[1], bq[1][3], xc);
-        face_flux<kGen>(g, 2, uq, bq[0], bq[1], xq[0], xq[1], dt, Fp);
-        // advance the U^n column queue to k .. k+2
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          uq[v][0] = uq[v][1];
-          uq[v][1] = uq[v][2];
-          uq[v][2] = uq[v][3];
+          for (int v = 0; v < 5; ++v) ak[v] = ak[v] + (S.fy[v][fyp] - S.fy[v][fym]);
         }
-      }
-      // the plane buffers are free: start the next plane, which lands while the
-      // updates below (no LDS, no pending loads) are computed
-      if constexpr (!kF64) {
-        if (k + 1 < T.z1) plane_load(k + 1);
+        // the plane buffers are free (the faces are done and read only fx, fy
+        // from here): start the next plane, which lands while the z face and the
+        // updates below (no LDS) are computed
+        if constexpr (!kF64) {
+          if (k + 1 < T.z1) plane_load(k + 1);
+        }
+      } else if (in) {
+        ld_col(k, uk);
+        ld_base(k, bk);
       }
       if (in) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) acc[v] = acc[v] + (Fp[v] - Fz[v]);
-        Real nv[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) nv[v] = bq[0][v] - (Real)g.inv_h * acc[v];
-        const long long pz = plane0(g, k);
-        const uint32_t o = opaque32(oc);
+        // z face k-1/2 from U^n at k-2 .. k+1, the bases and offsets of k-1, k
+        const Real xk = z_offset(bk[0], uk[3], xs, bk[3]);
+        Real u4[5][4], Fp[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          *at_plane(Uo[v], pz, o) = nv[v];
-          if (!isfinite(nv[v])) bad |= kBadNonFinite;
-          tot[v] += (double)nv[v];
+          u4[v][0] = uq[v][0];
+          u4[v][1] = uq[v][1];
+          u4[v][2] = uk[v];
+          u4[v][3] = un1[v];
         }
-        if (kPushX && (i < 2 || i >= g.nx - 2)) {
-          // x ghosts (two deep) of the new state
-          x_push<2>(g, bc, i, [&](int gi, bool flip, int face) {
-            const long long cg = cell(g, gi, j, k);
+        face_flux<kGen>(g, 2, u4, bq, bk, xq, xk, dt, Fp);
+        if (k > T.z0) {
+          // the update of cell k-1: x/y face sums, then the two z faces
+          Real acc[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) Uo[v][cg] = x_ghost_value(bc, nv[v], v, flip, face, 0.0);
-          });
+          for (int v = 0; v < 5; ++v) acc[v] = aq[v] + (Fp[v] - Fz[v]);
+          Real nv[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) nv[v] = bq[v] - (Real)g.inv_h * acc[v];
+          const long long pz = plane0(g, k - 1);
+          const uint32_t o = opaque32(oc);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            *at_plane(Uo[v], pz, o) = nv[v];
+            if (!isfinite(nv[v])) bad |= kBadNonFinite;
+            tot[v] += (double)nv[v];
+          }
+          if (kPushX && (i < 2 || i >= g.nx - 2)) {
+            // x ghosts (two deep) of the new state
+            x_push<2>(g, bc, i, [&](int gi, bool flip, int face) {
+              const long long cg = cell(g, gi, j, k - 1);
+#pragma unroll
+              for (int v = 0; v < 5; ++v) Uo[v][cg] = x_ghost_value(bc, nv[v], v, flip, face, 0.0);
+            });
+          }
+          if ((double)nv[0] < -g.neg_tol) bad |= kBadNegDensity;
+          if (!bad) smax = fmax(smax, signal_speed(g, nv[0], nv[1], nv[2], nv[3], nv[4]));
         }
-        if ((double)nv[0] < -g.neg_tol) bad |= kBadNegDensity;
-        if (!bad) smax = fmax(smax, signal_speed(g, nv[0], nv[1], nv[2], nv[3], nv[4]));
-        // advance the carried z face and the base queue to k+1
+        // advance the column by one plane
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           Fz[v] = Fp[v];
-          bq[0][v] = bq[1][v];
+          uq[v][0] = uq[v][1];
+          uq[v][1] = uk[v];
+          bq[v] = bk[v];
+          aq[v] = ak[v];
         }
-        xq[0] = xq[1];
+        xq = xk;
       }
-      // the next plane's LDS copy must have landed before the barrier (vmcnt(0);
-      // a workgroup barrier alone does not wait for global -> LDS transfers)
-      if constexpr (!kF64) __builtin_amdgcn_s_waitcnt(0x0F70);
-      lds_barrier();
+      if (plane) {
+        // the next plane's LDS copy must have landed before the barrier (vmcnt(0);
+        // a workgroup barrier alone does not wait for global -> LDS transfers)
+        if constexpr (!kF64) __builtin_amdgcn_s_waitcnt(0x0F70);
+        lds_barrier();
+      }
     }
   }
   // block epilogue: FP64 totals to a per-block slot, max signal speed, flags
