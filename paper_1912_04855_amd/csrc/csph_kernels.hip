@@ -1336,7 +1336,6 @@ template <bool kGen>
 __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              Ctrl* ctrl,
                                              const Tile& T, double* __restrict__ slot) {
-  const bool have = true;
   __shared__ PlaneE S;
   __shared__ double red[6][NT / kWave];
   __shared__ int redb;
@@ -1349,7 +1348,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
   double smax = 0.0;
   int bad = 0;
   if (tid == 0) redb = 0;
-  if (have) {
+  {
     const int i = T.x0 + tx, j = T.y0 + ty;
     const bool in = i < g.nx && j < g.ny;
     Real* const* Un = F.U[par];
@@ -1376,8 +1375,8 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[1 + v] = *at_plane(F.mt[v], pz, o);
     };
-    // z offset of this column's particle in plane k from its rho, m^n_z, and the
-    // z component of m~ (FP32: with m*_z); FP64 reads the stored offset
+    // z offset of a particle of this column: FP32 forms it from rho, m^n_z, m*_z
+    // (xs) and m~_z; FP64 has it stored (xs)
     auto z_offset = [&](Real rho, Real mnz, Real xs, Real mtz) {
       if constexpr (kKeepXi) return xs;
       else return xi_final(g, rho, mnz, xs, mtz, xc);
