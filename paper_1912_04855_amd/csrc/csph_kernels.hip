@@ -71,6 +71,10 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;          // one-cell halo
 constexpr int EX = TX + 4, EY = TY + 4, EP = EX * EY;          // two-cell halo
 constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);        // x and y faces of a tile
+// stage E numbers its x faces at the pitch of its two-cell-halo rows (TX + 1 of
+// every EX used), so that a wave's face reads are consecutive LDS words across
+// a row boundary (no bank conflicts), and its y faces start on a half-wave
+constexpr int NFXP = EX * TY;
 
 // ------------------------------------------------------------------ indexing
 __device__ __forceinline__ long long cell(const GridDev& g, int i, int j, int k) {
@@ -1282,7 +1286,7 @@ struct PlaneE {
   Real u[5][EP];      // U^n of the current plane, two-cell halo
   Real b[4][HP];      // m~, E~ of the current plane, one-cell halo
   Real xx[HP], xy[HP];  // x/y offsets xi (FP64), or the m*_x, m*_y they are formed from (FP32)
-  Real fx[5][NFX];    // x-face fluxes of the tile row by row: face i+1/2, i = x0-1 .. x0+TX-1
+  Real fx[5][NFXP];   // x-face fluxes of the tile row by row (pitch EX): face i+1/2, i = x0-1 .. x0+TX-1
   Real fy[5][NFY];    // y-face fluxes: face j+1/2, j = y0-1 .. y0+TY-1
 };
 
@@ -1474,15 +1478,16 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         }
         // every x and y face of the tile once: x faces first, then y faces
 #pragma unroll 1
-        for (int f = tid; f < NFX + NFY; f += NT) {
+        for (int f = tid; f < NFXP + NFY; f += NT) {
           Real Fo[5];
-          if (f < NFX) {
-            if (tile_face<kGen>(g, T, S, 0, f / (TX + 1), f % (TX + 1), dt, xc, Fo)) {
+          if (f < NFXP) {
+            const int row = f / EX, col = f % EX;
+            if (col <= TX && tile_face<kGen>(g, T, S, 0, row, col, dt, xc, Fo)) {
 #pragma unroll
               for (int v = 0; v < 5; ++v) S.fx[v][f] = Fo[v];
             }
           } else {
-            const int fy = f - NFX;
+            const int fy = f - NFXP;
             if (tile_face<kGen>(g, T, S, 1, fy / TX, fy % TX, dt, xc, Fo)) {
 #pragma unroll
               for (int v = 0; v < 5; ++v) S.fy[v][fy] = Fo[v];
@@ -1493,7 +1498,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
         if (in) {
           // x faces i+1/2 and i-1/2 of this cell (columns tx+1 and tx of its
           // row) and y faces j+1/2, j-1/2: the last LDS reads of the iteration
-          const int fxp = ty * (TX + 1) + tx + 1, fxm = fxp - 1;
+          const int fxp = ty * EX + tx + 1, fxm = fxp - 1;
           const int fyp = (ty + 1) * TX + tx, fym = ty * TX + tx;
 #pragma unroll
           for (int v = 0; v < 5; ++v) ak[v] = S.fx[v][fxp] - S.fx[v][fxm];
