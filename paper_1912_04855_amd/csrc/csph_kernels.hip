@@ -1465,7 +1465,10 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
       Real ak[5] = {0, 0, 0, 0, 0};
       Real uk[5], bk[5];
       if (plane) {
-        lds_barrier();
+        // plane k complete in LDS for every wave: FP64 has just stored it; FP32's
+        // copy was waited for before the barrier that ended the previous
+        // iteration (the first plane's before the loop, so it needs this one)
+        if (kF64 || k == T.z0) lds_barrier();
         if (in) {
           // this cell's own plane-k values (read before the faces: once the
           // faces are done, a wave may start copying the next plane over them)
