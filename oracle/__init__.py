@@ -18,6 +18,7 @@ POS_DISPLACED, POS_LATTICE = 0, 1
 BASE_POST, BASE_MID = 0, 1
 LIM_MINMOD, LIM_MC, LIM_VANLEER, LIM_SUPERBEE = 0, 1, 2, 3
 FLUX_SWEPT, FLUX_LF, FLUX_SWEPT_AV = 0, 1, 2
+FACE_PARTICLE, FACE_FOOT = 0, 1
 
 FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
           "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "psis"]
@@ -31,7 +32,8 @@ class _Params(C.Structure):
                 ("h", C.c_double), ("origin", C.c_double * 3), ("gamma", C.c_double),
                 ("cfl", C.c_double), ("rho_vac", C.c_double), ("bc", C.c_int32 * 6),
                 ("inflow", (C.c_double * 5) * 6), ("pos_mode", C.c_int32),
-                ("base_mode", C.c_int32), ("limiter", C.c_int32), ("flux", C.c_int32)]
+                ("base_mode", C.c_int32), ("limiter", C.c_int32), ("flux", C.c_int32),
+                ("face_mode", C.c_int32)]
 
 
 _lib = None
@@ -113,7 +115,8 @@ class OracleSim:
 
     def __init__(self, shape, h, gamma=1.4, cfl=0.4, rho_vac=1e-10, bc=(PERIODIC,) * 6,
                  inflow=None, origin=(0.0, 0.0, 0.0), pos_mode=POS_DISPLACED,
-                 base_mode=BASE_POST, limiter=LIM_MINMOD, flux=FLUX_SWEPT_AV):
+                 base_mode=BASE_POST, limiter=LIM_MINMOD, flux=FLUX_SWEPT_AV,
+                 face_mode=FACE_PARTICLE):
         nx, ny, nz = shape
         p = _Params()
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -128,6 +131,7 @@ class OracleSim:
             for v in range(5):
                 p.inflow[f][v] = st[v]
         p.pos_mode, p.base_mode, p.limiter, p.flux = pos_mode, base_mode, limiter, flux
+        p.face_mode = face_mode
         self.params = p
         self.shape = (nz, ny, nx)
         self.h = h

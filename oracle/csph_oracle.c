@@ -670,7 +670,13 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
    * swept volume
    *   Phi = max(xi_i, 0) U^L + min(xi_{i+1}, 0) U^R     (= dt * face flux),
    * and Eq. (4) becomes U^{n+1} = U~ - (1/h) sum_d (Phi_{i+1/2} - Phi_{i-1/2}).
-   * Each face value is computed once and used by both of its cells. */
+   * Each face value is computed once and used by both of its cells.
+   * A second reading of the face speed (face_mode = ORC_FACE_FOOT, not the
+   * default) takes one advective speed per face, the displacement of the
+   * material that reaches the face during the step,
+   *   X = (xi_i + xi_{i+1}) / 2 / (1 + (xi_{i+1} - xi_i) / h),
+   * i.e. the offset field interpolated linearly to the foot of the face's
+   * trajectory, and sweeps Phi = max(X, 0) U^L + min(X, 0) U^R. */
   const double* Un[5] = {s->rho, s->m[0], s->m[1], s->m[2], s->E};
   const double* Ut[5] = {s->rho, s->mt[0], s->mt[1], s->mt[2], s->Et};
   const int mid = s->P.base_mode == ORC_BASE_MID;
@@ -709,6 +715,9 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
             if (s->P.flux == ORC_FLUX_LF) {
               const double a = fmax(fabs(xL), fabs(xR));
               F = 0.5 * (xL * UL + xR * UR) - 0.5 * a * (UR - UL);
+            } else if (s->P.face_mode == ORC_FACE_FOOT) {
+              const double X = 0.5 * (xL + xR) / (1.0 + (xR - xL) * inv_h);
+              F = fmax(X, 0.0) * UL + fmin(X, 0.0) * UR;
             } else {
               F = fmax(xL, 0.0) * UL + fmin(xR, 0.0) * UR;
             }

@@ -37,6 +37,9 @@ enum { ORC_LIM_MINMOD = 0, ORC_LIM_MC = 1, ORC_LIM_VANLEER = 2, ORC_LIM_SUPERBEE
  * swept volume), the same plus the acoustic (Rusanov) velocity-jump dissipation
  * (the default), or Lax-Friedrichs with the advective speeds */
 enum { ORC_FLUX_SWEPT = 0, ORC_FLUX_LF = 1, ORC_FLUX_SWEPT_AV = 2 };
+/* swept width of the swept-volume fluxes: the offset of the upwind particle
+ * (xi_i or xi_{i+1}), or the displacement of the particle that reaches the face */
+enum { ORC_FACE_PARTICLE = 0, ORC_FACE_FOOT = 1 };
 
 /* status codes */
 enum {
@@ -61,6 +64,7 @@ typedef struct {
   int32_t base_mode;       /* ORC_BASE_* */
   int32_t limiter;         /* ORC_LIM_* */
   int32_t flux;            /* ORC_FLUX_* */
+  int32_t face_mode;       /* ORC_FACE_* */
 } orc_params;
 
 typedef struct orc_sim orc_sim;

@@ -282,23 +282,61 @@ def test_second_order_smooth_advection(limiter, min_order):
     assert orders(errs)[-1] >= min_order, errs
 
 
-def test_acoustic_wave_converges():
-    """A right-going acoustic simple wave on a background flow: the step converges,
-    at first order (the remap of rigid particles and the displaced-kernel sum of the
-    corrector both carry O(h) terms for a compressive velocity field)."""
-    errs = []
-    for n in (32, 64, 128):
-        pr = P.acoustic_wave(n, t_end=0.25)
-        s = oracle_sim(pr)
-        s.advance(pr.t_end)
-        rho = s.conserved()[0][0, 0, :]
-        c = math.sqrt(1.4)
-        x = (np.arange(n) + 0.5) / n
-        ph = (0.5 + c) * 0.25
-        ex = 1 + 1e-6 * (np.cos(2 * math.pi * (x - 0.5 / n - ph)) - np.cos(2 * math.pi * (x + 0.5 / n - ph))) * n / (2 * math.pi)
-        errs.append(np.mean(np.abs(rho - ex)))
+def _acoustic_error(n, u0=0.5, **kw):
+    pr = P.acoustic_wave(n, u0=u0, t_end=0.25)
+    s = oracle_sim(pr, **kw)
+    s.advance(pr.t_end)
+    rho = s.conserved()[0][0, 0, :]
+    c = math.sqrt(1.4)
+    x = (np.arange(n) + 0.5) / n
+    ph = (u0 + c) * 0.25
+    ex = 1 + 1e-6 * (np.cos(2 * math.pi * (x - 0.5 / n - ph)) - np.cos(2 * math.pi * (x + 0.5 / n - ph))) * n / (2 * math.pi)
+    return np.mean(np.abs(rho - ex))
+
+
+# readings of Eqs. (6)-(8) tried on the acoustic simple wave (N = 32, 64, 128);
+# the lowest order each must keep (measured orders in the comments, 32->64->128)
+_ACOUSTIC_READINGS = [
+    # the default: displaced corrector, post-Lagrange base, particle offsets as
+    # the face speeds, acoustic damping                          (0.93, 0.96)
+    (dict(), 0.9),
+    # corrector on the lattice                                   (0.96, 0.97)
+    (dict(pos_mode=O.POS_LATTICE), 0.9),
+    # reconstruction from (U^n + U~)/2                           (0.99, 0.99)
+    (dict(base_mode=O.BASE_MID), 0.9),
+    # lattice corrector and mid base together                    (1.01, 1.02)
+    (dict(pos_mode=O.POS_LATTICE, base_mode=O.BASE_MID), 0.9),
+    # swept volume without the damping                           (0.95, 0.97)
+    (dict(flux=O.FLUX_SWEPT), 0.9),
+    # one speed per face: the displacement of the material that
+    # reaches the face (error 2-4x smaller, still first order:
+    # 1.15 between 128 and 256)                                  (1.51, 1.44)
+    (dict(face_mode=O.FACE_FOOT), 1.3),
+    # the same with the mid base (1.38 between 128 and 256)      (1.69, 1.72)
+    (dict(face_mode=O.FACE_FOOT, base_mode=O.BASE_MID), 1.5),
+]
+
+
+@pytest.mark.parametrize("kw,min_order", _ACOUSTIC_READINGS)
+def test_acoustic_wave_converges(kw, min_order):
+    """A right-going acoustic simple wave on a background flow converges under
+    every reading tried, at first order.  Three terms are O(h) on a compressive
+    velocity field: the particle offsets used as face speeds put the divergence
+    of the remap half a cell upwind (the foot reading removes this one); the
+    Lagrangian stage keeps each particle's density (the mass row of Q in Eq. (7)
+    is zero), so the corrector's pressure misses the compression part of its
+    change over the step; and on displaced particles the kernel sum of a uniform
+    field is not zero (the zeroth-order consistency error of SPH)."""
+    errs = [_acoustic_error(n, **kw) for n in (32, 64, 128)]
     o = orders(errs)
-    assert all(k >= 0.9 for k in o), o
+    assert all(k >= min_order for k in o), o
+
+
+def test_acoustic_wave_foot_reading_more_accurate():
+    """The foot reading of the face speed has a smaller error than the particle
+    offsets on every grid (its remap divergence is centred on the cell)."""
+    for n in (32, 64, 128):
+        assert _acoustic_error(n, face_mode=O.FACE_FOOT) < 0.7 * _acoustic_error(n)
 
 
 # ---------------------------------------------------------------- symmetry
