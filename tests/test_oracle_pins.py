@@ -221,3 +221,45 @@ def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "runtime error" not in r.stderr, r.stderr[-4000:]
     assert "cases ok" in r.stdout
+
+
+# ------------------------------------------------- transverse acoustic damping
+def test_transverse_damping_rate_at_a_shear_jump():
+    """The weight of the velocity-jump damping on the transverse components.
+
+    A gas of uniform density and pressure with u_y = +v for x < 1/2 and -v for
+    x > 1/2 (no normal velocity) has no pressure force, no mass flux through the
+    x faces (the particles do not move along x) and zero minmod slopes next to the
+    jump, so over a vanishing step the only change is the damping term of the face
+    flux at x = 1/2: the momentum of the two cells beside it moves at the rate
+    -+ (1/h) (a/2) w_t rho (2v), with a = c, and the energy does not change (the
+    mean transverse velocity at the face is zero).  The weight w_t = 1/2 is the
+    value the scheme's reading fixes: with (1, 1/2, 1/2) a velocity checkerboard at
+    rest decays by 1 - 4 a dt/h per step, stable for a dt/h <= 1/2, which the CFL
+    rule (a dt/h <= C = 0.4) meets; weight 1 on all three axes would need
+    a dt/h <= 1/3.  The Lagrangian stage's share of the change (the displaced-
+    kernel sums of the sheared lattice) is O(dt^2) and negligible at dt = 1e-8."""
+    n, v, gm, dt = 16, 0.3, 1.4, 1e-8
+    shape = (n, 4, 4)
+    h = 1.0 / n
+    x, _, _ = P.centres(shape, h)
+    prim = np.zeros((5, 4, 4, n))
+    prim[0] = 1.0
+    prim[2] = np.where(x < 0.5, v, -v)
+    prim[4] = 1.0
+    pr = P.Problem("shear_jump", shape, h, gm, 0.4, (P.OUTFLOW,) * 2 + (P.PERIODIC,) * 4, prim, None)
+    s = oracle_sim(pr)
+    U0 = s.conserved()
+    assert s.step(dt_max=dt) == dt
+    U1 = s.conserved()
+    rate = (U1[2] - U0[2]) / dt
+    c = math.sqrt(gm)
+    want = c * 0.5 * v / h                       # (a/2) * w_t * rho * 2v / h with w_t = 1/2
+    i = n // 2
+    assert np.allclose(rate[:, :, i - 1], -want, rtol=1e-5), rate[0, 0, i - 2:i + 2]
+    assert np.allclose(rate[:, :, i], want, rtol=1e-5), rate[0, 0, i - 2:i + 2]
+    # away from the jump nothing changes at this order
+    far = np.r_[1:i - 1, i + 1:n - 1]
+    assert np.max(np.abs(rate[:, :, far])) <= 1e-4 * want
+    # kinetic energy turns into heat: E itself is unchanged to O(dt^2)
+    assert np.max(np.abs(U1[4] - U0[4])) <= 1e-6 * want * dt
