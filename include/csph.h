@@ -101,7 +101,8 @@ csph_status csph_create(const csph_grid_desc* desc, void* hip_stream, csph_sim**
 csph_status csph_create_in(const csph_grid_desc* desc, void* hip_stream, void* dev_buf,
                            size_t bytes, csph_sim** out);
 
-/* Free what the library owns.  NULL is accepted. */
+/* Free what the library owns.  NULL is accepted.  CSPH_ERR_ARG (nothing freed)
+ * while the simulation is a batch member. */
 csph_status csph_destroy(csph_sim* sim);
 
 /* Change the stream later work is issued on (NULL = null stream). */
@@ -211,7 +212,12 @@ csph_status csph_autotune(csph_sim* sim, int32_t trial_steps, int32_t tz_out[3],
  * target; members of different sizes are flattened into one tile list, and one
  * launch per stage advances all of them.  hbm_budget bounds the summed
  * csph_required_bytes of the members (0 = unbounded).  Reads of a member
- * (state, time, totals, stage fields) first wait for the batch's stream. */
+ * (state, time, totals, stage fields) first wait for the batch's stream.
+ * While a simulation is a member, every call that would change it or free it
+ * (csph_destroy, csph_set_stream, csph_set_state, csph_set_potential,
+ * csph_set_boundary, csph_set_time, csph_set_scheme, csph_set_tile_depth(s),
+ * csph_step, csph_advance, csph_autotune) returns CSPH_ERR_ARG and runs no
+ * kernel: remove it from the batch (or destroy the batch) first. */
 csph_status csph_batch_create(csph_dtype dtype, void* hip_stream, size_t hbm_budget,
                               csph_batch** out);
 /* Add a member that stops after `steps` more steps or at t_end (first reached).

@@ -490,6 +490,7 @@ csph_status csph_create_in(const csph_grid_desc* desc, void* hip_stream, void* d
 
 csph_status csph_destroy(csph_sim* s) {
   if (!s) return CSPH_OK;
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   (void)hipStreamSynchronize(s->stream);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->owned) (void)hipFree(s->buf);
@@ -499,6 +500,7 @@ csph_status csph_destroy(csph_sim* s) {
 
 csph_status csph_set_stream(csph_sim* s, void* hip_stream) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->stream = (hipStream_t)hip_stream;
   return CSPH_OK;
@@ -506,6 +508,7 @@ csph_status csph_set_stream(csph_sim* s, void* hip_stream) {
 
 csph_status csph_set_state(csph_sim* s, csph_vars vars, const double* host) {
   if (!s || !host) return fail(CSPH_ERR_ARG, "sim or host array is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   if (vars != CSPH_CONSERVED && vars != CSPH_PRIMITIVE) return fail(CSPH_ERR_ARG, "bad vars");
   const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
   std::vector<double> cons;
@@ -547,6 +550,7 @@ csph_status csph_set_state(csph_sim* s, csph_vars vars, const double* host) {
 
 csph_status csph_set_potential(csph_sim* s, const double* host_psi) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
   s->has_psi = host_psi != nullptr;
   s->psi_host.assign(N, 0.0);
@@ -566,6 +570,7 @@ csph_status csph_set_potential(csph_sim* s, const double* host_psi) {
 
 csph_status csph_set_boundary(csph_sim* s, int32_t face, csph_bc kind, const double inflow_prim[5]) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   if (face < 0 || face > 5) return fail(CSPH_ERR_ARG, "face must be 0..5");
   if (kind < CSPH_PERIODIC || kind > CSPH_REFLECT) return fail(CSPH_ERR_ARG, "bad boundary kind");
   s->bc.kind[face] = (int)kind;
@@ -687,6 +692,7 @@ csph_status csph_get_time(const csph_sim* s, double* t, int64_t* nsteps) {
 
 csph_status csph_set_time(csph_sim* s, double t, int64_t nsteps) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   if (!std::isfinite(t) || nsteps < 0) return fail(CSPH_ERR_ARG, "bad time or step count");
   Ctrl c{};
   csph_status st = read_ctrl(s, &c);

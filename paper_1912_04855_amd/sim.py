@@ -77,7 +77,8 @@ class Sim:
     # ------------------------------------------------------------------ lifetime
     def close(self):
         if self._h:
-            _lib.load().csph_destroy(self._h)
+            # refused (and nothing freed) while the sim is a batch member
+            check(_lib.load().csph_destroy(self._h), "csph_destroy")
             self._h = C.c_void_p()
         self._buf = None
 

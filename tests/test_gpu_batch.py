@@ -101,3 +101,45 @@ def test_batch_admission_budget_and_slot_reuse():
     b.advance(6)
     assert sorted(b.poll()) == sorted(b.members)
     b.close()
+
+
+def test_member_cannot_be_changed_or_freed():
+    """While a simulation belongs to a batch, the calls that would change or free
+    it return CSPH_ERR_ARG before any work is issued; after removal they work."""
+    need_gpu()
+    import ctypes as C
+    from paper_1912_04855_amd import _lib
+    from paper_1912_04855_amd.sim import Batch
+    L = _lib.load()
+    pr = P.sod(16, transverse=4)
+    announce("member_guard", pr.shape)
+    s = gpu_sim(pr, "f32")
+    b = Batch("f32")
+    slot = b.add(s, 5)
+    W = np.ascontiguousarray(pr.prim)
+    h = s.handle
+    inflow = (C.c_double * 5)(1.0, 0.0, 0.0, 0.0, 1.0)
+    calls = {
+        "destroy": lambda: L.csph_destroy(h),
+        "set_stream": lambda: L.csph_set_stream(h, None),
+        "set_state": lambda: L.csph_set_state(h, _lib.PRIMITIVE, W.ctypes.data),
+        "set_potential": lambda: L.csph_set_potential(h, None),
+        "set_boundary": lambda: L.csph_set_boundary(h, 0, _lib.OUTFLOW, inflow),
+        "set_time": lambda: L.csph_set_time(h, 0.0, 0),
+        "set_scheme": lambda: L.csph_set_scheme(h, _lib.LIM_MINMOD, _lib.FLUX_SWEPT_AV),
+        "set_tile_depth": lambda: L.csph_set_tile_depth(h, 8),
+        "step": lambda: L.csph_step(h, 0.0, None),
+        "advance": lambda: L.csph_advance(h, math.inf, 1, None),
+    }
+    for name, fn in calls.items():
+        assert fn() == _lib.ERR_ARG, name
+    with pytest.raises(_lib.CsphError):
+        s.close()
+    # the member is untouched and still advances with the batch
+    b.advance(5)
+    assert b.poll() == [slot]
+    assert s.time()[1] == 5
+    b.remove(slot)
+    assert L.csph_set_time(h, 0.0, 0) == _lib.OK
+    s.close()
+    b.close()
