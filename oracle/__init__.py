@@ -14,14 +14,14 @@ import numpy as np
 from .build import ensure_built
 
 PERIODIC, OUTFLOW, INFLOW, REFLECT = 0, 1, 2, 3
-POS_DISPLACED, POS_LATTICE = 0, 1
+POS_LAGRANGE, POS_DISPLACED, POS_LATTICE = 0, 1, 2
 BASE_POST, BASE_MID = 0, 1
 LIM_MINMOD, LIM_MC, LIM_VANLEER, LIM_SUPERBEE = 0, 1, 2, 3
 FLUX_SWEPT, FLUX_LF, FLUX_SWEPT_AV = 0, 1, 2
-FACE_PARTICLE, FACE_FOOT = 0, 1
+FACE_FOOT, FACE_PARTICLE = 0, 1
 
 FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
-          "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "psis"]
+          "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "psis", "vol", "phis"]
 
 ERRORS = {0: "ok", 1: "bad argument", 2: "out of memory", 5: "non-finite value",
           6: "negative density", 7: "no signal speed (need dt_max)"}
@@ -114,9 +114,9 @@ class OracleSim:
     """One CSPH-TVD simulation on the CPU (FP64, single thread)."""
 
     def __init__(self, shape, h, gamma=1.4, cfl=0.4, rho_vac=1e-10, bc=(PERIODIC,) * 6,
-                 inflow=None, origin=(0.0, 0.0, 0.0), pos_mode=POS_DISPLACED,
+                 inflow=None, origin=(0.0, 0.0, 0.0), pos_mode=POS_LAGRANGE,
                  base_mode=BASE_POST, limiter=LIM_MINMOD, flux=FLUX_SWEPT_AV,
-                 face_mode=FACE_PARTICLE):
+                 face_mode=FACE_FOOT):
         nx, ny, nz = shape
         p = _Params()
         p.nx, p.ny, p.nz = nx, ny, nz

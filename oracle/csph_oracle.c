@@ -42,6 +42,7 @@ struct orc_sim {
   double *ms[3], *Es, *xs[3];
   double *mt[3], *Et, *xt[3];
   double *psis;       /* psi at the predicted particle positions */
+  double *vol;        /* predicted particle volume / h^3 (Lagrangian corrector) */
   /* Eulerian stage */
   double *slope[5], *flux[5], *acc[5];
   double t;
@@ -172,7 +173,8 @@ static void all_primitives(orc_sim* s, const double* rho, double* const m[3], co
  * mirror with the normal momentum and normal offset negated.  The axes are
  * filled in the order x, y, z, each over the full extent of the other two, so
  * edges and corners are the composition of the face rules. */
-enum { R_RHO = 0, R_MX = 1, R_MY = 2, R_MZ = 3, R_E = 4, R_XX = 5, R_XY = 6, R_XZ = 7, R_PSI = 8 };
+enum { R_RHO = 0, R_MX = 1, R_MY = 2, R_MZ = 3, R_E = 4, R_XX = 5, R_XY = 6, R_XZ = 7, R_PSI = 8,
+       R_VOL = 9 };
 
 static double inflow_value(const orc_sim* s, int face, int role, double dt) {
   switch (role) {
@@ -184,6 +186,7 @@ static double inflow_value(const orc_sim* s, int face, int role, double dt) {
     case R_XX: return dt * s->P.inflow[face][1];
     case R_XY: return dt * s->P.inflow[face][2];
     case R_XZ: return dt * s->P.inflow[face][3];
+    case R_VOL: return 1.0; /* a uniform inflow state is not compressed */
     default: return 0.0;
   }
 }
@@ -331,6 +334,29 @@ static void hydro_force(const orc_sim* s, const double* rho, const double* phi,
   *B = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
 }
 
+/* Lattice divergence of a vector field at padded cell c: the same 27-point
+ * kernel gradients on the undisplaced lattice as Q, summed as 13 opposite pairs,
+ *   div_c = sum_{o in O13} (K(-h o) . f_{c+o} + K(h o) . f_{c-o}).
+ * A uniform field gives exactly zero. */
+static double lattice_div(const orc_sim* s, double* const f[3], size_t c) {
+  const long sx = s->sx, sxy = (long)s->sx * (long)s->sy;
+  const double h = s->P.h;
+  double dv = 0.0;
+  for (int q = 0; q < 13; ++q) {
+    double t[2];
+    for (int side = 0; side < 2; ++side) {
+      const int sg = side == 0 ? 1 : -1;
+      const int ox = sg * O13[q][0], oy = sg * O13[q][1], oz = sg * O13[q][2];
+      const size_t j = (size_t)((long)c + ox + oy * sx + oz * sxy);
+      double K[3];
+      kgrad(s, -ox * h, -oy * h, -oz * h, K);
+      t[side] = K[0] * f[0][j] + K[1] * f[1][j] + K[2] * f[2][j];
+    }
+    dv = dv + (t[0] + t[1]);
+  }
+  return dv;
+}
+
 /* ------------------------------------------------------------------------ */
 /* create / destroy / state                                                  */
 /* ------------------------------------------------------------------------ */
@@ -367,7 +393,7 @@ int orc_create(const orc_params* p, orc_sim** out) {
   double** all[] = {&s->rho, &s->m[0], &s->m[1], &s->m[2], &s->E, &s->psi, &s->u[0], &s->u[1],
                     &s->u[2], &s->p, &s->phi, &s->ms[0], &s->ms[1], &s->ms[2], &s->Es, &s->xs[0],
                     &s->xs[1], &s->xs[2], &s->mt[0], &s->mt[1], &s->mt[2], &s->Et, &s->xt[0],
-                    &s->xt[1], &s->xt[2], &s->psis, &s->slope[0], &s->slope[1], &s->slope[2],
+                    &s->xt[1], &s->xt[2], &s->psis, &s->vol, &s->slope[0], &s->slope[1], &s->slope[2],
                     &s->slope[3], &s->slope[4], &s->flux[0], &s->flux[1], &s->flux[2], &s->flux[3],
                     &s->flux[4], &s->acc[0], &s->acc[1], &s->acc[2], &s->acc[3], &s->acc[4]};
   for (size_t k = 0; k < sizeof all / sizeof all[0]; ++k) {
@@ -386,7 +412,7 @@ void orc_destroy(orc_sim* s) {
   double* all[] = {s->rho, s->m[0], s->m[1], s->m[2], s->E, s->psi, s->u[0], s->u[1], s->u[2],
                    s->p, s->phi, s->ms[0], s->ms[1], s->ms[2], s->Es, s->xs[0], s->xs[1],
                    s->xs[2], s->mt[0], s->mt[1], s->mt[2], s->Et, s->xt[0], s->xt[1], s->xt[2],
-                   s->psis, s->slope[0], s->slope[1], s->slope[2], s->slope[3], s->slope[4],
+                   s->psis, s->vol, s->slope[0], s->slope[1], s->slope[2], s->slope[3], s->slope[4],
                    s->flux[0], s->flux[1], s->flux[2], s->flux[3], s->flux[4], s->acc[0],
                    s->acc[1], s->acc[2], s->acc[3], s->acc[4]};
   for (size_t k = 0; k < sizeof all / sizeof all[0]; ++k) free(all[k]);
@@ -464,7 +490,8 @@ int orc_get_field(const orc_sim* s, int which, double* out) {
   if (!s || !out || which < 0 || which >= ORC_F_COUNT) return ORC_ERR_ARG;
   const double* src[ORC_F_COUNT] = {s->ms[0], s->ms[1], s->ms[2], s->Es,    s->xs[0],
                                     s->xs[1], s->xs[2], s->mt[0], s->mt[1], s->mt[2],
-                                    s->Et,    s->xt[0], s->xt[1], s->xt[2], s->psis};
+                                    s->Et,    s->xt[0], s->xt[1], s->xt[2], s->psis,
+                                    s->vol,   s->phi};
   gather(s, src[which], out);
   return ORC_OK;
 }
@@ -583,6 +610,7 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
   /* O2: primitives of U^n on every cell, ghosts included */
   all_primitives(s, s->rho, s->m, s->E);
 
+  const int lagrange = s->P.pos_mode == ORC_POS_LAGRANGE;
   /* O4-O5: predictor, Eq. (5):  U* = U^n + dt Q(U^n, r^n),  r* = r^n + dt (u^n + u*)/2.
    * The particles start at the cell centres; xi* = r* - r^n. */
   for (int k = 0; k < nz; ++k)
@@ -599,6 +627,9 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
         s->xs[0][c] = 0.5 * dt * (s->u[0][c] + usx);
         s->xs[1][c] = 0.5 * dt * (s->u[1][c] + usy);
         s->xs[2][c] = 0.5 * dt * (s->u[2][c] + usz);
+        /* volume of the predicted particle relative to its cell (Lagrangian
+         * corrector): V* / h^3 = 1 + dt div(u^n), to first order in dt */
+        if (lagrange) s->vol[c] = 1.0 + dt * lattice_div(s, s->u, c);
       }
 
   /* O6: ghosts of the predicted particles (rho* = rho^n: mass is untouched) */
@@ -609,6 +640,7 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
   fill_ghosts(s, s->xs[0], R_XX, dt);
   fill_ghosts(s, s->xs[1], R_XY, dt);
   fill_ghosts(s, s->xs[2], R_XZ, dt);
+  if (lagrange) fill_ghosts(s, s->vol, R_VOL, dt);
 
   /* keep u^n for the position update before the primitives are overwritten */
   /* (slopes below use the conserved U^n, which is still intact) */
@@ -622,16 +654,39 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
    *   U~^{n+1} = (U^n + U*)/2 + (dt/2) Q(U*, r*),
    *   r^{n+1}  = (r^n + r*)/2 + (dt/2) (u^n + u^{n+1})/2,
    * where u^{n+1} is read as the post-Lagrange velocity m~/rho.
-   * Default reading: Q(U*, r*) is evaluated at the displaced particles (kernel
-   * gradients at r*_i - r*_j, potential at r*), over the same 3x3x3 index
-   * neighbourhood. */
+   * Reading (ORC_POS_LAGRANGE, the default): the corrector differentiates in the
+   * particles' reference configuration.  Every particle starts the step at its
+   * cell centre, so the kernel gradients of Eq. (7) are the lattice ones, and
+   * the state of particle i at r* enters through its pressure and its potential:
+   * the pressure is its internal energy over its predicted volume,
+   * V*_i = h^3 (1 + dt div(u^n)_i) (the lattice divergence, first order in dt),
+   * and psi is sampled at r*_i.  In one dimension the lattice gradient times the
+   * reference volume is exactly the gradient at r* times the displaced volume,
+   * so this is the Lagrangian form of Q(U*, r*); it keeps the pairwise
+   * antisymmetry of the sums (hence conservation) and the exact rest state
+   * (u = 0 gives V* = h^3).  Evaluating the kernel gradients at the displaced
+   * separations instead (ORC_POS_DISPLACED) adds the zeroth-order consistency
+   * error of SPH: the sum of the gradients of a non-uniformly displaced
+   * neighbourhood is not zero, which acts as a first-order viscosity. */
   all_primitives(s, s->rho, s->ms, s->Es);
   const int displaced = s->P.pos_mode == ORC_POS_DISPLACED;
+  if (lagrange) {
+    /* the pressure of the predicted particle: its internal energy over its
+     * predicted volume, p* = (gamma-1)(E* - m*.u* / 2) / (V* / h^3) */
+    for (int k = -1; k <= nz; ++k)
+      for (int j = -1; j <= ny; ++j)
+        for (int i = -1; i <= nx; ++i) {
+          size_t c = IX(s, i, j, k);
+          s->p[c] = s->p[c] / s->vol[c];
+          s->phi[c] = sqrt(2.0 * s->p[c]);
+        }
+  }
   for (int k = -1; k <= nz; ++k)
     for (int j = -1; j <= ny; ++j)
       for (int i = -1; i <= nx; ++i) {
         size_t c = IX(s, i, j, k);
-        s->psis[c] = displaced ? psi_at(s, c, s->xs[0][c], s->xs[1][c], s->xs[2][c]) : s->psi[c];
+        s->psis[c] = (displaced || lagrange) ? psi_at(s, c, s->xs[0][c], s->xs[1][c], s->xs[2][c])
+                                             : s->psi[c];
       }
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
@@ -671,12 +726,16 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
    *   Phi = max(xi_i, 0) U^L + min(xi_{i+1}, 0) U^R     (= dt * face flux),
    * and Eq. (4) becomes U^{n+1} = U~ - (1/h) sum_d (Phi_{i+1/2} - Phi_{i-1/2}).
    * Each face value is computed once and used by both of its cells.
-   * A second reading of the face speed (face_mode = ORC_FACE_FOOT, not the
-   * default) takes one advective speed per face, the displacement of the
-   * material that reaches the face during the step,
+   * Reading of the swept width (ORC_FACE_FOOT, the default): the face's two
+   * particles are parts of one deforming medium, so the volume that crosses the
+   * face during the step is the displacement of the material that reaches it,
+   * the offset field interpolated linearly between the two particles and taken
+   * at the foot of the face's trajectory,
    *   X = (xi_i + xi_{i+1}) / 2 / (1 + (xi_{i+1} - xi_i) / h),
-   * i.e. the offset field interpolated linearly to the foot of the face's
-   * trajectory, and sweeps Phi = max(X, 0) U^L + min(X, 0) U^R. */
+   * and Phi = max(X, 0) U^L + min(X, 0) U^R.  ORC_FACE_PARTICLE sweeps the upwind
+   * particle's own offset instead (max(xi_i, 0), min(xi_{i+1}, 0)), which treats
+   * each particle as a rigid cube and misplaces the remap's divergence by half a
+   * cell (first order on compressive flow). */
   const double* Un[5] = {s->rho, s->m[0], s->m[1], s->m[2], s->E};
   const double* Ut[5] = {s->rho, s->mt[0], s->mt[1], s->mt[2], s->Et};
   const int mid = s->P.base_mode == ORC_BASE_MID;
@@ -836,7 +895,7 @@ int orc_interp_psi(orc_sim* s, const double* off, double* out) {
 }
 
 int orc_fill_ghosts_padded(orc_sim* s, double* padded, int role, double dt) {
-  if (!s || !padded || role < 0 || role > 8) return ORC_ERR_ARG;
+  if (!s || !padded || role < 0 || role > 9) return ORC_ERR_ARG;
   fill_ghosts(s, padded, role, dt);
   return ORC_OK;
 }

@@ -27,8 +27,15 @@ extern "C" {
 /* boundary kinds (ghost-cell rules; the paper states none) */
 enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1, ORC_INFLOW = 2, ORC_REFLECT = 3 };
 
-/* corrector positions: particles at r* (the literal Eq. (6)) or on the lattice */
-enum { ORC_POS_DISPLACED = 0, ORC_POS_LATTICE = 1 };
+/* Reading of Q(U*, r*) in the corrector of Eq. (6).  The default
+ * (ORC_POS_LAGRANGE) takes the 27-point kernel gradients in the particles'
+ * reference configuration -- the lattice, where every particle starts the step --
+ * and the state of each particle at r*: its pressure over its predicted volume
+ * V* = h^3 (1 + dt div u^n) and the potential sampled at r*.  The alternatives
+ * evaluate the kernel gradients at the displaced pairs r*_i - r*_j with the
+ * volume left at h^3 (ORC_POS_DISPLACED), or put everything on the lattice
+ * (ORC_POS_LATTICE). */
+enum { ORC_POS_LAGRANGE = 0, ORC_POS_DISPLACED = 1, ORC_POS_LATTICE = 2 };
 /* reconstruction base of Eq. (8): U~^{n+1} ("post") or (U^n + U~^{n+1})/2 ("mid") */
 enum { ORC_BASE_POST = 0, ORC_BASE_MID = 1 };
 /* TVD limiters (Sec. 2.2 allows any; Sec. 4 names the choice as an option) */
@@ -37,9 +44,11 @@ enum { ORC_LIM_MINMOD = 0, ORC_LIM_MC = 1, ORC_LIM_VANLEER = 2, ORC_LIM_SUPERBEE
  * swept volume), the same plus the acoustic (Rusanov) velocity-jump dissipation
  * (the default), or Lax-Friedrichs with the advective speeds */
 enum { ORC_FLUX_SWEPT = 0, ORC_FLUX_LF = 1, ORC_FLUX_SWEPT_AV = 2 };
-/* swept width of the swept-volume fluxes: the offset of the upwind particle
- * (xi_i or xi_{i+1}), or the displacement of the particle that reaches the face */
-enum { ORC_FACE_PARTICLE = 0, ORC_FACE_FOOT = 1 };
+/* swept width of the swept-volume fluxes: the displacement of the material that
+ * reaches the face, from the offsets of the face's two particles interpolated
+ * linearly to the foot of the face's trajectory (the default), or the offset of
+ * the upwind particle (xi_i or xi_{i+1}) */
+enum { ORC_FACE_FOOT = 0, ORC_FACE_PARTICLE = 1 };
 
 /* status codes */
 enum {
@@ -76,6 +85,8 @@ enum {
   ORC_F_MTX, ORC_F_MTY, ORC_F_MTZ, ORC_F_ET,         /* corrector m~, E~      */
   ORC_F_XTX, ORC_F_XTY, ORC_F_XTZ,                   /* corrector xi^{n+1}    */
   ORC_F_PSIS,                                        /* psi at r*             */
+  ORC_F_VOL,                                         /* predicted volume / h^3 */
+  ORC_F_PHIS,                                        /* phi* = sqrt(2 p*)      */
   ORC_F_COUNT
 };
 
@@ -105,7 +116,8 @@ int      orc_lattice_gradient(int32_t nx, int32_t ny, int32_t nz, double h,
 /* trilinear interpolation of psi (with ghosts filled by the sim's rules) at
  * cell centre + offset; writes one value per cell */
 int      orc_interp_psi(orc_sim* s, const double* off /* [3][nz][ny][nx] */, double* out);
-/* fill the ghost layers of one cell-shaped array (role: 0 rho,1-3 m,4 E,5-7 xi,8 psi)
+/* fill the ghost layers of one cell-shaped array (role: 0 rho,1-3 m,4 E,5-7 xi,8 psi,
+ * 9 predicted volume)
  * of width nx+4 etc., given dt for inflow xi; used by the BC unit tests */
 int      orc_fill_ghosts_padded(orc_sim* s, double* padded, int role, double dt);
 

@@ -46,6 +46,7 @@ static int run_case(const int bc[6], int nx, int ny, int nz, int vacuum, int psi
   P.gamma = 1.4;
   P.cfl = 0.4;
   P.rho_vac = 1e-10;
+  P.face_mode = (int)(seed & 1u); /* both swept widths */
   for (int f = 0; f < 6; ++f) {
     P.bc[f] = bc[f];
     P.inflow[f][0] = 1.0;
@@ -115,7 +116,7 @@ int main(void) {
                    kinds[(b + 2) % 4], kinds[(b + 2) % 4] == 0 ? 0 : kinds[a]};
       if ((bc[2] == 0) != (bc[3] == 0)) bc[3] = bc[2];
       if ((bc[4] == 0) != (bc[5] == 0)) bc[5] = bc[4];
-      bad |= run_case(bc, 6, 5, 4, 0, 1, ORC_POS_DISPLACED, ORC_BASE_POST, ORC_LIM_MINMOD,
+      bad |= run_case(bc, 6, 5, 4, 0, 1, ORC_POS_LAGRANGE, ORC_BASE_POST, ORC_LIM_MINMOD,
                       ORC_FLUX_SWEPT_AV, 1u + (unsigned)(4 * a + b));
       ++cases;
     }
@@ -123,10 +124,10 @@ int main(void) {
   const int out[6] = {1, 1, 1, 1, 1, 1};
   for (int lim = 0; lim < 4; ++lim)
     for (int flux = 0; flux < 3; ++flux) {
-      bad |= run_case(per, 5, 4, 6, 0, lim & 1, lim & 1, (lim >> 1) & 1, lim, flux, 77u);
+      bad |= run_case(per, 5, 4, 6, 0, lim & 1, lim % 3, (lim >> 1) & 1, lim, flux, 77u + (unsigned)flux);
       ++cases;
     }
-  bad |= run_case(out, 8, 4, 4, 1, 1, ORC_POS_DISPLACED, ORC_BASE_POST, ORC_LIM_MINMOD,
+  bad |= run_case(out, 8, 4, 4, 1, 1, ORC_POS_LAGRANGE, ORC_BASE_POST, ORC_LIM_MINMOD,
                   ORC_FLUX_SWEPT_AV, 5u);
   ++cases;
   /* building blocks */
