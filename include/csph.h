@@ -151,7 +151,8 @@ csph_status csph_totals(const csph_sim* sim, double out[5]);
 /* Intermediate fields of the last step, interior only, host FP64 `[nz][ny][nx]`:
  * which = 0..3 m*, E* (predictor, Eq. (5)); 4..6 xi* (predicted particle
  * offset); 7..10 m~, E~ (corrector, Eq. (6)); 11..13 xi^{n+1} (final particle
- * offset).  The offsets are kept by FP64 simulations only: the FP32 build
+ * offset); 14 phi* = sqrt(2 p*) of the predicted particle, p* its pressure over
+ * its predicted volume.  The offsets are kept by FP64 simulations only: the FP32 build
  * recomputes them from rho, m^n, m* and m~ where it needs them, and returns
  * CSPH_ERR_ARG for which = 4..6 and 11..13. */
 csph_status csph_get_stage(const csph_sim* sim, int32_t which, double* host_out);

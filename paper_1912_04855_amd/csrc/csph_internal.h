@@ -4,8 +4,8 @@
 // (nx+4) x (ny+4) x (nz+4) cells (two ghost layers per face), x fastest, one
 // array per field (structure of arrays), each starting on a 256-byte boundary.
 // Fields: two copies of the conserved state U = (rho, mx, my, mz, E) used in
-// turn as U^n and U^{n+1}; psi; the predictor output (m*, E*, xi*, and psi at
-// r*); the corrector output (m~, E~, xi^{n+1}).  The density never changes in the
+// turn as U^n and U^{n+1}; psi; the predictor output (m*, E*, xi*, psi at r*
+// and phi* of the predicted particle); the corrector output (m~, E~, xi^{n+1}).  The density never changes in the
 // Lagrangian stage, so rho* = rho~ = rho^n is not stored.
 #pragma once
 
@@ -20,7 +20,7 @@ constexpr int kGhost = 2;
 
 // roles of a field for the ghost-cell rules
 enum Role : int {
-  kRho = 0, kMx = 1, kMy = 2, kMz = 3, kE = 4, kXx = 5, kXy = 6, kXz = 7, kPsi = 8
+  kRho = 0, kMx = 1, kMy = 2, kMz = 3, kE = 4, kXx = 5, kXy = 6, kXz = 7, kPsi = 8, kPhi = 9
 };
 enum Bc : int { kPeriodic = 0, kOutflow = 1, kInflow = 2, kReflect = 3 };
 
@@ -39,8 +39,6 @@ struct GridDev {
   double kappa_h2;       // kernel normalisation / h^2
   // 13 lattice kernel gradients K(-h o), o in the half neighbour set
   double klat[13][3];
-  // -h o for the same 13 offsets (the lattice part of a pair separation)
-  double hoff[13][3];
   // Eulerian-stage scheme: TVD limiter and face flux (kLim*, kFlux*)
   int limiter, flux;
   // 1 if a potential was set; 0: psi = 0 everywhere, and psi(r*) stays 0 without
@@ -60,6 +58,7 @@ struct BcDev {
   int kind[6];
   double cons[6][5];     // inflow conserved state per face
   double vel[6][3];      // inflow velocity per face (particle offset = dt * vel)
+  double phi[6];         // sqrt(2 p) of the inflow state per face
 };
 
 // Per-simulation control block in device memory (FP64).
@@ -87,6 +86,7 @@ struct Fields {
   Real* ms[4];   // m*x, m*y, m*z, E*
   Real* xs[3];   // xi*
   Real* psis;    // psi at the predicted particle positions r* = x + xi*
+  Real* phs;     // phi* = sqrt(2 p*), p* the predicted particle's pressure at its predicted volume
   Real* mt[4];   // m~x, m~y, m~z, E~
   Real* xt[3];   // xi^{n+1}
 };

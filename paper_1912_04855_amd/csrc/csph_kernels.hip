@@ -205,50 +205,6 @@ __device__ __forceinline__ Real xi_final(const GridDev& g, Real rho, Real mn, Re
   return hx * xc + qdt * (un + ut);
 }
 
-// M4 cubic spline with support 2h: K(d) = -(kappa/h^2) (g(q)/q) d, q = |d|/h,
-// g(q)/q = 3 - 9q/4 (q < 1), 3(2-q)^2/(4q) (1 <= q < 2), 0 beyond.
-__device__ __forceinline__ void kgrad(const GridDev& g, Real dx, Real dy, Real dz, Real& Kx,
-                                      Real& Ky, Real& Kz) {
-  const Real r2 = dx * dx + dy * dy + dz * dz;
-  Real gq;
-  if constexpr (kF64) {
-    const Real q = sqrt(r2) * (Real)g.inv_h;
-    if (q < (Real)1) {
-      gq = (Real)3 - (Real)2.25 * q;
-    } else if (q < (Real)2) {
-      const Real t = (Real)2 - q;
-      gq = (Real)0.75 * t * t / q;
-    } else {
-      gq = (Real)0;
-    }
-  } else {
-    const Real rs = rsqrt_(r2);                  // 1/|d|
-    const Real q = r2 * rs * (Real)g.inv_h;      // |d|/h
-    // (3/4)(2-q)^2/q = 3/q - 3 + (3/4) q
-    const Real far = (Real)3 * (rs * (Real)g.h) - (Real)3 + (Real)0.75 * q;
-    gq = q < (Real)1 ? (Real)3 - (Real)2.25 * q : (q < (Real)2 ? far : (Real)0);
-  }
-  const Real c = (Real)g.kappa_h2 * gq;
-  Kx = -(c * dx);
-  Ky = -(c * dy);
-  Kz = -(c * dz);
-}
-
-// FP32 form of the same gradient with the separation in lattice units (d/h):
-// g(q) = (3/4)[(2-q)_+^2 - 4 (1-q)_+^2] covers both spline pieces without a
-// branch.  The result is K / ck, with K = ck (g(q)/q)/(3/4) d and ck = -(3/4) kappa / h:
-// every sum the corrector forms is linear in K, so the caller applies ck once per cell.
-__device__ __forceinline__ void kgrad_lat(float dx, float dy, float dz, float K[3]) {
-  const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 1e-12f);
-  const float rs = __builtin_amdgcn_rsqf(r2);
-  // q = r2 rs = |d|
-  const float t = fmaxf(fmaf(-r2, rs, 2.0f), 0.0f), u = fmaxf(fmaf(-r2, rs, 1.0f), 0.0f);
-  const float c = rs * fmaf(t, t, -4.0f * u * u);
-  K[0] = c * dx;
-  K[1] = c * dy;
-  K[2] = c * dz;
-}
-
 __device__ __forceinline__ Real minmod(Real a, Real b) {
   if (a * b <= (Real)0) return (Real)0;
   const Real sg = a > (Real)0 ? (Real)1 : (Real)-1;
@@ -423,6 +379,15 @@ __device__ __forceinline__ GhostSrc ghost_src(const GridDev& g, const BcDev& bc,
   return r;
 }
 
+// Dirichlet value of a field with the given role at an inflow face: the face's
+// conserved state, its particle offset dt * u_in, or phi = sqrt(2 p_in) (a uniform
+// inflow state is not compressed: its predicted volume is the cell's)
+__device__ __forceinline__ Real inflow_value(const BcDev& bc, int face, int role, double dt) {
+  if (role <= kE) return (Real)bc.cons[face][role];
+  if (role == kPhi) return (Real)bc.phi[face];
+  return (Real)(dt * bc.vel[face][role - kXx]);
+}
+
 // value of a field with the given role at a ghost cell
 __device__ __forceinline__ Real ghost_get(const BcDev& bc, const GhostSrc& m, const Real* f, int role,
                                           double dt) {
@@ -430,10 +395,7 @@ __device__ __forceinline__ Real ghost_get(const BcDev& bc, const GhostSrc& m, co
   if (role >= kMx && role <= kMz) axis = role - kMx;
   if (role >= kXx && role <= kXz) axis = role - kXx;
   const Real sign = (axis >= 0 && ((m.flip >> axis) & 1)) ? (Real)-1 : (Real)1;
-  if (m.inflow >= 0) {
-    const Real v = role <= kE ? (Real)bc.cons[m.inflow][role] : (Real)(dt * bc.vel[m.inflow][role - kXx]);
-    return sign * v;
-  }
+  if (m.inflow >= 0) return sign * inflow_value(bc, m.inflow, role, dt);
   return sign * f[m.src];
 }
 
@@ -479,7 +441,7 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
       ms[q] = ghost_get(bc, m, F.ms[q], kMx + q, dt);
       F.ms[q][cg] = ms[q];
     }
-    F.ms[3][cg] = ghost_get(bc, m, F.ms[3], kE, dt);
+    F.phs[cg] = ghost_get(bc, m, F.phs, kPhi, dt);
     if constexpr (kKeepXiStar) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -599,7 +561,7 @@ __device__ __forceinline__ void x_push(const GridDev& g, const BcDev& bc, int i,
 // components at a reflecting face) or the inflow face's state
 __device__ __forceinline__ Real x_ghost_value(const BcDev& bc, Real v, int role, bool flip, int face,
                                               double dt) {
-  if (face >= 0) return role <= kE ? (Real)bc.cons[face][role] : (Real)(dt * bc.vel[face][role - kXx]);
+  if (face >= 0) return inflow_value(bc, face, role, dt);
   return (flip && (role == kMx || role == kXx)) ? -v : v;
 }
 
@@ -722,17 +684,27 @@ __global__ void k_end_batch(const Inst<Real>* __restrict__ tab, int n, int* __re
 __device__ __forceinline__ int ring3(int k) { return ((k % 3) + 3) % 3; }
 __device__ __forceinline__ int hidx(int hx, int hy) { return hy * HX + hx; }
 
-// ==================================================================== stage P
-// Predictor, Eq. (5): m* = m - dt A, E* = E - dt B with Q = -(0, A, B) of Eq. (7)
-// on the lattice; xi* = dt (u^n + u*)/2; psi* = psi(x + xi*).
-struct PlaneP {
+// ==================================================================== stages P and C
+// Both Lagrangian sweeps evaluate Q = -(0, A, B) of Eq. (7) with the kernel
+// gradients of the particles' reference configuration: every particle starts the
+// step at its cell centre, so these are the 13 lattice gradients K(-h o) (and
+// their negatives), with pressure and potential in one pair-difference sum.
+//   stage P, predictor (Eq. (5)), on U^n: m* = m - dt A, E* = E - dt B,
+//     xi* = dt (u^n + u*)/2, psi* = psi(x + xi*), and phi* = sqrt(2 p*) of the
+//     predicted particle, p* its internal energy over its predicted volume
+//     V*/h^3 = 1 + dt div(u^n) (the lattice divergence);
+//   stage C, corrector (Eq. (6)), on the predicted particles (rho, u* = m*/rho,
+//     phi*, psi*): m~ = (m + m*)/2 - (dt/2) A*, E~ likewise, and in FP64
+//     xi^{n+1} = xi*/2 + dt (u^n + u~)/4 (FP32 forms it in stage E).
+struct PlaneL {
   Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP], psi[3][HP];
 };
 
-// kPsi: a potential is set (g.psi); without one psi = 0 and psi(r*) stays 0.
-// The plane buffers S belong to the kernel, so both forms share them.
-template <bool kPsi>
-__device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
+// kCorr: stage C (else P).  kPsi: a potential is set (g.psi); without one psi = 0
+// and psi(r*) stays 0.  The plane buffers S belong to the kernel, so every form
+// shares them.
+template <bool kCorr, bool kPsi>
+__device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              const Ctrl* __restrict__ ctrl, const Tile& T) {
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
@@ -740,7 +712,12 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
   const Real* __restrict__ MY = F.U[par][2];
   const Real* __restrict__ MZ = F.U[par][3];
   const Real* __restrict__ EE = F.U[par][4];
-  const Real* __restrict__ PS = F.psi;
+  // the fields the planes are formed from: U^n and psi (P), m*, phi*, psi* (C)
+  const Real* __restrict__ LX = kCorr ? F.ms[0] : MX;
+  const Real* __restrict__ LY = kCorr ? F.ms[1] : MY;
+  const Real* __restrict__ LZ = kCorr ? F.ms[2] : MZ;
+  const Real* __restrict__ LE = kCorr ? F.phs : EE;
+  const Real* __restrict__ PS = kCorr ? F.psis : F.psi;
   const double dt = ctrl->dt;
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int i = T.x0 + tx, j = T.y0 + ty;
@@ -756,14 +733,21 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
       if (ii > g.nx || jj > g.ny) continue;
       const uint32_t ob = opaque32(in_plane(g, ii, jj));
       const Real r = *at_plane(R, pz, ob);
-      Real ux, uy, uz, p;
-      primitive(g, r, *at_plane(MX, pz, ob), *at_plane(MY, pz, ob), *at_plane(MZ, pz, ob), *at_plane(EE, pz, ob),
-                ux, uy, uz, p);
+      Real u[3], ph;
+      if constexpr (kCorr) {
+        velocity(g, r, *at_plane(LX, pz, ob), *at_plane(LY, pz, ob), *at_plane(LZ, pz, ob), u);
+        ph = *at_plane(LE, pz, ob);
+      } else {
+        Real p;
+        primitive(g, r, *at_plane(LX, pz, ob), *at_plane(LY, pz, ob), *at_plane(LZ, pz, ob),
+                  *at_plane(LE, pz, ob), u[0], u[1], u[2], p);
+        ph = sqrt_fast((Real)2 * p);
+      }
       S.rho[s][q] = r;
-      S.phi[s][q] = sqrt_fast((Real)2 * p);
-      S.ux[s][q] = ux;
-      S.uy[s][q] = uy;
-      S.uz[s][q] = uz;
+      S.phi[s][q] = ph;
+      S.ux[s][q] = u[0];
+      S.uy[s][q] = u[1];
+      S.uz[s][q] = u[2];
       S.psi[s][q] = kPsi ? *at_plane(PS, pz, ob) : (Real)0;
     }
   };
@@ -783,8 +767,8 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
       const Real* uy_ = &S.uy[0][0];
       const Real* uz_ = &S.uz[0][0];
       const Real* psi_ = &S.psi[0][0];
-      Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
-      Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0;
+      Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0, dv = 0.0;
+      Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0, dvf = 0;
 #pragma unroll
       for (int q = 0; q < 13; ++q) {
         const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
@@ -793,7 +777,7 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
         if constexpr (kF64) {
           // the two terms of the pair, each as the scheme writes it, then their sum;
           // components whose offset is 0 carry an exact zero and are skipped
-          Acc ta[2][3], tg[2][3], te[2];
+          Acc ta[2][3], tg[2][3], te[2], td[2];
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
             const int n = side == 0 ? np : nm;
@@ -814,6 +798,14 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
             tg[side][1] = dpsi * ky;
             tg[side][2] = dpsi * kz;
             te[side] = ff * ub;
+            if constexpr (!kCorr) {
+              // K . u^n of the neighbour, for the lattice divergence
+              Acc t = kx * ux_[n];
+              if (ox == 0) t = ky * uy_[n];
+              else if (oy != 0) t = t + ky * uy_[n];
+              if (oz != 0) t = t + kz * uz_[n];
+              td[side] = t;
+            }
           }
           if (ox != 0) {
             a[0] = a[0] + (ta[0][0] + ta[1][0]);
@@ -828,6 +820,7 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
             gp[2] = gp[2] + (tg[0][2] + tg[1][2]);
           }
           be = be + (te[0] + te[1]);
+          if constexpr (!kCorr) dv = dv + (td[0] + td[1]);
         } else {
           // pair difference phi_c (phi_+ - phi_-) + rho_c (psi_+ - psi_-): the FP32
           // differences are exact for neighbours within a factor 2, the combination
@@ -851,292 +844,123 @@ __device__ __forceinline__ void stage_p_body(PlaneP& S, const Fields<Real>& F, c
           if (ox != 0) {
             upk += (uc[0] + ux_[np]) * Kx;
             umk += (uc[0] + ux_[nm]) * Kx;
+            if constexpr (!kCorr) dvf = fmaf(Kx, ux_[np] - ux_[nm], dvf);
           }
           if (oy != 0) {
             upk += (uc[1] + uy_[np]) * Ky;
             umk += (uc[1] + uy_[nm]) * Ky;
+            if constexpr (!kCorr) dvf = fmaf(Ky, uy_[np] - uy_[nm], dvf);
           }
           if (oz != 0) {
             upk += (uc[2] + uz_[np]) * Kz;
             umk += (uc[2] + uz_[nm]) * Kz;
+            if constexpr (!kCorr) dvf = fmaf(Kz, uz_[np] - uz_[nm], dvf);
           }
           bf += (Real)0.5 * fc * (phi_[np] * upk - phi_[nm] * umk);
         }
       }
       const long long c = cell(g, i, j, k);
-      Real ms[3], Es;
+      // A and B of this cell
+      Real Av[3], Bv;
+      if constexpr (kF64) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Av[d] = a[d];
+        Bv = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Av[d] = af[d];
+        Bv = bf + rc * (uc[0] * gf[0] + uc[1] * gf[1] + uc[2] * gf[2]);
+      }
       const Real m0[3] = {MX[c], MY[c], MZ[c]};
-      if constexpr (kF64) {
-        const Acc B = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
+      if constexpr (!kCorr) {
+        // ---------------------------------------------------------- predictor
+        Real ms[3], Es;
+        if constexpr (kF64) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ms[d] = m0[d] - dt * a[d];
-        Es = EE[c] - dt * B;
-      } else {
-        const Real B = bf + rc * (uc[0] * gf[0] + uc[1] * gf[1] + uc[2] * gf[2]);
-        const Real rdt = (Real)dt;
+          for (int d = 0; d < 3; ++d) ms[d] = m0[d] - dt * Av[d];
+          Es = EE[c] - dt * Bv;
+        } else {
+          const Real rdt = (Real)dt;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ms[d] = m0[d] - rdt * af[d];
-        Es = EE[c] - rdt * B;
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) F.ms[d][c] = ms[d];
-      F.ms[3][c] = Es;
-      Real us[3], ps;
-      primitive(g, rc, ms[0], ms[1], ms[2], Es, us[0], us[1], us[2], ps);
-      Real xi[3];
-      xi_star(uc, us, (Real)(0.5 * dt), xi);
-      if constexpr (kKeepXiStar) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) F.xs[d][c] = xi[d];
-      }
-      if constexpr (kPsi) {
-        auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
-        F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
-      }
-      if (kPushX && (i < 2 || i >= g.nx - 2)) {
-        // x ghosts of the predicted particles (psi at their positions is left to
-        // the fill kernel: it needs loads that would stall this sweep)
-        x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
-          const long long cg = cell(g, gi, j, k);
-          F.ms[0][cg] = x_ghost_value(bc, ms[0], kMx, flip, face, dt);
-          F.ms[1][cg] = x_ghost_value(bc, ms[1], kMy, flip, face, dt);
-          F.ms[2][cg] = x_ghost_value(bc, ms[2], kMz, flip, face, dt);
-          F.ms[3][cg] = x_ghost_value(bc, Es, kE, flip, face, dt);
-        });
-      }
-    }
-    lds_barrier();
-  }
-}
-
-// ==================================================================== stage C
-// Corrector, Eq. (6): m~ = (m + m*)/2 - (dt/2) A*, E~ likewise, with Q(U*, r*)
-// evaluated at the displaced particles r* = x + xi* (kernel gradients of the
-// displaced pairs, psi at r*); xi = xi*/2 + dt (u^n + u~)/4.
-// Four values of a cell kept as one aligned LDS vector, so that a neighbour's values
-// cost one vector read at an immediate offset from the plane's base.
-struct alignas(4 * sizeof(Real)) Quad {
-  Real x, y, z, w;
-};
-// Per cell of a plane: a = (xi_x, xi_y, xi_z, phi), b = (u_x, u_y, u_z, psi).
-struct PlaneC {
-  Quad a[3][HP], b[3][HP];
-  Real rho[3][HP];
-};
-
-template <bool kPsi>
-__device__ __forceinline__ void stage_c_body(PlaneC& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
-                                             const Ctrl* __restrict__ ctrl, const Tile& T) {
-  const int par = ctrl->par;
-  const Real* __restrict__ R = F.U[par][0];
-  const Real* __restrict__ MSX = F.ms[0];
-  const Real* __restrict__ MSY = F.ms[1];
-  const Real* __restrict__ MSZ = F.ms[2];
-  const Real* __restrict__ ES = F.ms[3];
-  const double dt = ctrl->dt;
-  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
-  const int i = T.x0 + tx, j = T.y0 + ty;
-  const bool in = i < g.nx && j < g.ny;
-  const uint32_t oc = in ? in_plane(g, i, j) : 0u;  // this column's cell in a plane
-  const Real ih = (Real)g.inv_h;
-
-  auto load = [&](int k) {
-    const int s = ring3(k);
-    const long long pz = plane0(g, k);
-    for (int q = tid; q < HP; q += NT) {
-      const int hx = q % HX, hy = q / HX;
-      const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
-      if (ii > g.nx || jj > g.ny) continue;
-      const uint32_t ob = opaque32(in_plane(g, ii, jj));
-      const Real r = *at_plane(R, pz, ob);
-      Real ux, uy, uz, p;
-      primitive(g, r, *at_plane(MSX, pz, ob), *at_plane(MSY, pz, ob), *at_plane(MSZ, pz, ob),
-                *at_plane(ES, pz, ob), ux, uy, uz, p);
-      S.rho[s][q] = r;
-      Real xi[3];
-      if constexpr (kKeepXiStar) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xi[d] = *at_plane(F.xs[d], pz, ob);
-      } else {
-        // xi* from rho, m^n and m* (u* = (ux, uy, uz) above), as stage P formed it;
-        // kept in lattice units
-        Real un[3];
-        const Real us[3] = {ux, uy, uz};
-        velocity(g, r, *at_plane(F.U[par][1], pz, ob), *at_plane(F.U[par][2], pz, ob),
-                 *at_plane(F.U[par][3], pz, ob), un);
-        xi_star(un, us, (Real)(0.5 * dt), xi);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xi[d] *= ih;
-      }
-      S.a[s][q] = Quad{xi[0], xi[1], xi[2], sqrt_fast((Real)2 * p)};
-      S.b[s][q] = Quad{ux, uy, uz, kPsi ? *at_plane(F.psis, pz, ob) : (Real)0};
-    }
-  };
-
-  load(T.z0 - 1);
-  load(T.z0);
-  for (int k = T.z0; k < T.z1; ++k) {
-    load(k + 1);
-    lds_barrier();
-    if (in) {
-      const int s0 = ring3(k), c0 = hidx(tx + 1, ty + 1);
-      auto nb = [&](int ox, int oy, int oz) { return ring3(k + oz) * HP + hidx(tx + 1 + ox, ty + 1 + oy); };
-      const Quad* A_ = &S.a[0][0];
-      const Quad* B_ = &S.b[0][0];
-      const Quad Ac = S.a[s0][c0], Bc = S.b[s0][c0];
-      const Real rc = S.rho[s0][c0], fc = Ac.w, psc = Bc.w;
-      const Real uc[3] = {Bc.x, Bc.y, Bc.z};
-      const Real xc[3] = {Ac.x, Ac.y, Ac.z};
-      Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
-      Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0;
-      const int tb = hidx(tx + 1, ty + 1);
-      if constexpr (kF64) {
-#pragma unroll 1
-        for (int q = 0; q < 13; ++q) {
-          const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
-          // LDS index of the two partners: this thread's cell + a uniform offset
-          const int np = tb + ring3(k + oz) * HP + oy * HX + ox;
-          const int nm = tb + ring3(k - oz) * HP - oy * HX - ox;
-          const Real hx = (Real)g.hoff[q][0], hy = (Real)g.hoff[q][1], hz = (Real)g.hoff[q][2];
-          Real K[2][3], ub[2], fn[2], pn[2];
-#pragma unroll
-          for (int side = 0; side < 2; ++side) {
-            const int n = side == 0 ? np : nm;
-            const Quad An = A_[n], Bn = B_[n];
-            // separation r_c - r_n = -h o + (xi_c - xi_n) (o -> -o on the minus side)
-            const Real dx = side == 0 ? hx + (xc[0] - An.x) : (xc[0] - An.x) - hx;
-            const Real dy = side == 0 ? hy + (xc[1] - An.y) : (xc[1] - An.y) - hy;
-            const Real dz = side == 0 ? hz + (xc[2] - An.z) : (xc[2] - An.z) - hz;
-            kgrad(g, dx, dy, dz, K[side][0], K[side][1], K[side][2]);
-            fn[side] = An.w;
-            pn[side] = Bn.w;
-            ub[side] = (uc[0] + Bn.x) * K[side][0] + (uc[1] + Bn.y) * K[side][1] +
-                       (uc[2] + Bn.z) * K[side][2];
-            ub[side] = 0.5 * ub[side];
-          }
-          {
-            Acc sp[2], dpsi[2], ff[2];
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-              ff[side] = fc * fn[side];
-              dpsi[side] = pn[side] - psc;
-              sp[side] = ff[side] + rc * dpsi[side];
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              a[d] = a[d] + (sp[0] * K[0][d] + sp[1] * K[1][d]);
-              gp[d] = gp[d] + (dpsi[0] * K[0][d] + dpsi[1] * K[1][d]);
-            }
-            be = be + (ff[0] * ub[0] + ff[1] * ub[1]);
-          }
-        }
-      } else {
-        // the 13 pairs unrolled with their offsets known at compile time; the
-        // separations are in lattice units: d = (xi_c - xi_n)/h -+ o.  The sums
-        // are formed with K / ck and scaled by ck after the loop.
-        const float ck = (float)(-0.75 * g.kappa_h2 * g.h);
-        const int bm = ring3(k - 1) * HP + tb, b0 = ring3(k) * HP + tb, bp = ring3(k + 1) * HP + tb;
-        // xi_c/h - 1 and xi_c/h + 1 per axis: a partner at s = +-1 along an axis
-        // is then at d = (xi_c/h - s) - xi_n/h there
-        const Real xlo[3] = {xc[0] - (Real)1, xc[1] - (Real)1, xc[2] - (Real)1};
-        const Real xhi[3] = {xc[0] + (Real)1, xc[1] + (Real)1, xc[2] + (Real)1};
-#pragma unroll
-        for (int q = 0; q < 13; ++q) {
-          const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
-          const int np = (oz == 0 ? b0 : bp) + oy * HX + ox;
-          const int nm = (oz == 0 ? b0 : bm) - oy * HX - ox;
-          float K[2][3], ub[2], fn[2], pn[2];
-#pragma unroll
-          for (int side = 0; side < 2; ++side) {
-            const int n = side == 0 ? np : nm;
-            const int sg = side == 0 ? 1 : -1;
-            const Quad An = A_[n], Bn = B_[n];
-            auto xo = [&](int c, int so) { return so > 0 ? xlo[c] : so < 0 ? xhi[c] : xc[c]; };
-            const float d[3] = {(float)(xo(0, sg * ox) - An.x), (float)(xo(1, sg * oy) - An.y),
-                                (float)(xo(2, sg * oz) - An.z)};
-            kgrad_lat(d[0], d[1], d[2], K[side]);
-            fn[side] = An.w;
-            pn[side] = Bn.w;
-            ub[side] = (uc[0] + Bn.x) * K[side][0] + (uc[1] + Bn.y) * K[side][1] +
-                       (uc[2] + Bn.z) * K[side][2];
-          }
-          // sp+ K+ + sp- K- = (sp+ - sp-) K+ + sp- (K+ + K-).  The difference
-          // sp+ - sp- = phi_c (phi+ - phi-) + rho_c (psi+ - psi-) carries the
-          // well-balance cancellation: its two FP32 differences are exact for
-          // neighbours within a factor 2, and their combination is a compensated
-          // sum (the first product's rounding error, exact by a fused multiply-add,
-          // is added back), as accurate as forming it in FP64.  K+ + K- vanishes on
-          // the lattice, so the large sp- meets only a small factor.
-          const Real dphi = fn[0] - fn[1], dps = pn[0] - pn[1];
-          const float pr = fc * dphi;
-          const float pe = fmaf(fc, dphi, -pr);
-          const float dsp = fmaf(rc, dps, pr) + pe;
-          const Real d0 = pn[0] - psc, d1 = pn[1] - psc;
-          const Real spm = fc * fn[1] + rc * d1;
-          // each term goes straight into its accumulator (one fused multiply-add each)
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            af[d] = fmaf(dsp, K[0][d], af[d]);
-            af[d] = fmaf(spm, K[0][d] + K[1][d], af[d]);
-            gf[d] = fmaf(d0, K[0][d], gf[d]);
-            gf[d] = fmaf(d1, K[1][d], gf[d]);
-          }
-          bf = fmaf(fn[0], ub[0], bf);
-          bf = fmaf(fn[1], ub[1], bf);
+          for (int d = 0; d < 3; ++d) ms[d] = m0[d] - rdt * Av[d];
+          Es = EE[c] - rdt * Bv;
         }
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          af[d] *= ck;
-          gf[d] *= ck;
+        for (int d = 0; d < 3; ++d) F.ms[d][c] = ms[d];
+        F.ms[3][c] = Es;
+        Real us[3], ps;
+        primitive(g, rc, ms[0], ms[1], ms[2], Es, us[0], us[1], us[2], ps);
+        // phi* of the predicted particle: its pressure over its predicted volume
+        Real phs;
+        if constexpr (kF64) {
+          const Real vol = 1.0 + dt * dv;
+          const Real pv = ps / vol;
+          phs = sqrt(2.0 * pv);
+        } else {
+          const float vol = fmaf((float)dt, dvf, 1.0f);
+          phs = sqrt_fast((Real)2 * (ps * __builtin_amdgcn_rcpf(vol)));
         }
-        bf *= (Real)0.5 * fc * ck;
-      }
-      const long long pz = plane0(g, k);
-      const uint32_t o = opaque32(oc);
-      const Real m0[3] = {*at_plane(F.U[par][1], pz, o), *at_plane(F.U[par][2], pz, o),
-                          *at_plane(F.U[par][3], pz, o)};
-      const Real E0 = *at_plane(F.U[par][4], pz, o);
-      Real un[3], pn;
-      primitive(g, rc, m0[0], m0[1], m0[2], E0, un[0], un[1], un[2], pn);
-      const Real msc[3] = {*at_plane(MSX, pz, o), *at_plane(MSY, pz, o), *at_plane(MSZ, pz, o)};
-      const Real Esc = *at_plane(ES, pz, o);
-      Real mt[3], Et;
-      if constexpr (kF64) {
-        const Acc B = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
-        const Acc hdt = 0.5 * dt;
+        F.phs[c] = phs;
+        Real xi[3];
+        xi_star(uc, us, (Real)(0.5 * dt), xi);
+        if constexpr (kKeepXiStar) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) mt[d] = 0.5 * (m0[d] + msc[d]) - hdt * a[d];
-        Et = 0.5 * (E0 + Esc) - hdt * B;
+          for (int d = 0; d < 3; ++d) F.xs[d][c] = xi[d];
+        }
+        if constexpr (kPsi) {
+          auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
+          F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
+        }
+        if (kPushX && (i < 2 || i >= g.nx - 2)) {
+          // x ghosts of the predicted particles (psi at their positions is left to
+          // the fill kernel: it needs loads that would stall this sweep)
+          x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
+            const long long cg = cell(g, gi, j, k);
+            F.ms[0][cg] = x_ghost_value(bc, ms[0], kMx, flip, face, dt);
+            F.ms[1][cg] = x_ghost_value(bc, ms[1], kMy, flip, face, dt);
+            F.ms[2][cg] = x_ghost_value(bc, ms[2], kMz, flip, face, dt);
+            F.phs[cg] = x_ghost_value(bc, phs, kPhi, flip, face, dt);
+          });
+        }
       } else {
-        const Real B = bf + rc * (uc[0] * gf[0] + uc[1] * gf[1] + uc[2] * gf[2]);
-        const Real hdt = (Real)(0.5 * dt);
+        // ---------------------------------------------------------- corrector
+        const Real E0 = EE[c];
+        const Real msc[3] = {F.ms[0][c], F.ms[1][c], F.ms[2][c]};
+        const Real Esc = F.ms[3][c];
+        Real mt[3], Et;
+        if constexpr (kF64) {
+          const Acc hdt = 0.5 * dt;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) mt[d] = (Real)0.5 * (m0[d] + msc[d]) - hdt * af[d];
-        Et = (Real)0.5 * (E0 + Esc) - hdt * B;
-      }
+          for (int d = 0; d < 3; ++d) mt[d] = 0.5 * (m0[d] + msc[d]) - hdt * Av[d];
+          Et = 0.5 * (E0 + Esc) - hdt * Bv;
+        } else {
+          const Real hdt = (Real)(0.5 * dt);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) *at_plane(F.mt[d], pz, o) = mt[d];
-      *at_plane(F.mt[3], pz, o) = Et;
-      Real ut[3], pt;
-      primitive(g, rc, mt[0], mt[1], mt[2], Et, ut[0], ut[1], ut[2], pt);
-      const Real qdt = (Real)(0.25 * dt);
-      // xi^{n+1} = xi*/2 + dt (u^n + u~)/4 (the FP32 LDS holds xi*/h)
-      const Real hx = kF64 ? (Real)0.5 : (Real)(0.5 * g.h);
-      Real xn[3];
+          for (int d = 0; d < 3; ++d) mt[d] = (Real)0.5 * (m0[d] + msc[d]) - hdt * Av[d];
+          Et = (Real)0.5 * (E0 + Esc) - hdt * Bv;
+        }
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xn[d] = hx * xc[d] + qdt * (un[d] + ut[d]);
-        if constexpr (kKeepXi) *at_plane(F.xt[d], pz, o) = xn[d];
-      }
-      if (kPushX && (i < 2 || i >= g.nx - 2)) {
-        // x ghosts of the post-Lagrange particles
-        x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
-          const long long cg = cell(g, gi, j, k);
-          F.mt[0][cg] = x_ghost_value(bc, mt[0], kMx, flip, face, dt);
-          F.mt[1][cg] = x_ghost_value(bc, mt[1], kMy, flip, face, dt);
-          F.mt[2][cg] = x_ghost_value(bc, mt[2], kMz, flip, face, dt);
-          F.mt[3][cg] = x_ghost_value(bc, Et, kE, flip, face, dt);
-        });
+        for (int d = 0; d < 3; ++d) F.mt[d][c] = mt[d];
+        F.mt[3][c] = Et;
+        if constexpr (kKeepXi) {
+          // xi^{n+1} = xi*/2 + dt (u^n + u~)/4
+          Real un[3], ut[3], pn, pt;
+          primitive(g, rc, m0[0], m0[1], m0[2], E0, un[0], un[1], un[2], pn);
+          primitive(g, rc, mt[0], mt[1], mt[2], Et, ut[0], ut[1], ut[2], pt);
+          const Real qdt = (Real)(0.25 * dt);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) F.xt[d][c] = (Real)0.5 * F.xs[d][c] + qdt * (un[d] + ut[d]);
+        }
+        if (kPushX && (i < 2 || i >= g.nx - 2)) {
+          // x ghosts of the post-Lagrange particles
+          x_push<1>(g, bc, i, [&](int gi, bool flip, int face) {
+            const long long cg = cell(g, gi, j, k);
+            F.mt[0][cg] = x_ghost_value(bc, mt[0], kMx, flip, face, dt);
+            F.mt[1][cg] = x_ghost_value(bc, mt[1], kMy, flip, face, dt);
+            F.mt[2][cg] = x_ghost_value(bc, mt[2], kMz, flip, face, dt);
+            F.mt[3][cg] = x_ghost_value(bc, Et, kE, flip, face, dt);
+          });
+        }
       }
     }
     lds_barrier();
@@ -1184,8 +1008,11 @@ __device__ __forceinline__ Real limit(int kind, Real a, Real b) {
   return sg * fmin(aa, ab);
 }
 
-// Swept content of one face (Eq. (8) shifted reconstruction, HLL with the
-// advective speeds = max(xi_L,0) U^L + min(xi_R,0) U^R, plus the damping).
+// Swept content of one face: Eq. (8) shifted reconstruction, HLL with the
+// advective speed = max(X,0) U^L + min(X,0) U^R, plus the damping.  X is the
+// displacement of the material that reaches the face, the particle offsets
+// interpolated linearly between the face's two particles and taken at the foot
+// of the face's trajectory: X = (xi_L + xi_R)/2 / (1 + (xi_R - xi_L)/h).
 // kGen: the limiter and flux of the grid's scheme (g.limiter, g.flux) instead of
 // the default minmod + swept volume with damping.
 // u4[v][0..3]: component v of U^n at cells L-1, L, L+1 (= R), R+1;
@@ -1197,6 +1024,7 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
   if constexpr (kGen) {
     const Real nuL = xL * (Real)g.inv_h;
     const Real nuR = xR * (Real)g.inv_h;
+    const Real X = (Real)0.5 * (xL + xR) / ((Real)1 + (xR - xL) * (Real)g.inv_h);
     Real UL[5], UR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -1209,7 +1037,7 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
         const Real a = fmax(fabs(xL), fabs(xR));
         Fo[v] = (Real)0.5 * (xL * UL[v] + xR * UR[v]) - (Real)0.5 * a * (UR[v] - UL[v]);
       } else {
-        Fo[v] = fmax(xL, (Real)0) * UL[v] + fmin(xR, (Real)0) * UR[v];
+        Fo[v] = fmax(X, (Real)0) * UL[v] + fmin(X, (Real)0) * UR[v];
       }
     }
     if (g.flux == kFluxSweptAV) {
@@ -1221,6 +1049,7 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
   } else if constexpr (kF64) {
     const Real nuL = xL * (Real)g.inv_h;
     const Real nuR = xR * (Real)g.inv_h;
+    const Real X = (Real)0.5 * (xL + xR) / ((Real)1 + (xR - xL) * (Real)g.inv_h);
     Real UL[5], UR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -1228,7 +1057,7 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
       const Real sR = minmod(u4[v][3] - u4[v][2], u4[v][2] - u4[v][1]);
       UL[v] = bL[v] + (Real)0.5 * ((Real)1 - nuL) * sL;
       UR[v] = bR[v] - (Real)0.5 * ((Real)1 + nuR) * sR;
-      Fo[v] = fmax(xL, (Real)0) * UL[v] + fmin(xR, (Real)0) * UR[v];
+      Fo[v] = fmax(X, (Real)0) * UL[v] + fmin(X, (Real)0) * UR[v];
     }
     Real D[5];
     acoustic_dissipation(g, axis, UL, UR, D);
@@ -1237,9 +1066,10 @@ __device__ __forceinline__ void face_flux(const GridDev& g, int axis, const Real
   } else {
     // minmod(a, b) is the median of (a, b, 0); the reconstruction weights
     // (1 -+ xi/h)/2 and the swept fractions are formed once per face
-    const float hh = 0.5f * (float)g.inv_h;
+    const float ih = (float)g.inv_h, hh = 0.5f * ih;
     const float wL = fmaf(xL, -hh, 0.5f), wR = fmaf(xR, hh, 0.5f);
-    const float pL = fmaxf(xL, 0.0f), pR = fminf(xR, 0.0f);
+    const float X = (0.5f * (xL + xR)) * __builtin_amdgcn_rcpf(fmaf(xR - xL, ih, 1.0f));
+    const float pL = fmaxf(X, 0.0f), pR = fminf(X, 0.0f);
     float UL[5], UR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -1610,20 +1440,20 @@ __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  __shared__ PlaneP S;
-  if (g.psi) stage_p_body<true>(S, F, g, bc, ctrl, T);
-  else stage_p_body<false>(S, F, g, bc, ctrl, T);
+  __shared__ PlaneL S;
+  if (g.psi) stage_l_body<false, true>(S, F, g, bc, ctrl, T);
+  else stage_l_body<false, false>(S, F, g, bc, ctrl, T);
 }
 
-__global__ void __launch_bounds__(NT, 2) k_stage_c(Fields<Real> F, GridDev g, BcDev bc,
+__global__ void __launch_bounds__(NT) k_stage_c(Fields<Real> F, GridDev g, BcDev bc,
                                                    const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
   Tile T;
   int id;
   if (!single_tile(g, tz, T, id)) return;
-  __shared__ PlaneC S;
-  if (g.psi) stage_c_body<true>(S, F, g, bc, ctrl, T);
-  else stage_c_body<false>(S, F, g, bc, ctrl, T);
+  __shared__ PlaneL S;
+  if (g.psi) stage_l_body<true, true>(S, F, g, bc, ctrl, T);
+  else stage_l_body<true, false>(S, F, g, bc, ctrl, T);
 }
 
 // Workgroups per CU the register allocation must allow: the default scheme's
@@ -1653,13 +1483,13 @@ __global__ void __launch_bounds__(NT, kStage == 2 ? e_blocks(kGen) : 2)
   Tile T;
   tile_at(I.g, I.tz, w.y, T);
   if constexpr (kStage == 0) {
-    __shared__ PlaneP S;
-    if (I.g.psi) stage_p_body<true>(S, I.F, I.g, I.bc, I.ctrl, T);
-    else stage_p_body<false>(S, I.F, I.g, I.bc, I.ctrl, T);
+    __shared__ PlaneL S;
+    if (I.g.psi) stage_l_body<false, true>(S, I.F, I.g, I.bc, I.ctrl, T);
+    else stage_l_body<false, false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if constexpr (kStage == 1) {
-    __shared__ PlaneC S;
-    if (I.g.psi) stage_c_body<true>(S, I.F, I.g, I.bc, I.ctrl, T);
-    else stage_c_body<false>(S, I.F, I.g, I.bc, I.ctrl, T);
+    __shared__ PlaneL S;
+    if (I.g.psi) stage_l_body<true, true>(S, I.F, I.g, I.bc, I.ctrl, T);
+    else stage_l_body<true, false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if (!kGen || default_scheme(I.g))
     stage_e_body<false>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);
   else

@@ -42,10 +42,10 @@ csph_status fail(csph_status code, const std::string& msg) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// device fields: U[2][5], psi, ms[4], (xs[3]), psis, mt[4], (xt[3]); the FP32
+// device fields: U[2][5], psi, ms[4], (xs[3]), psis, phs, mt[4], (xt[3]); the FP32
 // build forms the particle offsets xs, xt where it needs them and has no storage
 // for them
-constexpr int kNumFields64 = 26, kNumFields32 = 20;
+constexpr int kNumFields64 = 27, kNumFields32 = 21;
 int num_fields(int dtype) { return dtype == CSPH_F64 ? kNumFields64 : kNumFields32; }
 
 // tile depths (z-planes per workgroup of the stencil sweeps) the autotuner tries
@@ -72,6 +72,22 @@ double g_over_q(double q) {
     return 0.75 * t * t / q;
   }
   return 0.0;
+}
+
+// phi = sqrt(2 p) of a conserved state, p = (gamma - 1)(E - m.u/2) floored at 0,
+// u = m/rho (0 in vacuum): the arithmetic of the kernels' FP64 primitive()
+double inflow_phi(const double cons[5], double gamma, double rho_vac) {
+  const double r = cons[0];
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+  if (r > rho_vac) {
+    ux = cons[1] / r;
+    uy = cons[2] / r;
+    uz = cons[3] / r;
+  }
+  const double ke = 0.5 * (cons[1] * ux + cons[2] * uy + cons[3] * uz);
+  const double pp = (gamma - 1.0) * (cons[4] - ke);
+  const double p = pp > 0.0 ? pp : 0.0;
+  return std::sqrt(2.0 * p);
 }
 
 double kernel_kappa() {
@@ -158,9 +174,6 @@ GridDev make_grid(const csph_grid_desc* d) {
     g.klat[q][0] = -(c * dx);
     g.klat[q][1] = -(c * dy);
     g.klat[q][2] = -(c * dz);
-    g.hoff[q][0] = dx;
-    g.hoff[q][1] = dy;
-    g.hoff[q][2] = dz;
   }
   g.limiter = kLimMinmod;
   g.flux = kFluxSweptAV;
@@ -235,6 +248,7 @@ void bind_fields(csph_sim* s, Fields<Real>& F) {
   for (int v = 0; v < 4; ++v) F.ms[v] = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 3; ++v) F.xs[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
   F.psis = (Real*)s->field_ptr(k++);
+  F.phs = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 4; ++v) F.mt[v] = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 3; ++v) F.xt[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
 }
@@ -588,6 +602,7 @@ csph_status csph_set_boundary(csph_sim* s, int32_t face, csph_bc kind, const dou
     s->bc.vel[face][0] = ux;
     s->bc.vel[face][1] = uy;
     s->bc.vel[face][2] = uz;
+    s->bc.phi[face] = inflow_phi(s->bc.cons[face], s->desc.gamma, s->desc.rho_vac);
   }
   s->psi_dirty = true;
   s->x_stale = true;
@@ -730,7 +745,9 @@ csph_status csph_totals(const csph_sim* s, double out[5]) {
 
 csph_status csph_get_stage(const csph_sim* s, int32_t which, double* out) {
   if (!s || !out) return fail(CSPH_ERR_ARG, "sim or output is NULL");
-  if (which < 0 || which > 13) return fail(CSPH_ERR_ARG, "which must be 0..13");
+  if (which < 0 || which > 14) return fail(CSPH_ERR_ARG, "which must be 0..14");
+  if (which == 14)
+    return s->is_f64() ? download_field<double>(s, s->f64.phs, out) : download_field<float>(s, s->f32.phs, out);
   if (s->is_f64()) {
     const double* src = which < 4 ? s->f64.ms[which] : which < 7 ? s->f64.xs[which - 4]
                       : which < 11 ? s->f64.mt[which - 7] : s->f64.xt[which - 11];

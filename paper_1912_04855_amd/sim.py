@@ -215,7 +215,7 @@ class Sim:
         return tuple(int(v) for v in tz), ms.value
 
     STAGE_FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
-                    "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz"]
+                    "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "phis"]
 
     def stage(self, name) -> np.ndarray:
         out = np.empty(self.shape)

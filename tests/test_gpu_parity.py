@@ -18,8 +18,8 @@ from helpers import oracle_sim
 
 pytestmark = pytest.mark.gpu
 
-STAGES = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz", "mtx", "mty", "mtz", "Et", "xtx",
-          "xty", "xtz"]
+STAGES = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz", "phis", "mtx", "mty", "mtz", "Et",
+          "xtx", "xty", "xtz"]
 
 
 def _mixed_bc_problem():
