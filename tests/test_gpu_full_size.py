@@ -60,14 +60,12 @@ def test_well256_symmetry_after_100_steps(dtype, tol):
     assert np.all(np.isfinite(U))
     assert np.min(U[0]) > 0.0
     # mirror y -> 1 - y (the grid and the well are symmetric about 0.5), and y <-> z;
-    # measured in relative L1 (FP32 rounding is not mirror-symmetric, and shocks in
-    # this flow amplify it locally)
-    # momentum defects on the scale of the whole momentum vector
-    m1 = float(np.sum(np.abs(U[1:4])))
+    # measured in relative L1 of each variable on its own norm (FP32 rounding is
+    # not mirror-symmetric, and shocks in this flow amplify it locally)
     errs = [rel_l1(U[0][:, ::-1, :], U[0]),
-            float(np.sum(np.abs(-U[2][:, ::-1, :] - U[2]))) / m1,
+            rel_l1(-U[2][:, ::-1, :], U[2]),
             rel_l1(np.transpose(U[0], (1, 0, 2)), U[0]),
-            float(np.sum(np.abs(np.transpose(U[3], (1, 0, 2)) - U[2]))) / m1]
+            rel_l1(np.transpose(U[3], (1, 0, 2)), U[2])]
     print(f"well 256^3 {dtype} after 100 steps: symmetry defects (relative L1) "
           + ", ".join(f"{e:.2e}" for e in errs))
     assert max(errs) <= tol

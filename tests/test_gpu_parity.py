@@ -106,11 +106,10 @@ def test_smooth_flows_fp32(name, steps, tol):
     mom = rel_l1(Ug[1:4], Uo[1:4])
     print(f"{name}: FP32 relative L1 of the state vs FP64 oracle = {err:.3e} (per variable "
           + ", ".join(f"{e:.2e}" for e in per) + f"; momentum vector {mom:.2e})")
-    # the bar: relative L1 of the whole conserved state, and of rho, momentum and E
-    # each on its own norm (a transverse momentum component that the flow barely
-    # excites is reported, not bounded: its own norm is tiny)
+    # the bar: relative L1 of the whole conserved state and of every conserved
+    # variable on its own norm
     assert err <= tol
-    assert per[0] <= tol and per[4] <= tol and mom <= tol
+    assert max(per) <= tol and mom <= tol
     g.close()
 
 
