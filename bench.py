@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -38,37 +40,41 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X
 # figure is reported as the peak.
 ALU_PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 ALU_PEAK_NONPACKED = 78.6e12
-VALU_ISSUE = 256 * 4 * 16 * 2.4e9   # lane-instructions/s (one wave64 op per SIMD per 4 clocks)
 
 # Algorithmic bytes per interior cell of each stage kernel, in words (4 B in
 # FP32, 8 B in FP64): every input of the kernel read once, every output written
 # once.  The FP32 build does not store the particle offsets xi*, xi^{n+1}: it
 # forms them from the momenta where they are needed.
-#   stage P: read U^n (5) + psi (1);  write m*, E* (4) + psi(r*) (1)
+#   stage P: read U^n (5) + psi (1);  write m*, E* (4) + psi(r*) (1) + phi* (1)
 #            [FP64 also writes xi* (3)]
-#   stage C: read rho, m*, E* (5) + psi(r*) (1) + m^n, E^n (4);  write m~, E~ (4)
-#            [FP64 reads xi* (3) and writes xi^{n+1} (3)]
+#   stage C: read rho, m* (4) + phi* (1) + psi(r*) (1) + m^n, E^n (4) + E* (1);
+#            write m~, E~ (4)  [FP64 reads xi* (3) and writes xi^{n+1} (3)]
 #   stage E: read U^n (5) + m~, E~ (4) + m* (3) [FP64: xi^{n+1} (3)];  write U^{n+1} (5)
-RW = {"f32": {"stage_p": (6, 5), "stage_c": (10, 4), "stage_e": (12, 5)},
-      "f64": {"stage_p": (6, 8), "stage_c": (13, 7), "stage_e": (12, 5)}}
+RW = {"f32": {"stage_p": (6, 6), "stage_c": (11, 4), "stage_e": (12, 5)},
+      "f64": {"stage_p": (6, 9), "stage_c": (14, 7), "stage_e": (12, 5)}}
 WORDS = {t: {k: r + w for k, (r, w) in m.items()} for t, m in RW.items()}
-# What bounds each kernel (rocprofv3 counters): the corrector issues vector-ALU
-# instructions back to back; the predictor and the Eulerian update wait on HBM.
-BOUND = {"stage_p": "hbm", "stage_c": "alu", "stage_e": "hbm"}
 # Algorithmic floating-point operations per interior cell of each stage (each
 # +, -, *, /, sqrt, min, max counted once; a fused multiply-add is two), as the
 # method defines them, not as the kernels happen to issue them:
 #   stage P: primitives (14) + the 13 lattice pair terms of A (119), D[psi] (54)
 #            and B (212) + rho u.D[psi] (7) + the predictor update (20) + psi at
-#            r* (27)                                                      = 453
-#   stage C: per neighbour (26): separation (5), |d| and q (7), g(q)/q (4), K (4),
-#            pressure-potential term (4), A (6), D[psi] (6), (u_i+u_j).K/2 (9),
-#            B (2) = 47.1; plus primitives, corrector update and xi (51)  = 1275
-#   stage E: three faces per cell (a face is shared by two cells) x 148 (slopes
-#            and minmod 45, reconstruction and swept flux 41, acoustic damping
-#            62) + the update (35) + the next step's signal speed (21) and the
-#            totals (5)                                                    = 505
-FLOPS = {"stage_p": 453, "stage_c": 1275, "stage_e": 505}
+#            r* (27) + the lattice divergence of u^n (27 pair components x 3 = 81)
+#            + the predicted volume and phi* (5)                          = 539
+#   stage C: u* = m*/rho (3) + the same lattice sums on the predicted particles
+#            (119 + 54 + 212 + 7 = 392) + the corrector update (16)        = 411
+#   stage E: three faces per cell (a face is shared by two cells) x 154 (slopes
+#            and minmod 45, reconstruction and swept flux 41, the swept width at
+#            the foot of the face's trajectory 6, acoustic damping 62) + the
+#            update (35) + the next step's signal speed (21) and the totals (5) = 523
+FLOPS = {"stage_p": 539, "stage_c": 411, "stage_e": 523}
+# What bounds each kernel is read from rocprofv3 counters of the current kernel
+# source (profiles/traffic.json): the share of the launch in which the SIMDs
+# issue vector-ALU instructions, SQ_ACTIVE_INST_VALU / (CU count x GRBM_GUI_ACTIVE)
+# (AMD's VALUBusy).  A kernel busier than VALU_BOUND is reported against the
+# vector-ALU peak, any other against HBM.  Without a summary of the current
+# source the last measured bounds below stand.
+VALU_BOUND = 0.75
+BOUND_MEASURED = {"stage_p": "alu", "stage_c": "hbm", "stage_e": "hbm"}
 KERNEL_NAMES = {"stage_p": "k_stage_p", "stage_c": "k_stage_c", "stage_e": "k_stage_e"}
 
 
@@ -144,22 +150,18 @@ def _counters(kernel, dtype, cells):
     return None
 
 
-def step_issue_bound(dtype, cells, ms_per_step):
-    """The whole step against the vector-ALU issue rate: the counted VALU
-    instructions per cell of the three stage kernels (rocprofv3 SQ_INSTS_VALU,
-    committed summary of the current kernel source), each a wave64 instruction
-    taking 4 clocks of one of 1024 SIMDs at 2.4 GHz.  None without a summary."""
-    per = {}
+def bounds(dtype, cells):
+    """Each stage kernel's bound and measured VALU-busy share (None without a
+    counter summary of the current source)."""
+    out = {}
     for k in WORDS[dtype]:
         rec = _counters(KERNEL_NAMES[k], dtype, cells)
-        if not rec or not rec.get("valu_per_cell"):
-            return None
-        per[k] = rec["valu_per_cell"]
-    total = sum(per.values())
-    issue_ms = total * cells / VALU_ISSUE * 1e3
-    return {"valu_instr_per_cell": {k: round(v, 1) for k, v in per.items()},
-            "valu_instr_per_cell_total": round(total, 1), "issue_bound_ms": round(issue_ms, 4),
-            "frac_of_step": round(issue_ms / ms_per_step, 3)}
+        busy = rec.get("valu_busy") if rec else None
+        if busy is None:
+            out[k] = (BOUND_MEASURED[k], None)
+        else:
+            out[k] = ("alu" if busy >= VALU_BOUND else "hbm", busy)
+    return out
 
 
 def dominant(prof, dtype):
@@ -198,7 +200,9 @@ def roofline(prof, cells, dtype, stream_gbps=None):
     tflops = flops_per_launch / sec / 1e12
     rec = _counters(KERNEL_NAMES[dom], dtype, cells)
     traffic = rec["bytes_per_launch"] if rec else None
-    per = {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1], "bound": BOUND[k],
+    bd = bounds(dtype, cells)
+    per = {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1], "bound": bd[k][0],
+               "valu_busy": bd[k][1],
                "GBps": round(W[k] * word * cells / (prof[k][0] * 1e-3) / 1e9, 1),
                "TFLOPs": round(FLOPS[k] * cells / (prof[k][0] * 1e-3) / 1e12, 2)}
            for k in W}
@@ -216,17 +220,16 @@ def roofline(prof, cells, dtype, stream_gbps=None):
             "GBps": round(stream_gbps, 1), "frac": round(gbps / stream_gbps, 4),
             "what": "a plain kernel with the same read/write stream mix over the interior cells "
                     "(no halos, address order)"}
-    main = hbm if BOUND[dom] == "hbm" else alu
-    out = {"bound": BOUND[dom], "kernel": KERNEL_NAMES[dom], "achieved": main["achieved"],
+    main = hbm if bd[dom][0] == "hbm" else alu
+    out = {"bound": bd[dom][0], "kernel": KERNEL_NAMES[dom], "achieved": main["achieved"],
            "peak": main["peak"], "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
            "alu": alu, "hbm": hbm, "kernels": per,
            # the step's other launches: three ghost fills (the first timed with the
            # step's opening launch) and the closing bookkeeping launch
            "other_kernels": {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1]}
                              for k in ("ghost_fill", "bookkeeping") if k in prof}}
-    if rec and rec.get("valu_per_cell"):
-        # VALU issue utilisation from the counted instructions per cell
-        out["valu_issue_frac"] = round(rec["valu_per_cell"] * cells / sec / VALU_ISSUE, 3)
+    if bd[dom][1] is not None:
+        out["valu_busy"] = bd[dom][1]
     return out
 
 
@@ -314,6 +317,31 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+def host_description():
+    """CPU model, cores and threads of this host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    d = {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+                "Thread(s) per core": "threads_per_core"}
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys:
+                d[keys[k.strip()]] = v.strip()
+    except Exception:
+        pass
+    if "model" not in d:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    d["model"] = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return d
+
+
 def cpu_baseline(budget_s=15.0):
     """The FP64 oracle (single thread) on a 64^3 sample of the same workload."""
     import oracle as O
@@ -333,7 +361,50 @@ def cpu_baseline(budget_s=15.0):
     return {"value": round(pr.cells * n / el, 1), "unit": "cell-updates/s", "cores": 1,
             "kind": "oracle",
             "sample": f"potential-well flow 64^3 (same setup rescaled), {n} FP64 steps, "
-                      f"single-threaded C oracle, {el:.1f} s"}
+                      f"single-threaded C oracle, {el:.1f} s",
+            "host": host_description()}
+
+
+def _oracle_batch_member(args):
+    """One batch instance stepped by the oracle (a worker process of cpu_box)."""
+    master, k, steps = args
+    import oracle as O
+    from paper_1912_04855_amd import problems as P
+    pr = P.batch_instance(master, k, steps=steps)
+    s = O.OracleSim(pr.shape, pr.h, gamma=pr.gamma, cfl=pr.cfl, rho_vac=pr.rho_vac, bc=pr.bc,
+                    inflow=pr.inflow_list())
+    s.set_primitive(pr.prim)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step()
+    return pr.cells * steps, time.perf_counter() - t0
+
+
+def cpu_box(instances=32, steps=4, master=0, batch_count=512, batch_steps=100):
+    """The multi-instance comparator of the batched workload: one oracle process
+    per host core (at most 16, this host's share of a one-GPU machine) on the first
+    `instances` members of the batch, `steps` steps each; the aggregate rate is
+    extrapolated to the whole batch (batch_count members, batch_steps steps)."""
+    import multiprocessing as mp
+    from paper_1912_04855_amd import problems as P
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("spawn")  # fresh interpreters: nothing of this process's GPU state
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_batch_member, [(master, k, steps) for k in range(instances)],
+                       chunksize=1)
+    wall = time.perf_counter() - t0
+    work = sum(r[0] for r in res)
+    # each process's own stepping rate, measured while all of them run at once
+    # (shared caches and memory bandwidth included), times the processes
+    rate = workers * work / sum(r[1] for r in res)
+    total = sum(int(np.prod(P.batch_shape(master, k)[0])) for k in range(batch_count)) * batch_steps
+    return {"value": round(rate, 1), "unit": "cell-updates/s", "cores": workers, "kind": "oracle",
+            "sample": f"{instances} of the {batch_count} batch members, {steps} FP64 steps each, "
+                      f"one single-threaded oracle process per core ({wall:.1f} s wall with "
+                      f"process start-up); value = processes x their mean stepping rate",
+            "wall_rate": round(work / wall, 1),
+            "extrapolated_batch_s": round(total / rate, 1)}
 
 
 def main():
@@ -357,9 +428,11 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-tile-depth", type=int, default=0,
                     help="tile depth of every batch member instead of autotuning it")
-    ap.add_argument("--serve-count", type=int, default=40)
-    ap.add_argument("--serve-rate", type=float, default=1.0,
+    ap.add_argument("--serve-count", type=int, default=80)
+    ap.add_argument("--serve-rate", type=float, default=1.2,
                     help="mean arrival rate of the serving workload (requests per second)")
+    ap.add_argument("--no-cloud", action="store_true", help="skip the gas-vacuum cloud workload")
+    ap.add_argument("--cloud-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for the HBM "
                          "byte counters) and exit")
@@ -404,9 +477,6 @@ def main():
         log(f"[bench] streaming reference failed: {e}")
         ref = None
     rl = roofline(r["profile"], cells, args.dtype, ref)
-    sib = step_issue_bound(args.dtype, cells, ms_step)
-    if sib:
-        rl["step_valu_issue"] = sib
     out = {
         "metric": "cell-updates/s", "value": round(value, 1), "unit": "cell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -427,6 +497,24 @@ def main():
         out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(r64["event_ms"] / k64, 4),
                        "steps": k64, "tile": _tile(r64["tile_depth"]),
                        "roofline": roofline(r64["profile"], cells, "f64")}
+    if not args.no_cloud:
+        log(f"[bench] gas-vacuum cloud 384^3 f32: {args.cloud_steps} steps")
+        try:
+            prc = P.cloud(384)
+            rc = run_gpu(prc, "f32", args.cloud_steps, args.warmup, autotune=not args.no_autotune)
+            vc = prc.cells * args.cloud_steps / (rc["event_ms"] * 1e-3)
+            out["cloud"] = {"value": round(vc, 1), "unit": "cell-updates/s",
+                            "ms_per_step": round(rc["event_ms"] / args.cloud_steps, 4),
+                            "steps": args.cloud_steps, "cells": prc.cells, "dtype": "f32",
+                            "tile": _tile(rc["tile_depth"]),
+                            "kernels_ms": {k: round(v[0], 5) for k, v in rc["profile"].items()},
+                            "workload": "gas-vacuum cloud 384^3 (rho = 1 - r^2/0.09 with 1% "
+                                        "SplitMix64 noise, Plummer psi, vacuum outside, "
+                                        "gamma = 5/3, outflow faces)"}
+            log(f"[bench] cloud: {vc:.3e} cell-updates/s")
+            del prc
+        except Exception as e:
+            out["cloud"] = {"error": repr(e)}
     if not args.no_batch:
         log(f"[bench] batched workload: {args.batch_count} instances")
         try:
@@ -444,6 +532,12 @@ def main():
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()
+        if not args.no_batch:
+            log("[bench] CPU box comparator of the batched workload")
+            try:
+                out["cpu_box_batched"] = cpu_box(batch_count=args.batch_count)
+            except Exception as e:
+                out["cpu_box_batched"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

@@ -308,12 +308,19 @@ def smooth_state(shape=(16, 12, 10), seed=0, gamma=1.4, bc=None, potential=True)
 BATCH_EDGES = (32, 48, 64, 96)
 
 
+def batch_shape(master_seed: int, k: int):
+    """(nx, ny, nz) and the kind ('sedov' or 'sod') of instance k of the batched
+    workload, without building it."""
+    r = splitmix64(master_seed, np.arange(4 * k, 4 * k + 4, dtype=np.uint64))
+    shape = tuple(BATCH_EDGES[int(r[a] % np.uint64(4))] for a in range(3))
+    return shape, ("sedov" if int(r[3]) & 1 else "sod")
+
+
 def batch_instance(master_seed: int, k: int, gamma=1.4, steps=100) -> Problem:
     """Instance k of the batched workload: edges uniform in {32, 48, 64, 96} per axis,
     a Sod tube along x or a Sedov blast chosen by one hash bit (h = 1/nx, psi = 0)."""
-    r = splitmix64(master_seed, np.arange(4 * k, 4 * k + 4, dtype=np.uint64))
-    nx, ny, nz = (BATCH_EDGES[int(r[a] % np.uint64(4))] for a in range(3))
-    if int(r[3]) & 1:
+    (nx, ny, nz), kind = batch_shape(master_seed, k)
+    if kind == "sedov":
         p = sedov((nx, ny, nz), gamma=gamma, steps=steps)
     else:
         p = riemann_tube(nx, gamma=gamma)

@@ -61,6 +61,8 @@ class ServeStats:
             "mean_device_s": mean([r.done - r.admitted for r in self.records]),
             "mean_readback_s": mean([r.finished - r.done for r in self.records]),
             "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p90_s": float(np.percentile(lat, 90)) if len(lat) else None,
+            # with n requests the 99th percentile rests on the slowest n/100 of them
             "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "mean_s": float(lat.mean()) if len(lat) else None,
             "cell_updates_per_s": work / self.wall_s if self.wall_s > 0 else None,

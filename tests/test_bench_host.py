@@ -1,7 +1,7 @@
 """Host-side logic of bench.py (no GPU): the one-GPU guard, the tile-depth
-argument, the roofline arithmetic of the dominant kernel, the issue bound of the
-whole step, and that counter summaries are used only for the source they were
-taken of."""
+argument, the roofline arithmetic of the dominant kernel, each kernel's bound
+from its measured VALU-busy share, and that counter summaries are used only for
+the source they were taken of."""
 import os
 import subprocess
 import sys
@@ -48,24 +48,32 @@ def test_roofline_of_an_hbm_bound_kernel(monkeypatch):
     assert r["traffic"] is None
     assert r["hbm"]["bytes_per_launch"] == 17 * 4 * CELLS
     assert r["hbm"]["stream_reference"]["frac"] == pytest.approx(gbps / 5000.0, abs=1e-4)
-    # every stage kernel is listed with its own bound and rate
+    # every stage kernel is listed with its own bound and rate; without a counter
+    # summary of the current source the last measured bounds stand
     assert set(r["kernels"]) == {"stage_p", "stage_c", "stage_e"}
-    assert r["kernels"]["stage_c"]["bound"] == "alu"
-    assert r["kernels"]["stage_p"]["GBps"] == pytest.approx(11 * 4 * CELLS / 0.3e-3 / 1e9, abs=0.06)
+    assert r["kernels"]["stage_p"]["bound"] == "alu" and r["kernels"]["stage_c"]["bound"] == "hbm"
+    assert r["kernels"]["stage_p"]["valu_busy"] is None
+    assert r["kernels"]["stage_p"]["GBps"] == pytest.approx(12 * 4 * CELLS / 0.3e-3 / 1e9, abs=0.06)
     assert r["other_kernels"]["ghost_fill"]["launches"] == 300
 
 
-def test_roofline_of_an_alu_bound_kernel(monkeypatch):
-    monkeypatch.setattr(bench, "_counters", lambda *a: None)
+def test_bound_follows_measured_valu_busy(monkeypatch):
+    busy = {"k_stage_p": 0.81, "k_stage_c": 0.9, "k_stage_e": 0.65}
+    monkeypatch.setattr(bench, "_counters", lambda k, d, c: {"valu_busy": busy[k],
+                                                             "bytes_per_launch": None})
     r = bench.roofline(_prof(0.3, 0.6, 0.5), CELLS, "f32")
+    # stage C has the longest launch and its VALU is busy 90% of it: ALU-bound
     assert r["kernel"] == "k_stage_c" and r["bound"] == "alu" and r["unit"] == "TFLOP/s"
-    tf = 1275 * CELLS / 0.6e-3 / 1e12
+    assert r["valu_busy"] == 0.9
+    tf = 411 * CELLS / 0.6e-3 / 1e12
     assert r["achieved"] == pytest.approx(tf, abs=0.006)
     assert r["peak"] == pytest.approx(157.3)
     assert r["alu"]["frac_nonpacked"] == pytest.approx(tf / 78.6, abs=1e-4)
-    # FP64 words are 8 bytes, and stage C moves 13 + 7 of them
+    assert r["kernels"]["stage_e"]["bound"] == "hbm"
+    assert max(k["valu_busy"] for k in r["kernels"].values()) <= 1.0
+    # FP64 words are 8 bytes, and stage C moves 14 + 7 of them
     r64 = bench.roofline(_prof(1.0, 2.0, 0.9), CELLS, "f64")
-    assert r64["hbm"]["bytes_per_launch"] == 20 * 8 * CELLS
+    assert r64["hbm"]["bytes_per_launch"] == 21 * 8 * CELLS
     assert r64["peak"] == pytest.approx(78.6)
 
 
@@ -78,19 +86,22 @@ def test_counter_summaries_follow_the_source(monkeypatch):
     rec = bench._counters("k_stage_e", "f32", CELLS)
     if rec is not None:
         # measured traffic of a summary taken of this source: of the order of
-        # the algorithmic bytes (halos add to them)
+        # the algorithmic bytes (halos add to them), and a VALU-busy share
         alg = 17 * 4 * CELLS
         assert 0.8 * alg < rec["bytes_per_launch"] < 3.0 * alg
         assert rec["read"] + rec["written"] == pytest.approx(rec["bytes_per_launch"], rel=1e-6)
+        assert 0.0 < rec["valu_busy"] <= 1.0
 
 
-def test_step_issue_bound(monkeypatch):
-    per = {"k_stage_p": 500.0, "k_stage_c": 1100.0, "k_stage_e": 700.0}
-    monkeypatch.setattr(bench, "_counters", lambda k, d, c: {"valu_per_cell": per[k]})
-    r = bench.step_issue_bound("f32", CELLS, 1.25)
-    ms = 2300.0 * CELLS / (256 * 4 * 16 * 2.4e9) * 1e3
-    assert r["valu_instr_per_cell_total"] == 2300.0
-    assert r["issue_bound_ms"] == pytest.approx(ms, abs=1e-4)
-    assert r["frac_of_step"] == pytest.approx(ms / 1.25, abs=1e-3)
-    monkeypatch.setattr(bench, "_counters", lambda *a: None)
-    assert bench.step_issue_bound("f32", CELLS, 1.25) is None
+def test_host_description():
+    d = bench.host_description()
+    assert d["nproc"] >= 1 and d["usable_cpus"] >= 1
+    assert d.get("model")
+
+
+def test_batch_shapes_match_the_instances():
+    from paper_1912_04855_amd import problems as P
+    for k in range(6):
+        shape, kind = P.batch_shape(0, k)
+        pr = P.batch_instance(0, k, steps=3)
+        assert pr.shape == shape and pr.name == kind
