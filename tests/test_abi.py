@@ -29,12 +29,12 @@ def test_required_bytes_and_argument_errors():
     L = _lib.load()
     d = make_desc((256, 256, 256), 1 / 256, dtype="f32")
     nb = L.csph_required_bytes(C.byref(d))
-    # FP32: 20 padded fields of 260^3 floats (no stored particle offsets) plus the
-    # control block and block totals; FP64: 26 fields of doubles
-    assert 20 * 260 ** 3 * 4 <= nb < 20 * 260 ** 3 * 4 + (8 << 20)
+    # FP32: 21 padded fields of 260^3 floats (no stored particle offsets) plus the
+    # control block and block totals; FP64: 27 fields of doubles
+    assert 21 * 260 ** 3 * 4 <= nb < 21 * 260 ** 3 * 4 + (8 << 20)
     d64 = make_desc((256, 256, 256), 1 / 256, dtype="f64")
     nb64 = L.csph_required_bytes(C.byref(d64))
-    assert 26 * 260 ** 3 * 8 <= nb64 < 26 * 260 ** 3 * 8 + (8 << 20)
+    assert 27 * 260 ** 3 * 8 <= nb64 < 27 * 260 ** 3 * 8 + (8 << 20)
     bad = make_desc((3, 8, 8), 0.1)
     assert L.csph_required_bytes(C.byref(bad)) == 0
     out = C.c_void_p()
