@@ -101,6 +101,19 @@ csph_status csph_create(const csph_grid_desc* desc, void* hip_stream, csph_sim**
 csph_status csph_create_in(const csph_grid_desc* desc, void* hip_stream, void* dev_buf,
                            size_t bytes, csph_sim** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid hipMalloc): the same as csph_create_in,
+ * with the simulation in a static device array of CSPH_STATIC_BYTES that the
+ * library holds on every GPU it runs on until the process ends.  The call makes
+ * no device or host-heap allocation; the array is cleared (state = 0, psi = 0,
+ * t = 0) as by the other create calls.  One such simulation per GPU at a time:
+ * calls on two of them would race on the same memory, so a second creation
+ * returns CSPH_ERR_STATE until the first is destroyed.  CSPH_ERR_ARG if
+ * csph_required_bytes(desc) > CSPH_STATIC_BYTES (an FP32 cube of 112^3 cells
+ * fits, an FP64 one of 81^3).  Every other call works on it as on any sim. */
+#define CSPH_STATIC_BYTES ((size_t)128 << 20)
+csph_status csph_create_static(const csph_grid_desc* desc, void* hip_stream, csph_sim** out);
+
 /* Free what the library owns.  NULL is accepted.  CSPH_ERR_ARG (nothing freed)
  * while the simulation is a batch member. */
 csph_status csph_destroy(csph_sim* sim);

@@ -222,6 +222,7 @@ struct csph_sim {
   bool in_batch = false;
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool stepped = false;  // partials describe the current state
+  bool in_static = false;  // lives in this device's static array (csph_create_static)
   std::vector<double> psi_host;  // interior psi, kept to refill ghosts after BC changes
   bool has_psi = false;
   // kernel timing: events of up to kProfSteps steps in flight, accumulated at syncs
@@ -237,6 +238,23 @@ struct csph_sim {
 };
 
 namespace {
+
+// ------------------------------------------------------------ static array
+// Device memory of csph_create_static: one array per GPU the library runs on,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in; its device address on each GPU comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// handed to kernels and memory calls.  The simulation object of each slot has
+// static host storage too, so creating one allocates nothing.
+__device__ __align__(256) unsigned char scratch[CSPH_STATIC_BYTES];
+constexpr int kMaxDevices = 64;
+struct StaticSlot {
+  void* dev = nullptr;   // device address of `scratch` on this GPU (set once)
+  bool in_use = false;   // a simulation lives in it
+  alignas(csph_sim) unsigned char host[sizeof(csph_sim)];
+};
+StaticSlot g_static[kMaxDevices];
+std::mutex g_static_mu;
 
 template <typename Real>
 void bind_fields(csph_sim* s, Fields<Real>& F) {
@@ -446,28 +464,33 @@ size_t csph_required_bytes(const csph_grid_desc* desc) {
   return make_layout(desc).total;
 }
 
+// host_mem: storage for the simulation object (NULL: the heap)
 static csph_status create_common(const csph_grid_desc* desc, void* stream, void* dev_buf,
-                                 size_t bytes, csph_sim** out) {
+                                 size_t bytes, csph_sim** out, void* host_mem = nullptr) {
   if (!out) return fail(CSPH_ERR_ARG, "out is NULL");
   *out = nullptr;
   std::string why;
   if (!desc_ok(desc, &why)) return fail(CSPH_ERR_ARG, why);
-  csph_sim* s = new (std::nothrow) csph_sim();
+  csph_sim* s = host_mem ? new (host_mem) csph_sim() : new (std::nothrow) csph_sim();
   if (!s) return fail(CSPH_ERR_NOMEM, "host allocation failed");
+  auto drop = [&]() {
+    if (host_mem) s->~csph_sim();
+    else delete s;
+  };
   s->desc = *desc;
   s->stream = (hipStream_t)stream;
   s->L = make_layout(desc);
   if (hipGetDevice(&s->device) != hipSuccess) {
-    delete s;
+    drop();
     return fail(CSPH_ERR_DEVICE, "hipGetDevice failed");
   }
   if (dev_buf) {
     if (bytes < s->L.total) {
-      delete s;
+      drop();
       return fail(CSPH_ERR_ARG, "caller buffer smaller than csph_required_bytes");
     }
     if ((uintptr_t)dev_buf % kAlign) {
-      delete s;
+      drop();
       return fail(CSPH_ERR_ARG, "caller buffer must be 256-byte aligned");
     }
     s->buf = (char*)dev_buf;
@@ -476,7 +499,7 @@ static csph_status create_common(const csph_grid_desc* desc, void* stream, void*
     void* p = nullptr;
     if (hipMalloc(&p, s->L.total) != hipSuccess) {
       (void)hipGetLastError();
-      delete s;
+      drop();
       return fail(CSPH_ERR_NOMEM, "hipMalloc failed");
     }
     s->buf = (char*)p;
@@ -485,7 +508,7 @@ static csph_status create_common(const csph_grid_desc* desc, void* stream, void*
   csph_status st = init_sim(s);
   if (st) {
     if (s->owned) (void)hipFree(s->buf);
-    delete s;
+    drop();
     return st;
   }
   *out = s;
@@ -502,12 +525,53 @@ csph_status csph_create_in(const csph_grid_desc* desc, void* hip_stream, void* d
   return create_common(desc, hip_stream, dev_buf, bytes, out);
 }
 
+csph_status csph_create_static(const csph_grid_desc* desc, void* hip_stream, csph_sim** out) {
+  if (!out) return fail(CSPH_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  const size_t need = csph_required_bytes(desc);
+  if (need == 0) {
+    std::string why;
+    desc_ok(desc, &why);
+    return fail(CSPH_ERR_ARG, why);
+  }
+  if (need > CSPH_STATIC_BYTES)
+    return fail(CSPH_ERR_ARG, "grid needs " + std::to_string(need) + " device bytes; the static array holds " +
+                                  std::to_string((size_t)CSPH_STATIC_BYTES));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CSPH_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  StaticSlot& slot = g_static[dev];
+  if (slot.in_use)
+    return fail(CSPH_ERR_STATE, "the static array of this GPU holds another simulation: destroy it first");
+  if (!slot.dev) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(CSPH_ERR_DEVICE, "hipGetSymbolAddress of the static array failed");
+    }
+    slot.dev = p;
+  }
+  csph_status st = create_common(desc, hip_stream, slot.dev, CSPH_STATIC_BYTES, out, slot.host);
+  if (st) return st;
+  (*out)->in_static = true;
+  slot.in_use = true;
+  return CSPH_OK;
+}
+
 csph_status csph_destroy(csph_sim* s) {
   if (!s) return CSPH_OK;
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   (void)hipStreamSynchronize(s->stream);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->owned) (void)hipFree(s->buf);
+  if (s->in_static) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    const int dev = s->device;
+    s->~csph_sim();
+    g_static[dev].in_use = false;
+    return CSPH_OK;
+  }
   delete s;
   return CSPH_OK;
 }

@@ -50,7 +50,7 @@ class Sim:
     torch's current stream."""
 
     def __init__(self, shape, h, gamma=1.4, cfl=0.4, rho_vac=1e-10, dtype="f64",
-                 origin=(0.0, 0.0, 0.0), torch=False, stream=None):
+                 origin=(0.0, 0.0, 0.0), torch=False, stream=None, static=False):
         L = _lib.load()
         self.shape = (int(shape[2]), int(shape[1]), int(shape[0]))  # (nz, ny, nx)
         self.dtype = _dtype_code(dtype)
@@ -58,7 +58,11 @@ class Sim:
         self.gamma = gamma
         self._buf = None
         self._h = C.c_void_p()
-        if torch:
+        if static:
+            # the library's static device array (csph_create_static): no allocation
+            check(L.csph_create_static(C.byref(self.desc), C.c_void_p(stream or 0), C.byref(self._h)),
+                  "csph_create_static")
+        elif torch:
             import torch as _t
             nbytes = int(L.csph_required_bytes(C.byref(self.desc)))
             if nbytes == 0:
