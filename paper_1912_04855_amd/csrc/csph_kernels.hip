@@ -696,6 +696,7 @@ __device__ __forceinline__ int hidx(int hx, int hy) { return hy * HX + hx; }
 //   stage C, corrector (Eq. (6)), on the predicted particles (rho, u* = m*/rho,
 //     phi*, psi*): m~ = (m + m*)/2 - (dt/2) A*, E~ likewise, and in FP64
 //     xi^{n+1} = xi*/2 + dt (u^n + u~)/4 (FP32 forms it in stage E).
+// ux, uy, uz hold the velocity, or phi u in the FP32 corrector (see kPhiU)
 struct PlaneL {
   Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP], psi[3][HP];
 };
@@ -723,6 +724,11 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
   const int i = T.x0 + tx, j = T.y0 + ty;
   const bool in = i < g.nx && j < g.ny;
   const uint32_t oc = in ? in_plane(g, i, j) : 0u;  // this column's cell in a plane
+  // The FP32 corrector keeps phi u in the planes instead of u: with K_- = -K_+ the
+  // energy sum of a pair, phi_c [phi_+ (u_c + u_+) - phi_- (u_c + u_-)] . K / 2, is
+  // phi_c [(phi_+ - phi_-) u_c . K + ((phi u)_+ - (phi u)_-) . K] / 2, whose first
+  // part reuses the pressure difference of the momentum sum.
+  constexpr bool kPhiU = kCorr && !kF64;
 
   auto load = [&](int k) {
     const int s = ring3(k);
@@ -742,6 +748,10 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
         primitive(g, r, *at_plane(LX, pz, ob), *at_plane(LY, pz, ob), *at_plane(LZ, pz, ob),
                   *at_plane(LE, pz, ob), u[0], u[1], u[2], p);
         ph = sqrt_fast((Real)2 * p);
+      }
+      if constexpr (kPhiU) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] *= ph;
       }
       S.rho[s][q] = r;
       S.phi[s][q] = ph;
@@ -769,6 +779,7 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
       const Real* psi_ = &S.psi[0][0];
       Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0, dv = 0.0;
       Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0, dvf = 0;
+      Real gph[3] = {0, 0, 0};  // kPhiU: sum of (phi_+ - phi_-) K
 #pragma unroll
       for (int q = 0; q < 13; ++q) {
         const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
@@ -840,6 +851,22 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
             af[2] += s * Kz;
             gf[2] += ds * Kz;
           }
+          if constexpr (kPhiU) {
+            // planes hold phi u: K . ((phi u)_+ - (phi u)_-) and (phi_+ - phi_-) K
+            if (ox != 0) {
+              gph[0] = fmaf(dphi, Kx, gph[0]);
+              bf = fmaf(Kx, ux_[np] - ux_[nm], bf);
+            }
+            if (oy != 0) {
+              gph[1] = fmaf(dphi, Ky, gph[1]);
+              bf = fmaf(Ky, uy_[np] - uy_[nm], bf);
+            }
+            if (oz != 0) {
+              gph[2] = fmaf(dphi, Kz, gph[2]);
+              bf = fmaf(Kz, uz_[np] - uz_[nm], bf);
+            }
+            continue;
+          }
           Real upk = 0, umk = 0;
           if (ox != 0) {
             upk += (uc[0] + ux_[np]) * Kx;
@@ -866,6 +893,14 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
 #pragma unroll
         for (int d = 0; d < 3; ++d) Av[d] = a[d];
         Bv = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
+      } else if constexpr (kPhiU) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Av[d] = af[d];
+        // the cell's own u* (the planes hold phi u)
+        Real u0[3];
+        velocity(g, rc, F.ms[0][c], F.ms[1][c], F.ms[2][c], u0);
+        const Real ug = u0[0] * gph[0] + u0[1] * gph[1] + u0[2] * gph[2];
+        Bv = (Real)0.5 * fc * (ug + bf) + rc * (u0[0] * gf[0] + u0[1] * gf[1] + u0[2] * gf[2]);
       } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) Av[d] = af[d];
