@@ -724,10 +724,11 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
   const int i = T.x0 + tx, j = T.y0 + ty;
   const bool in = i < g.nx && j < g.ny;
   const uint32_t oc = in ? in_plane(g, i, j) : 0u;  // this column's cell in a plane
-  // The FP32 corrector keeps phi u in the planes instead of u: with K_- = -K_+ the
-  // energy sum of a pair, phi_c [phi_+ (u_c + u_+) - phi_- (u_c + u_-)] . K / 2, is
+  // FP32: with K_- = -K_+ the energy sum of a pair,
+  // phi_c [phi_+ (u_c + u_+) - phi_- (u_c + u_-)] . K / 2, is
   // phi_c [(phi_+ - phi_-) u_c . K + ((phi u)_+ - (phi u)_-) . K] / 2, whose first
-  // part reuses the pressure difference of the momentum sum.
+  // part reuses the pressure difference of the momentum sum.  The corrector keeps
+  // phi u in its planes instead of u (it needs no neighbour velocity otherwise).
   constexpr bool kPhiU = kCorr && !kF64;
 
   auto load = [&](int k) {
@@ -779,7 +780,7 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
       const Real* psi_ = &S.psi[0][0];
       Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0, dv = 0.0;
       Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0, dvf = 0;
-      Real gph[3] = {0, 0, 0};  // kPhiU: sum of (phi_+ - phi_-) K
+      Real gph[3] = {0, 0, 0};  // FP32: sum of (phi_+ - phi_-) K
 #pragma unroll
       for (int q = 0; q < 13; ++q) {
         const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
@@ -851,39 +852,28 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
             af[2] += s * Kz;
             gf[2] += ds * Kz;
           }
-          if constexpr (kPhiU) {
-            // planes hold phi u: K . ((phi u)_+ - (phi u)_-) and (phi_+ - phi_-) K
-            if (ox != 0) {
-              gph[0] = fmaf(dphi, Kx, gph[0]);
-              bf = fmaf(Kx, ux_[np] - ux_[nm], bf);
-            }
-            if (oy != 0) {
-              gph[1] = fmaf(dphi, Ky, gph[1]);
-              bf = fmaf(Ky, uy_[np] - uy_[nm], bf);
-            }
-            if (oz != 0) {
-              gph[2] = fmaf(dphi, Kz, gph[2]);
-              bf = fmaf(Kz, uz_[np] - uz_[nm], bf);
-            }
-            continue;
-          }
-          Real upk = 0, umk = 0;
+          // energy sum: K . ((phi u)_+ - (phi u)_-) and (phi_+ - phi_-) K (the
+          // corrector's planes hold phi u; the predictor forms it here)
+          const Real fp = phi_[np], fm = phi_[nm];
+          auto dphiu = [&](const Real* u_) {
+            if constexpr (kPhiU) return u_[np] - u_[nm];
+            else return fmaf(-fm, u_[nm], fp * u_[np]);
+          };
           if (ox != 0) {
-            upk += (uc[0] + ux_[np]) * Kx;
-            umk += (uc[0] + ux_[nm]) * Kx;
+            gph[0] = fmaf(dphi, Kx, gph[0]);
+            bf = fmaf(Kx, dphiu(ux_), bf);
             if constexpr (!kCorr) dvf = fmaf(Kx, ux_[np] - ux_[nm], dvf);
           }
           if (oy != 0) {
-            upk += (uc[1] + uy_[np]) * Ky;
-            umk += (uc[1] + uy_[nm]) * Ky;
+            gph[1] = fmaf(dphi, Ky, gph[1]);
+            bf = fmaf(Ky, dphiu(uy_), bf);
             if constexpr (!kCorr) dvf = fmaf(Ky, uy_[np] - uy_[nm], dvf);
           }
           if (oz != 0) {
-            upk += (uc[2] + uz_[np]) * Kz;
-            umk += (uc[2] + uz_[nm]) * Kz;
+            gph[2] = fmaf(dphi, Kz, gph[2]);
+            bf = fmaf(Kz, dphiu(uz_), bf);
             if constexpr (!kCorr) dvf = fmaf(Kz, uz_[np] - uz_[nm], dvf);
           }
-          bf += (Real)0.5 * fc * (phi_[np] * upk - phi_[nm] * umk);
         }
       }
       const long long c = cell(g, i, j, k);
@@ -893,18 +883,14 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
 #pragma unroll
         for (int d = 0; d < 3; ++d) Av[d] = a[d];
         Bv = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
-      } else if constexpr (kPhiU) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) Av[d] = af[d];
-        // the cell's own u* (the planes hold phi u)
-        Real u0[3];
-        velocity(g, rc, F.ms[0][c], F.ms[1][c], F.ms[2][c], u0);
-        const Real ug = u0[0] * gph[0] + u0[1] * gph[1] + u0[2] * gph[2];
-        Bv = (Real)0.5 * fc * (ug + bf) + rc * (u0[0] * gf[0] + u0[1] * gf[1] + u0[2] * gf[2]);
       } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) Av[d] = af[d];
-        Bv = bf + rc * (uc[0] * gf[0] + uc[1] * gf[1] + uc[2] * gf[2]);
+        // the cell's own velocity (the corrector's planes hold phi u)
+        Real u0[3] = {uc[0], uc[1], uc[2]};
+        if constexpr (kPhiU) velocity(g, rc, F.ms[0][c], F.ms[1][c], F.ms[2][c], u0);
+        const Real ug = u0[0] * gph[0] + u0[1] * gph[1] + u0[2] * gph[2];
+        Bv = (Real)0.5 * fc * (ug + bf) + rc * (u0[0] * gf[0] + u0[1] * gf[1] + u0[2] * gf[2]);
       }
       const Real m0[3] = {MX[c], MY[c], MZ[c]};
       if constexpr (!kCorr) {
