@@ -33,7 +33,7 @@ class _Params(C.Structure):
                 ("cfl", C.c_double), ("rho_vac", C.c_double), ("bc", C.c_int32 * 6),
                 ("inflow", (C.c_double * 5) * 6), ("pos_mode", C.c_int32),
                 ("base_mode", C.c_int32), ("limiter", C.c_int32), ("flux", C.c_int32),
-                ("face_mode", C.c_int32)]
+                ("face_mode", C.c_int32), ("nu", C.c_double)]
 
 
 _lib = None
@@ -116,7 +116,7 @@ class OracleSim:
     def __init__(self, shape, h, gamma=1.4, cfl=0.4, rho_vac=1e-10, bc=(PERIODIC,) * 6,
                  inflow=None, origin=(0.0, 0.0, 0.0), pos_mode=POS_LAGRANGE,
                  base_mode=BASE_POST, limiter=LIM_MINMOD, flux=FLUX_SWEPT_AV,
-                 face_mode=FACE_FOOT):
+                 face_mode=FACE_FOOT, nu=0.0):
         nx, ny, nz = shape
         p = _Params()
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -132,6 +132,7 @@ class OracleSim:
                 p.inflow[f][v] = st[v]
         p.pos_mode, p.base_mode, p.limiter, p.flux = pos_mode, base_mode, limiter, flux
         p.face_mode = face_mode
+        p.nu = nu
         self.params = p
         self.shape = (nz, ny, nx)
         self.h = h

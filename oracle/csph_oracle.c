@@ -277,6 +277,19 @@ static const int O13[13][3] = {
     {1, 0, 0},   {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1}, {0, -1, 1}, {1, -1, 1},
     {-1, 0, 1},  {0, 0, 1},  {1, 0, 1},  {-1, 1, 1}, {0, 1, 1},   {1, 1, 1}};
 
+/* Viscosity (Sec. 4 names viscous flows as an extension).  Reading: the SPH
+ * viscous force of Morris et al. (1997) on the same 3x3x3 neighbourhood, with a
+ * uniform kinematic viscosity nu.  Particle j pulls particle i towards its own
+ * velocity with
+ *   f_ij = nu (rho_i + rho_j)/2 lambda_ij (u_j - u_i),
+ *   lambda_ij = -2 (r_ij . K(r_ij)) / |r_ij|^2   (r_ij = r_i - r_j),
+ * which on the lattice is 2 w_|o| / h^2 (the operator sum_o lambda_o (f_j - f_i) is
+ * the lattice Laplacian, exact for quadratics), and does the work
+ * f_ij . (u_i + u_j)/2 on it.  Both are antisymmetric in i, j, so momentum and
+ * total energy are conserved exactly, while the kinetic energy falls by
+ * sum_pairs nu rho lambda |u_i - u_j|^2 and turns into heat.  For a uniform
+ * density the force is rho nu Lap(u) and the work div(rho nu grad(|u|^2/2)). */
+
 /* Q(U, r) at padded cell c.  The particles sit at cell centre + xi (xi == NULL:
  * on the lattice) and feel the potential psi_p (one value per particle).
  * Returns A and B with
@@ -296,9 +309,11 @@ static void hydro_force(const orc_sim* s, const double* rho, const double* phi,
   const double h = s->P.h;
   const double rc = rho[c], fc = phi[c], pc = psi_p[c];
   const double uc[3] = {u[0][c], u[1][c], u[2][c]};
+  const double nu = s->P.nu;
   double a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0;
+  double vm[3] = {0.0, 0.0, 0.0}, ve = 0.0;
   for (int q = 0; q < 13; ++q) {
-    double ta[2][3], tg[2][3], te[2];
+    double ta[2][3], tg[2][3], te[2], tv[2][3], tw[2];
     for (int side = 0; side < 2; ++side) {
       const int sg = side == 0 ? 1 : -1;
       const int ox = sg * O13[q][0], oy = sg * O13[q][1], oz = sg * O13[q][2];
@@ -321,17 +336,30 @@ static void hydro_force(const orc_sim* s, const double* rho, const double* phi,
         tg[side][k] = dpsi * K[k];
       }
       te[side] = ff * ub;
+      if (nu > 0.0) {
+        const double lam = -2.0 * (d[0] * K[0] + d[1] * K[1] + d[2] * K[2]) /
+                           (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double cv = (nu * lam) * (0.5 * (rc + rho[j]));
+        for (int k = 0; k < 3; ++k) tv[side][k] = cv * (u[k][j] - uc[k]);
+        tw[side] = 0.5 * (tv[side][0] * (uc[0] + u[0][j]) + tv[side][1] * (uc[1] + u[1][j]) +
+                          tv[side][2] * (uc[2] + u[2][j]));
+      }
     }
     for (int k = 0; k < 3; ++k) {
       a[k] = a[k] + (ta[0][k] + ta[1][k]);
       gp[k] = gp[k] + (tg[0][k] + tg[1][k]);
     }
     be = be + (te[0] + te[1]);
+    if (nu > 0.0) {
+      for (int k = 0; k < 3; ++k) vm[k] = vm[k] + (tv[0][k] + tv[1][k]);
+      ve = ve + (tw[0] + tw[1]);
+    }
   }
-  A[0] = a[0];
-  A[1] = a[1];
-  A[2] = a[2];
-  *B = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
+  /* Q = -(0, A, B): the viscous force and its work enter with the other sign */
+  A[0] = a[0] - vm[0];
+  A[1] = a[1] - vm[1];
+  A[2] = a[2] - vm[2];
+  *B = (be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2])) - ve;
 }
 
 /* Lattice divergence of a vector field at padded cell c: the same 27-point
@@ -366,7 +394,7 @@ int orc_create(const orc_params* p, orc_sim** out) {
   if (!p || !out) return ORC_ERR_ARG;
   *out = NULL;
   if (p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->h > 0.0) || !(p->gamma > 1.0) ||
-      !(p->cfl > 0.0) || !(p->rho_vac >= 0.0))
+      !(p->cfl > 0.0) || !(p->rho_vac >= 0.0) || !(p->nu >= 0.0))
     return ORC_ERR_ARG;
   for (int ax = 0; ax < 3; ++ax) {
     int lo = p->bc[2 * ax], hi = p->bc[2 * ax + 1];
@@ -533,9 +561,19 @@ static double signal_max(orc_sim* s) {
   return smax;
 }
 
+/* the explicit viscous limit of dt (Heun's method on the lattice Laplacian, whose
+ * most negative eigenvalue is -4 (6 w_1 + 8 w_sqrt3) / h^2 = -5.93 / h^2, is stable
+ * for nu dt <= 0.337 h^2); 0 when inviscid */
+static double visc_dt(const orc_sim* s) {
+  return s->P.nu > 0.0 ? 0.25 * s->P.h * s->P.h / s->P.nu : 0.0;
+}
+
 double orc_cfl_dt(orc_sim* s) {
   double smax = signal_max(s);
-  return smax > 0.0 ? s->P.cfl * s->P.h / smax : INFINITY;
+  double dt = smax > 0.0 ? s->P.cfl * s->P.h / smax : INFINITY;
+  const double dv = visc_dt(s);
+  if (dv > 0.0 && dv < dt) dt = dv;
+  return dt;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -593,8 +631,10 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
   /* O3: time step */
   double smax = signal_max(s);
   double dt;
-  if (smax > 0.0) {
-    dt = s->P.cfl * h / smax;
+  const double dv = visc_dt(s);
+  if (smax > 0.0 || dv > 0.0) {
+    dt = smax > 0.0 ? s->P.cfl * h / smax : dv;
+    if (dv > 0.0 && dv < dt) dt = dv;
     if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
   } else {
     if (!(dt_max > 0.0)) return ORC_ERR_NO_SIGNAL;

@@ -74,6 +74,7 @@ typedef struct {
   int32_t limiter;         /* ORC_LIM_* */
   int32_t flux;            /* ORC_FLUX_* */
   int32_t face_mode;       /* ORC_FACE_* */
+  double nu;               /* kinematic viscosity (0: inviscid) */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
