@@ -199,6 +199,16 @@ csph_status csph_stream_probe(int32_t reads, int32_t writes, int64_t words, int3
 csph_status csph_set_scheme(csph_sim* sim, csph_limiter limiter, csph_flux flux);
 csph_status csph_get_scheme(const csph_sim* sim, int32_t* limiter, int32_t* flux);
 
+/* Viscosity (Sec. 4 names viscous flows as an extension of the method): a
+ * uniform kinematic viscosity nu >= 0 (0, the default, is inviscid), applied in
+ * the Lagrangian stage as the SPH viscous force of Morris et al. on the 27-point
+ * neighbourhood, f_ij = nu (rho_i + rho_j)/2 lambda_ij (u_j - u_i) with the
+ * lattice weight lambda_ij = -2 (r_ij . grad W_ij) / |r_ij|^2, and its work
+ * f_ij . (u_i + u_j)/2 in the energy; momentum and energy stay conserved.  The
+ * step is further limited to nu dt <= h^2/4.  Applies from the next step.
+ * CSPH_ERR_ARG for a negative or non-finite nu or a batch member. */
+csph_status csph_set_viscosity(csph_sim* sim, double nu);
+
 /* Tile depth: the stencil sweeps give each workgroup a 32 x 8 tile of an x-y
  * plane and march it through tz planes along z.  Deeper tiles reuse more of the
  * halo they stage; shallower ones give more workgroups.  Each of the three

@@ -44,6 +44,11 @@ struct GridDev {
   // 1 if a potential was set; 0: psi = 0 everywhere, and psi(r*) stays 0 without
   // being loaded, interpolated or stored
   int psi;
+  // viscosity: kinematic nu (0: inviscid), the explicit limit h^2/(4 nu) of dt
+  // (0 when inviscid), and nu lambda_o per half-set offset, lambda_o =
+  // -2 (d . K(d)) / |d|^2 at d = -h o (the lattice pair weight of the viscous force)
+  double nu, dt_visc;
+  double nulam[13];
 };
 
 enum : int { kLimMinmod = 0, kLimMC = 1, kLimVanLeer = 2, kLimSuperbee = 3 };

@@ -610,8 +610,10 @@ __device__ __forceinline__ void begin_body(Ctrl* ctrl, const GridDev& g, double 
   }
   const double smax = __longlong_as_double((long long)ctrl->smax_bits[ctrl->cur]);
   double dt;
-  if (smax > 0.0) {
-    dt = g.cfl_h / smax;
+  const double dv = g.dt_visc;  // the viscous limit, 0 when inviscid
+  if (smax > 0.0 || dv > 0.0) {
+    dt = smax > 0.0 ? g.cfl_h / smax : dv;
+    if (dv > 0.0 && dv < dt) dt = dv;
     if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
   } else {
     if (!(dt_max > 0.0)) {
@@ -704,7 +706,8 @@ struct PlaneL {
 // kCorr: stage C (else P).  kPsi: a potential is set (g.psi); without one psi = 0
 // and psi(r*) stays 0.  The plane buffers S belong to the kernel, so every form
 // shares them.
-template <bool kCorr, bool kPsi>
+// kVisc: a viscosity is set (g.nu > 0): the viscous force and its work join the sums.
+template <bool kCorr, bool kPsi, bool kVisc>
 __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              const Ctrl* __restrict__ ctrl, const Tile& T) {
   const int par = ctrl->par;
@@ -729,7 +732,7 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
   // phi_c [(phi_+ - phi_-) u_c . K + ((phi u)_+ - (phi u)_-) . K] / 2, whose first
   // part reuses the pressure difference of the momentum sum.  The corrector keeps
   // phi u in its planes instead of u (it needs no neighbour velocity otherwise).
-  constexpr bool kPhiU = kCorr && !kF64;
+  constexpr bool kPhiU = kCorr && !kF64 && !kVisc;
 
   auto load = [&](int k) {
     const int s = ring3(k);
@@ -781,6 +784,9 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
       Acc a[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, be = 0.0, dv = 0.0;
       Real af[3] = {0, 0, 0}, gf[3] = {0, 0, 0}, bf = 0, dvf = 0;
       Real gph[3] = {0, 0, 0};  // FP32: sum of (phi_+ - phi_-) K
+      // viscous force and work (kVisc)
+      Acc vm[3] = {0.0, 0.0, 0.0}, ve = 0.0;
+      const Real* rho_ = &S.rho[0][0];
 #pragma unroll
       for (int q = 0; q < 13; ++q) {
         const int ox = O13::o[q][0], oy = O13::o[q][1], oz = O13::o[q][2];
@@ -833,6 +839,23 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
           }
           be = be + (te[0] + te[1]);
           if constexpr (!kCorr) dv = dv + (td[0] + td[1]);
+          if constexpr (kVisc) {
+            // f = nu lambda (rho_c + rho_n)/2 (u_n - u_c), work f . (u_c + u_n)/2
+            Acc tv[2][3], tw[2];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              const int n = side == 0 ? np : nm;
+              const Acc cv = g.nulam[q] * (0.5 * (rc + rho_[n]));
+              tv[side][0] = cv * (ux_[n] - uc[0]);
+              tv[side][1] = cv * (uy_[n] - uc[1]);
+              tv[side][2] = cv * (uz_[n] - uc[2]);
+              tw[side] = 0.5 * (tv[side][0] * (uc[0] + ux_[n]) + tv[side][1] * (uc[1] + uy_[n]) +
+                                tv[side][2] * (uc[2] + uz_[n]));
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) vm[d] = vm[d] + (tv[0][d] + tv[1][d]);
+            ve = ve + (tw[0] + tw[1]);
+          }
         } else {
           // pair difference phi_c (phi_+ - phi_-) + rho_c (psi_+ - psi_-): the FP32
           // differences are exact for neighbours within a factor 2, the combination
@@ -851,6 +874,20 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
           if (oz != 0) {
             af[2] += s * Kz;
             gf[2] += ds * Kz;
+          }
+          if constexpr (kVisc) {
+            const float nl = (float)g.nulam[q];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              const int n = side == 0 ? np : nm;
+              const float cv = nl * (0.5f * (rc + rho_[n]));
+              const float t0 = cv * (ux_[n] - uc[0]), t1 = cv * (uy_[n] - uc[1]),
+                          t2 = cv * (uz_[n] - uc[2]);
+              vm[0] += t0;
+              vm[1] += t1;
+              vm[2] += t2;
+              ve += 0.5f * (t0 * (uc[0] + ux_[n]) + t1 * (uc[1] + uy_[n]) + t2 * (uc[2] + uz_[n]));
+            }
           }
           // energy sum: K . ((phi u)_+ - (phi u)_-) and (phi_+ - phi_-) K (the
           // corrector's planes hold phi u; the predictor forms it here)
@@ -880,17 +917,19 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
       // A and B of this cell
       Real Av[3], Bv;
       if constexpr (kF64) {
+        // Q = -(0, A, B): the viscous force and its work enter with the other sign
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Av[d] = a[d];
-        Bv = be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2]);
+        for (int d = 0; d < 3; ++d) Av[d] = a[d] - vm[d];
+        Bv = (be + rc * (uc[0] * gp[0] + uc[1] * gp[1] + uc[2] * gp[2])) - ve;
       } else {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Av[d] = af[d];
+        for (int d = 0; d < 3; ++d) Av[d] = af[d] - (Real)vm[d];
         // the cell's own velocity (the corrector's planes hold phi u)
         Real u0[3] = {uc[0], uc[1], uc[2]};
         if constexpr (kPhiU) velocity(g, rc, F.ms[0][c], F.ms[1][c], F.ms[2][c], u0);
         const Real ug = u0[0] * gph[0] + u0[1] * gph[1] + u0[2] * gph[2];
-        Bv = (Real)0.5 * fc * (ug + bf) + rc * (u0[0] * gf[0] + u0[1] * gf[1] + u0[2] * gf[2]);
+        Bv = (Real)0.5 * fc * (ug + bf) + rc * (u0[0] * gf[0] + u0[1] * gf[1] + u0[2] * gf[2]) -
+             (Real)ve;
       }
       const Real m0[3] = {MX[c], MY[c], MZ[c]};
       if constexpr (!kCorr) {
@@ -1455,6 +1494,18 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
 }
 
 // ------------------------------------------------------------------ stage launches
+// one Lagrangian sweep in the form the grid needs (potential, viscosity)
+template <bool kCorr>
+__device__ __forceinline__ void lattice_sweep(PlaneL& S, const Fields<Real>& F, const GridDev& g,
+                                              const BcDev& bc, const Ctrl* ctrl, const Tile& T) {
+  if (g.nu > 0.0) {
+    if (g.psi) stage_l_body<kCorr, true, true>(S, F, g, bc, ctrl, T);
+    else stage_l_body<kCorr, false, true>(S, F, g, bc, ctrl, T);
+  } else {
+    if (g.psi) stage_l_body<kCorr, true, false>(S, F, g, bc, ctrl, T);
+    else stage_l_body<kCorr, false, false>(S, F, g, bc, ctrl, T);
+  }
+}
 __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev bc,
                                                 const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
@@ -1462,8 +1513,7 @@ __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev
   int id;
   if (!single_tile(g, tz, T, id)) return;
   __shared__ PlaneL S;
-  if (g.psi) stage_l_body<false, true>(S, F, g, bc, ctrl, T);
-  else stage_l_body<false, false>(S, F, g, bc, ctrl, T);
+  lattice_sweep<false>(S, F, g, bc, ctrl, T);
 }
 
 __global__ void __launch_bounds__(NT) k_stage_c(Fields<Real> F, GridDev g, BcDev bc,
@@ -1473,8 +1523,7 @@ __global__ void __launch_bounds__(NT) k_stage_c(Fields<Real> F, GridDev g, BcDev
   int id;
   if (!single_tile(g, tz, T, id)) return;
   __shared__ PlaneL S;
-  if (g.psi) stage_l_body<true, true>(S, F, g, bc, ctrl, T);
-  else stage_l_body<true, false>(S, F, g, bc, ctrl, T);
+  lattice_sweep<true>(S, F, g, bc, ctrl, T);
 }
 
 // Workgroups per CU the register allocation must allow: the default scheme's
@@ -1505,12 +1554,10 @@ __global__ void __launch_bounds__(NT, kStage == 2 ? e_blocks(kGen) : 2)
   tile_at(I.g, I.tz, w.y, T);
   if constexpr (kStage == 0) {
     __shared__ PlaneL S;
-    if (I.g.psi) stage_l_body<false, true>(S, I.F, I.g, I.bc, I.ctrl, T);
-    else stage_l_body<false, false>(S, I.F, I.g, I.bc, I.ctrl, T);
+    lattice_sweep<false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if constexpr (kStage == 1) {
     __shared__ PlaneL S;
-    if (I.g.psi) stage_l_body<true, true>(S, I.F, I.g, I.bc, I.ctrl, T);
-    else stage_l_body<true, false>(S, I.F, I.g, I.bc, I.ctrl, T);
+    lattice_sweep<true>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if (!kGen || default_scheme(I.g))
     stage_e_body<false>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);
   else

@@ -146,6 +146,20 @@ struct Layout {
   int nblocks;
 };
 
+// viscosity constants of a grid: nu lambda_o with lambda_o = -2 (d . K) / |d|^2 at
+// the lattice separation d = -h o, and the explicit limit of dt (the arithmetic
+// of the kernels' FP64 build, operation for operation)
+void set_viscosity(GridDev& g, double nu) {
+  g.nu = nu;
+  g.dt_visc = nu > 0.0 ? 0.25 * g.h * g.h / nu : 0.0;
+  for (int q = 0; q < 13; ++q) {
+    const double dx = -kHalf[q][0] * g.h, dy = -kHalf[q][1] * g.h, dz = -kHalf[q][2] * g.h;
+    const double lam = -2.0 * (dx * g.klat[q][0] + dy * g.klat[q][1] + dz * g.klat[q][2]) /
+                       (dx * dx + dy * dy + dz * dz);
+    g.nulam[q] = nu * lam;
+  }
+}
+
 GridDev make_grid(const csph_grid_desc* d) {
   GridDev g{};
   g.nx = d->nx;
@@ -178,6 +192,7 @@ GridDev make_grid(const csph_grid_desc* d) {
   g.limiter = kLimMinmod;
   g.flux = kFluxSweptAV;
   g.psi = 0;
+  set_viscosity(g, 0.0);
   return g;
 }
 
@@ -861,6 +876,14 @@ csph_status csph_set_scheme(csph_sim* s, csph_limiter limiter, csph_flux flux) {
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
   s->g.limiter = (int)limiter;
   s->g.flux = (int)flux;
+  return CSPH_OK;
+}
+
+csph_status csph_set_viscosity(csph_sim* s, double nu) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(CSPH_ERR_ARG, "nu must be finite and >= 0");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
+  set_viscosity(s->g, nu);
   return CSPH_OK;
 }
 

@@ -57,6 +57,7 @@ class Problem:
     rho_vac: float = 1e-10
     t_end: float = math.inf
     steps: Optional[int] = None
+    nu: float = 0.0                      # kinematic viscosity (0: inviscid)
 
     @property
     def cells(self) -> int:

@@ -186,6 +186,10 @@ class Sim:
         """TVD limiter and face flux of the Eulerian stage (``_lib.LIM_*``, ``_lib.FLUX_*``)."""
         check(_lib.load().csph_set_scheme(self._h, int(limiter), int(flux)), "csph_set_scheme")
 
+    def set_viscosity(self, nu):
+        """Uniform kinematic viscosity of the Lagrangian stage (0: inviscid)."""
+        check(_lib.load().csph_set_viscosity(self._h, float(nu)), "csph_set_viscosity")
+
     def scheme(self):
         lim, flux = C.c_int32(), C.c_int32()
         check(_lib.load().csph_get_scheme(self._h, C.byref(lim), C.byref(flux)), "csph_get_scheme")
@@ -236,6 +240,8 @@ def from_problem(prob, dtype="f64", torch=False, stream=None) -> Sim:
         s.set_boundary(f, prob.bc[f], prob.inflow.get(f) if prob.bc[f] == _lib.INFLOW else None)
     s.set_potential(prob.psi)
     s.set_primitive(prob.prim)
+    if prob.nu:
+        s.set_viscosity(prob.nu)
     return s
 
 

@@ -8,7 +8,8 @@ import oracle as O
 
 def oracle_sim(prob, **kw):
     s = O.OracleSim(prob.shape, prob.h, gamma=prob.gamma, cfl=prob.cfl, rho_vac=prob.rho_vac,
-                    bc=prob.bc, inflow=prob.inflow_list(), origin=prob.origin, **kw)
+                    bc=prob.bc, inflow=prob.inflow_list(), origin=prob.origin,
+                    **dict({"nu": prob.nu}, **kw))
     s.set_primitive(prob.prim)
     s.set_potential(prob.psi)
     return s
