@@ -1494,18 +1494,23 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
 }
 
 // ------------------------------------------------------------------ stage launches
-// one Lagrangian sweep in the form the grid needs (potential, viscosity)
-template <bool kCorr>
+// one Lagrangian sweep in the form the grid needs (with or without a potential;
+// kVisc fixed by the caller, so that the inviscid kernels are not given the
+// viscous form's registers)
+template <bool kCorr, bool kVisc>
 __device__ __forceinline__ void lattice_sweep(PlaneL& S, const Fields<Real>& F, const GridDev& g,
                                               const BcDev& bc, const Ctrl* ctrl, const Tile& T) {
-  if (g.nu > 0.0) {
-    if (g.psi) stage_l_body<kCorr, true, true>(S, F, g, bc, ctrl, T);
-    else stage_l_body<kCorr, false, true>(S, F, g, bc, ctrl, T);
-  } else {
-    if (g.psi) stage_l_body<kCorr, true, false>(S, F, g, bc, ctrl, T);
-    else stage_l_body<kCorr, false, false>(S, F, g, bc, ctrl, T);
-  }
+  if (g.psi) stage_l_body<kCorr, true, kVisc>(S, F, g, bc, ctrl, T);
+  else stage_l_body<kCorr, false, kVisc>(S, F, g, bc, ctrl, T);
 }
+template <bool kCorr>
+__device__ __forceinline__ void lattice_sweep_any(PlaneL& S, const Fields<Real>& F, const GridDev& g,
+                                                  const BcDev& bc, const Ctrl* ctrl, const Tile& T) {
+  if (g.nu > 0.0) lattice_sweep<kCorr, true>(S, F, g, bc, ctrl, T);
+  else lattice_sweep<kCorr, false>(S, F, g, bc, ctrl, T);
+}
+
+template <bool kVisc>
 __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev bc,
                                                 const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
@@ -1513,9 +1518,10 @@ __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev
   int id;
   if (!single_tile(g, tz, T, id)) return;
   __shared__ PlaneL S;
-  lattice_sweep<false>(S, F, g, bc, ctrl, T);
+  lattice_sweep<false, kVisc>(S, F, g, bc, ctrl, T);
 }
 
+template <bool kVisc>
 __global__ void __launch_bounds__(NT) k_stage_c(Fields<Real> F, GridDev g, BcDev bc,
                                                    const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
@@ -1523,7 +1529,7 @@ __global__ void __launch_bounds__(NT) k_stage_c(Fields<Real> F, GridDev g, BcDev
   int id;
   if (!single_tile(g, tz, T, id)) return;
   __shared__ PlaneL S;
-  lattice_sweep<true>(S, F, g, bc, ctrl, T);
+  lattice_sweep<true, kVisc>(S, F, g, bc, ctrl, T);
 }
 
 // Workgroups per CU the register allocation must allow: the default scheme's
@@ -1554,10 +1560,10 @@ __global__ void __launch_bounds__(NT, kStage == 2 ? e_blocks(kGen) : 2)
   tile_at(I.g, I.tz, w.y, T);
   if constexpr (kStage == 0) {
     __shared__ PlaneL S;
-    lattice_sweep<false>(S, I.F, I.g, I.bc, I.ctrl, T);
+    lattice_sweep_any<false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if constexpr (kStage == 1) {
     __shared__ PlaneL S;
-    lattice_sweep<true>(S, I.F, I.g, I.bc, I.ctrl, T);
+    lattice_sweep_any<true>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if (!kGen || default_scheme(I.g))
     stage_e_body<false>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);
   else
@@ -1692,11 +1698,13 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
   k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(1);
-  k_stage_p<<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
+  if (g.nu > 0.0) k_stage_p<true><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
+  else k_stage_p<false><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
   mark(2);
   k_fill_pred<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(3);
-  k_stage_c<<<nbc, NT, 0, s>>>(F, g, bc, ctrl, tz[1]);
+  if (g.nu > 0.0) k_stage_c<true><<<nbc, NT, 0, s>>>(F, g, bc, ctrl, tz[1]);
+  else k_stage_c<false><<<nbc, NT, 0, s>>>(F, g, bc, ctrl, tz[1]);
   mark(4);
   k_fill_corr<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(5);
