@@ -134,9 +134,10 @@ struct Launch {
   // one step of every active member of a batch, one launch per stage
   // tile_map[t] = (member, tile of that member); fill_map[b] = (member, first
   // ghost cell of fill block b); generic: some member uses a non-default scheme
+  // viscous: some member has a viscosity (the Lagrangian sweeps' viscous form)
   static hipError_t batch_step(const Inst<Real>* tab, const int2* tile_map, const int2* fill_map,
                                int n, int total_tiles, int fill_blocks, int* flags, bool generic,
-                               hipStream_t s);
+                               bool viscous, hipStream_t s);
   static int tiles(const GridDev& g, int tz);
   static int default_tz(const GridDev& g);
   static long long ghosts(const GridDev& g);

@@ -1547,7 +1547,9 @@ __global__ void __launch_bounds__(NT, e_blocks(kGen)) k_stage_e(Fields<Real> F, 
 }
 
 // batched sweeps: workgroup -> (instance, tile) through a host-built map of the
-// flattened tile list; the XCD inversion runs over the whole list
+// flattened tile list; the XCD inversion runs over the whole list.  kGen: the
+// general form -- for stage E a member uses a non-default scheme, for stages P
+// and C a member has a viscosity (each member then takes its own form)
 template <int kStage, bool kGen>
 __global__ void __launch_bounds__(NT, kStage == 2 ? e_blocks(kGen) : 2)
     k_stage_batch(const Inst<Real>* __restrict__ tab, const int2* __restrict__ map, int ntiles) {
@@ -1560,10 +1562,12 @@ __global__ void __launch_bounds__(NT, kStage == 2 ? e_blocks(kGen) : 2)
   tile_at(I.g, I.tz, w.y, T);
   if constexpr (kStage == 0) {
     __shared__ PlaneL S;
-    lattice_sweep_any<false>(S, I.F, I.g, I.bc, I.ctrl, T);
+    if constexpr (kGen) lattice_sweep_any<false>(S, I.F, I.g, I.bc, I.ctrl, T);
+    else lattice_sweep<false, false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if constexpr (kStage == 1) {
     __shared__ PlaneL S;
-    lattice_sweep_any<true>(S, I.F, I.g, I.bc, I.ctrl, T);
+    if constexpr (kGen) lattice_sweep_any<true>(S, I.F, I.g, I.bc, I.ctrl, T);
+    else lattice_sweep<true, false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if (!kGen || default_scheme(I.g))
     stage_e_body<false>(I.F, I.g, I.bc, I.ctrl, T, I.partials + (long long)w.y * 5);
   else
@@ -1632,14 +1636,20 @@ long long Launch<Real>::ghosts(const GridDev& g) {
 template <>
 hipError_t Launch<Real>::batch_step(const Inst<Real>* tab, const int2* tile_map, const int2* fill_map,
                                     int n, int total_tiles, int fill_blocks, int* flags, bool generic,
-                                    hipStream_t s) {
+                                    bool viscous, hipStream_t s) {
   const unsigned nb = (unsigned)((total_tiles + kXcd - 1) / kXcd * kXcd);
   const unsigned ib = (unsigned)((n + 63) / 64);
   k_begin_batch<<<ib, 64, 0, s>>>(tab, n);
   k_fill_batch<0><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
-  k_stage_batch<0, false><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  if (viscous)
+    k_stage_batch<0, true><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  else
+    k_stage_batch<0, false><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
   k_fill_batch<1><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
-  k_stage_batch<1, false><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  if (viscous)
+    k_stage_batch<1, true><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
+  else
+    k_stage_batch<1, false><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);
   k_fill_batch<2><<<fill_blocks, 256, 0, s>>>(tab, fill_map, fill_blocks);
   if (generic)
     k_stage_batch<2, true><<<nb, NT, 0, s>>>(tab, tile_map, total_tiles);

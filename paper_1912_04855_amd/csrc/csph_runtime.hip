@@ -1115,6 +1115,7 @@ struct csph_batch {
   int total_tiles = 0;
   int fill_blocks = 0;
   bool generic = false;  // a member uses a non-default scheme (generic stage-E kernel)
+  bool viscous = false;  // a member has a viscosity (viscous form of the Lagrangian sweeps)
   bool dirty = true;
   // a captured k-step graph, replayed while membership does not change
   hipGraph_t graph = nullptr;
@@ -1171,6 +1172,7 @@ csph_status build_table(csph_batch* b) {
   std::vector<Inst<Real>> tab(n);
   std::vector<int2> tmap, fmap;
   b->generic = false;
+  b->viscous = false;
   for (size_t r = 0; r < n; ++r) {
     csph_sim* s = b->slots[b->order[r]].sim;
     Inst<Real>& I = tab[r];
@@ -1183,6 +1185,7 @@ csph_status build_table(csph_batch* b) {
     I.tz = s->tz[1];
     s->tz_last = I.tz;
     if (!default_scheme(s->g)) b->generic = true;
+    if (s->g.nu > 0.0) b->viscous = true;
     const int nt = Launch<Real>::tiles(s->g, I.tz);
     for (int t = 0; t < nt; ++t) tmap.push_back(make_int2((int)r, t));
     // each member's ghost cells in whole fill blocks (one member per block)
@@ -1220,7 +1223,8 @@ csph_status batch_launch(csph_batch* b, int k) {
     hipError_t e = hipSuccess;
     for (int q = 0; q < k && e == hipSuccess; ++q)
       e = Launch<Real>::batch_step((const Inst<Real>*)b->table, b->tile_map, b->fill_map, n,
-                                   b->total_tiles, b->fill_blocks, b->flags, b->generic, b->stream);
+                                   b->total_tiles, b->fill_blocks, b->flags, b->generic, b->viscous,
+                                   b->stream);
     hipGraph_t gr = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
     if (e != hipSuccess || e2 != hipSuccess) {
