@@ -308,12 +308,18 @@ def run_serve(count=40, rate=1.0, seed=0, budget=64 << 30):
 
 
 def source_hash():
+    """Hash of the kernel sources (csrc/*.hip, *.h) with comments and blank space
+    removed, so that a counter summary stays tied to the code, not to its prose."""
     import hashlib
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1912_04855_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(d, f), "rb").read())
+            txt = open(os.path.join(d, f), encoding="utf-8").read()
+            txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+            txt = re.sub(r"//[^\n]*", " ", txt)
+            h.update(" ".join(txt.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -10,25 +10,29 @@
 // the time step and the conservation totals.
 //
 // Per step:
-//   begin  : dt from the max signal speed of U^n (FP64), CFL rule
+//   begin  : dt from the max signal speed of U^n (FP64), CFL and viscous limits
 //   fill   : ghost cells of U^n
-//   stage P: predictor, Eq. (5) with Q of Eq. (7) on the lattice
-//   fill   : ghost cells of m*, E*, xi* and of psi at r*
-//   stage C: corrector, Eq. (6) with Q of Eq. (7) at the displaced particles
+//   stage P: predictor, Eq. (5) with Q of Eq. (7) on the lattice; the predicted
+//            particle's phi* over its predicted volume, psi at r*
+//   fill   : ghost cells of m*, phi*, xi* and of psi at r*
+//   stage C: corrector, Eq. (6) with Q(U*, r*) of Eq. (7) in the particles'
+//            reference configuration (lattice kernel gradients, the predicted
+//            particles' phi* and psi at r*)
 //   fill   : ghost cells of m~, E~, xi^{n+1}
-//   stage E: reconstruction Eq. (8), face fluxes, update Eq. (4); epilogue:
-//            signal-speed max of U^{n+1}, FP64 block totals, error flags
+//   stage E: reconstruction Eq. (8), face fluxes (swept width at the foot of the
+//            face's trajectory), update Eq. (4); epilogue: signal-speed max of
+//            U^{n+1}, FP64 block totals, error flags
 //   end    : swap the state copies
 //
 // Stages P, C and E are 2.5D stencil sweeps: a workgroup owns a TX x TY tile of
-// an x-y plane and marches along z through TZ planes.  P and C keep three planes
-// of per-cell derived quantities (primitive variables, offsets, potential) with
-// a one-cell halo in LDS, so each cell's primitives are formed once per sweep
-// instead of once per neighbour.  E keeps a register queue of its own column
-// along z (U^n at k-1..k+2, the z-face flux carried to the next plane) and the
-// current plane's x-y stencil (two-cell halo) in LDS.  Workgroup ids are
-// remapped so that each of the 8 XCDs (separate L2s) gets a contiguous run of
-// tiles, which keeps the halo reads of neighbouring tiles in one L2.
+// an x-y plane and marches along z through TZ planes.  P and C are one sweep
+// (stage_l_body) that keeps three planes of per-cell values (density, phi,
+// velocity, potential) with a one-cell halo in LDS, so each cell's values are
+// formed once per sweep instead of once per neighbour.  E keeps a register queue
+// of its own column along z (U^n at k-1..k+2, the z-face flux carried to the next
+// plane) and the current plane's x-y stencil (two-cell halo) in LDS.  Workgroup
+// ids are remapped so that each of the 8 XCDs (separate L2s) gets a contiguous
+// run of tiles, which keeps the halo reads of neighbouring tiles in one L2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -415,7 +419,7 @@ __device__ __forceinline__ bool in_x_zone(const GridDev& g, unsigned t) {
   return t >= 4u * (unsigned)g.sx * (unsigned)g.sy + (unsigned)g.nz * 4u * (unsigned)g.sx;
 }
 
-// ghosts of the predicted particles, then psi at their displaced positions for
+// ghosts of the predicted particles, then psi at their predicted positions for
 // the first ghost layer (the corrector reads psi* of index neighbours only)
 __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                                const Ctrl* ctrl, unsigned t) {
