@@ -21,7 +21,8 @@ FLUX_SWEPT, FLUX_LF, FLUX_SWEPT_AV = 0, 1, 2
 FACE_FOOT, FACE_PARTICLE = 0, 1
 
 FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
-          "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "psis", "vol", "phis"]
+          "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "psis", "vol", "phis", "psi",
+          "psih"]
 
 ERRORS = {0: "ok", 1: "bad argument", 2: "out of memory", 5: "non-finite value",
           6: "negative density", 7: "no signal speed (need dt_max)"}
@@ -33,7 +34,7 @@ class _Params(C.Structure):
                 ("cfl", C.c_double), ("rho_vac", C.c_double), ("bc", C.c_int32 * 6),
                 ("inflow", (C.c_double * 5) * 6), ("pos_mode", C.c_int32),
                 ("base_mode", C.c_int32), ("limiter", C.c_int32), ("flux", C.c_int32),
-                ("face_mode", C.c_int32), ("nu", C.c_double)]
+                ("face_mode", C.c_int32), ("nu", C.c_double), ("grav", C.c_double)]
 
 
 _lib = None
@@ -71,6 +72,7 @@ def lib():
         L.orc_limiter.restype = C.c_double
         L.orc_lattice_gradient.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double, dp, dp]
         L.orc_interp_psi.argtypes = [vp, dp, dp]
+        L.orc_self_potential.argtypes = [vp, dp, dp]
         L.orc_fill_ghosts_padded.argtypes = [vp, dp, C.c_int, C.c_double]
         _lib = L
     return _lib
@@ -116,7 +118,7 @@ class OracleSim:
     def __init__(self, shape, h, gamma=1.4, cfl=0.4, rho_vac=1e-10, bc=(PERIODIC,) * 6,
                  inflow=None, origin=(0.0, 0.0, 0.0), pos_mode=POS_LAGRANGE,
                  base_mode=BASE_POST, limiter=LIM_MINMOD, flux=FLUX_SWEPT_AV,
-                 face_mode=FACE_FOOT, nu=0.0):
+                 face_mode=FACE_FOOT, nu=0.0, grav=0.0):
         nx, ny, nz = shape
         p = _Params()
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -133,6 +135,7 @@ class OracleSim:
         p.pos_mode, p.base_mode, p.limiter, p.flux = pos_mode, base_mode, limiter, flux
         p.face_mode = face_mode
         p.nu = nu
+        p.grav = grav
         self.params = p
         self.shape = (nz, ny, nx)
         self.h = h
@@ -219,6 +222,13 @@ class OracleSim:
         off = np.ascontiguousarray(off, dtype=np.float64)
         out = np.empty(self.shape)
         _check(lib().orc_interp_psi(self._h, off, out), "interp_psi")
+        return out
+
+    def self_potential(self, rho) -> np.ndarray:
+        """The self-gravity potential the step would compute from this density."""
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        out = np.empty(self.shape)
+        _check(lib().orc_self_potential(self._h, rho, out), "self_potential")
         return out
 
     def fill_ghosts_padded(self, padded, role, dt=0.0):

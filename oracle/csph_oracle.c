@@ -43,6 +43,9 @@ struct orc_sim {
   double *mt[3], *Et, *xt[3];
   double *psis;       /* psi at the predicted particle positions */
   double *vol;        /* predicted particle volume / h^3 (Lagrangian corrector) */
+  double *psi_ext;    /* the external potential as set (self-gravity adds to it) */
+  double *psih;       /* self-gravity: the potential at t^{n+1}, from the predicted density */
+  double *fre, *fim;  /* Poisson solve: one complex value per interior cell */
   /* Eulerian stage */
   double *slope[5], *flux[5], *acc[5];
   double t;
@@ -250,13 +253,13 @@ static void fill_ghosts(orc_sim* s, double* f, int role, double dt) {
  * cell's own value exactly. */
 static double lerp(double a, double b, double t) { return a + t * (b - a); }
 
-static double psi_at(const orc_sim* s, size_t c, double ox, double oy, double oz) {
+static double psi_at(const orc_sim* s, const double* P, size_t c, double ox, double oy,
+                     double oz) {
   const double fx = ox * s->inv_h, fy = oy * s->inv_h, fz = oz * s->inv_h;
   const long di = fx >= 0.0 ? 1 : -1;
   const long dj = (fy >= 0.0 ? 1 : -1) * (long)s->sx;
   const long dk = (fz >= 0.0 ? 1 : -1) * (long)s->sx * (long)s->sy;
   const double tx = fabs(fx), ty = fabs(fy), tz = fabs(fz);
-  const double* P = s->psi;
   const long cc = (long)c;
   double a00 = lerp(P[cc], P[cc + di], tx);
   double a10 = lerp(P[cc + dj], P[cc + dj + di], tx);
@@ -394,8 +397,11 @@ int orc_create(const orc_params* p, orc_sim** out) {
   if (!p || !out) return ORC_ERR_ARG;
   *out = NULL;
   if (p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->h > 0.0) || !(p->gamma > 1.0) ||
-      !(p->cfl > 0.0) || !(p->rho_vac >= 0.0) || !(p->nu >= 0.0))
+      !(p->cfl > 0.0) || !(p->rho_vac >= 0.0) || !(p->nu >= 0.0) || !(p->grav >= 0.0))
     return ORC_ERR_ARG;
+  if (p->grav > 0.0)
+    for (int f = 0; f < 6; ++f)
+      if (p->bc[f] != ORC_PERIODIC) return ORC_ERR_ARG;
   for (int ax = 0; ax < 3; ++ax) {
     int lo = p->bc[2 * ax], hi = p->bc[2 * ax + 1];
     if (lo < 0 || lo > 3 || hi < 0 || hi > 3) return ORC_ERR_ARG;
@@ -421,7 +427,7 @@ int orc_create(const orc_params* p, orc_sim** out) {
   double** all[] = {&s->rho, &s->m[0], &s->m[1], &s->m[2], &s->E, &s->psi, &s->u[0], &s->u[1],
                     &s->u[2], &s->p, &s->phi, &s->ms[0], &s->ms[1], &s->ms[2], &s->Es, &s->xs[0],
                     &s->xs[1], &s->xs[2], &s->mt[0], &s->mt[1], &s->mt[2], &s->Et, &s->xt[0],
-                    &s->xt[1], &s->xt[2], &s->psis, &s->vol, &s->slope[0], &s->slope[1], &s->slope[2],
+                    &s->xt[1], &s->xt[2], &s->psis, &s->vol, &s->psi_ext, &s->psih, &s->fre, &s->fim, &s->slope[0], &s->slope[1], &s->slope[2],
                     &s->slope[3], &s->slope[4], &s->flux[0], &s->flux[1], &s->flux[2], &s->flux[3],
                     &s->flux[4], &s->acc[0], &s->acc[1], &s->acc[2], &s->acc[3], &s->acc[4]};
   for (size_t k = 0; k < sizeof all / sizeof all[0]; ++k) {
@@ -440,7 +446,7 @@ void orc_destroy(orc_sim* s) {
   double* all[] = {s->rho, s->m[0], s->m[1], s->m[2], s->E, s->psi, s->u[0], s->u[1], s->u[2],
                    s->p, s->phi, s->ms[0], s->ms[1], s->ms[2], s->Es, s->xs[0], s->xs[1],
                    s->xs[2], s->mt[0], s->mt[1], s->mt[2], s->Et, s->xt[0], s->xt[1], s->xt[2],
-                   s->psis, s->vol, s->slope[0], s->slope[1], s->slope[2], s->slope[3], s->slope[4],
+                   s->psis, s->vol, s->psi_ext, s->psih, s->fre, s->fim, s->slope[0], s->slope[1], s->slope[2], s->slope[3], s->slope[4],
                    s->flux[0], s->flux[1], s->flux[2], s->flux[3], s->flux[4], s->acc[0],
                    s->acc[1], s->acc[2], s->acc[3], s->acc[4]};
   for (size_t k = 0; k < sizeof all / sizeof all[0]; ++k) free(all[k]);
@@ -496,6 +502,130 @@ int orc_set_potential(orc_sim* s, const double* psi) {
         for (int i = 0; i < s->P.nx; ++i, ++q) s->psi[IX(s, i, j, k)] = psi[q];
   }
   fill_ghosts(s, s->psi, R_PSI, 0.0);
+  memcpy(s->psi_ext, s->psi, s->n * sizeof(double));
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* self-gravity                                                              */
+/* ------------------------------------------------------------------------ */
+/* Sec. 4 names the gas's self-gravity as an extension.  Reading: on a periodic
+ * box the potential of the gas solves the discrete Poisson equation
+ *   L7[psi] = 4 pi G (rho - mean(rho)),
+ * L7 the 7-point Laplacian (f_{i+1} + f_{i-1} - 2 f_i)/h^2 summed over the axes;
+ * the total potential is the external one plus this.  The predictor, Eq. (5),
+ * takes the potential of rho^n.  The corrector, Eq. (6), evaluates Q at the end
+ * of the step, so it takes the potential of the density predicted for t^{n+1}
+ * by the continuity equation,
+ *   rho^ = rho^n - dt sum_d (m_d,i+1 - m_d,i-1) / (2h),
+ * which is rho^{n+1} to O(dt^2): a potential of rho^n there would make the force
+ * of the corrector O(dt) wrong and the step first order in time.  The solve is
+ * spectral: the discrete Fourier transform diagonalises L7 with eigenvalues
+ *   lambda(k) = sum_d (2 cos(2 pi k_d / n_d) - 2) / h^2,
+ * so psi_k = 4 pi G rho_k / lambda(k) for k != 0 and psi_0 = 0 (the mean density
+ * has no potential on a periodic box).  The transforms are plain O(n^2) sums
+ * along each axis. */
+
+#define ORC_PI 3.14159265358979323846
+
+/* DFT along one axis of the complex interior array (re, im), in place, with
+ * the sign sg of the exponent; scratch line buffers of length n */
+static void dft_axis(const orc_sim* s, double* re, double* im, int axis, double sg) {
+  const int n[3] = {s->P.nx, s->P.ny, s->P.nz};
+  const long st[3] = {1, n[0], (long)n[0] * n[1]};
+  const int m = n[axis];
+  double* lr = (double*)malloc(2 * (size_t)m * sizeof(double));
+  double* li = lr + m;
+  const int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
+  for (int b = 0; b < n[o2]; ++b)
+    for (int a = 0; a < n[o1]; ++a) {
+      const long base = (long)a * st[o1] + (long)b * st[o2];
+      for (int k = 0; k < m; ++k) {
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < m; ++j) {
+          const double ang = sg * 2.0 * ORC_PI * (double)(((long)j * k) % m) / (double)m;
+          const double c = cos(ang), sn = sin(ang);
+          const double xr = re[base + j * st[axis]], xi = im[base + j * st[axis]];
+          sr += xr * c - xi * sn;
+          si += xr * sn + xi * c;
+        }
+        lr[k] = sr;
+        li[k] = si;
+      }
+      for (int k = 0; k < m; ++k) {
+        re[base + k * st[axis]] = lr[k];
+        im[base + k * st[axis]] = li[k];
+      }
+    }
+  free(lr);
+}
+
+/* psi_self of the interior density rho_in ([nz][ny][nx]) into out ([nz][ny][nx]) */
+static void poisson(orc_sim* s, const double* rho_in, double* out) {
+  const int nx = s->P.nx, ny = s->P.ny, nz = s->P.nz;
+  const size_t N = (size_t)nx * ny * nz;
+  for (size_t q = 0; q < N; ++q) {
+    s->fre[q] = rho_in[q];
+    s->fim[q] = 0.0;
+  }
+  for (int ax = 0; ax < 3; ++ax) dft_axis(s, s->fre, s->fim, ax, -1.0);
+  const double h2 = s->P.h * s->P.h;
+  const double fpg = 4.0 * ORC_PI * s->P.grav;
+  size_t q = 0;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i, ++q) {
+        if (i == 0 && j == 0 && k == 0) {
+          s->fre[q] = 0.0;
+          s->fim[q] = 0.0;
+          continue;
+        }
+        const double lam = (2.0 * cos(2.0 * ORC_PI * i / nx) - 2.0) / h2 +
+                           (2.0 * cos(2.0 * ORC_PI * j / ny) - 2.0) / h2 +
+                           (2.0 * cos(2.0 * ORC_PI * k / nz) - 2.0) / h2;
+        const double f = fpg / lam / (double)N;
+        s->fre[q] *= f;
+        s->fim[q] *= f;
+      }
+  for (int ax = 2; ax >= 0; --ax) dft_axis(s, s->fre, s->fim, ax, 1.0);
+  for (size_t p = 0; p < N; ++p) out[p] = s->fre[p];
+}
+
+static void gather(const orc_sim* s, const double* src, double* out);
+
+/* out = psi_ext + the potential of the interior density rho_in; ghosts by wrap */
+static void self_gravity(orc_sim* s, const double* rho_in, double* out) {
+  const size_t N = ninterior(s);
+  double* pout = (double*)malloc(N * sizeof(double));
+  poisson(s, rho_in, pout);
+  size_t q = 0;
+  for (int k = 0; k < s->P.nz; ++k)
+    for (int j = 0; j < s->P.ny; ++j)
+      for (int i = 0; i < s->P.nx; ++i, ++q) {
+        const size_t c = IX(s, i, j, k);
+        out[c] = s->psi_ext[c] + pout[q];
+      }
+  free(pout);
+  fill_ghosts(s, out, R_PSI, 0.0);
+}
+
+/* the density predicted for t^{n+1} by the continuity equation (interior) */
+static void predicted_density(const orc_sim* s, double dt, double* out) {
+  const long st[3] = {1, s->sx, (long)s->sx * (long)s->sy};
+  size_t q = 0;
+  for (int k = 0; k < s->P.nz; ++k)
+    for (int j = 0; j < s->P.ny; ++j)
+      for (int i = 0; i < s->P.nx; ++i, ++q) {
+        const size_t c = IX(s, i, j, k);
+        double div = 0.0;
+        for (int d = 0; d < 3; ++d) div += (s->m[d][c + st[d]] - s->m[d][c - st[d]]) / (2.0 * s->P.h);
+        out[q] = s->rho[c] - dt * div;
+      }
+}
+
+int orc_self_potential(orc_sim* s, const double* rho, double* psi_out) {
+  if (!s || !rho || !psi_out) return ORC_ERR_ARG;
+  poisson(s, rho, psi_out);
   return ORC_OK;
 }
 
@@ -519,7 +649,7 @@ int orc_get_field(const orc_sim* s, int which, double* out) {
   const double* src[ORC_F_COUNT] = {s->ms[0], s->ms[1], s->ms[2], s->Es,    s->xs[0],
                                     s->xs[1], s->xs[2], s->mt[0], s->mt[1], s->mt[2],
                                     s->Et,    s->xt[0], s->xt[1], s->xt[2], s->psis,
-                                    s->vol,   s->phi};
+                                    s->vol,   s->phi,   s->psi,   s->psih};
   gather(s, src[which], out);
   return ORC_OK;
 }
@@ -628,6 +758,14 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
   fill_ghosts(s, s->m[2], R_MZ, 0.0);
   fill_ghosts(s, s->E, R_E, 0.0);
 
+  /* self-gravity: the potential of rho^n, for the predictor */
+  if (s->P.grav > 0.0) {
+    double* rin = (double*)malloc(ninterior(s) * sizeof(double));
+    gather(s, s->rho, rin);
+    self_gravity(s, rin, s->psi);
+    free(rin);
+  }
+
   /* O3: time step */
   double smax = signal_max(s);
   double dt;
@@ -646,6 +784,17 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
     lands = 1;
   }
   if (!(dt > 0.0)) return ORC_ERR_ARG;
+
+  /* self-gravity: the potential of the density predicted for t^{n+1}, for the
+   * corrector; without it the corrector samples the potential of the step */
+  const double* psi_c = s->psi;
+  if (s->P.grav > 0.0) {
+    double* rin = (double*)malloc(ninterior(s) * sizeof(double));
+    predicted_density(s, dt, rin);
+    self_gravity(s, rin, s->psih);
+    free(rin);
+    psi_c = s->psih;
+  }
 
   /* O2: primitives of U^n on every cell, ghosts included */
   all_primitives(s, s->rho, s->m, s->E);
@@ -725,8 +874,9 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
     for (int j = -1; j <= ny; ++j)
       for (int i = -1; i <= nx; ++i) {
         size_t c = IX(s, i, j, k);
-        s->psis[c] = (displaced || lagrange) ? psi_at(s, c, s->xs[0][c], s->xs[1][c], s->xs[2][c])
-                                             : s->psi[c];
+        s->psis[c] = (displaced || lagrange)
+                         ? psi_at(s, psi_c, c, s->xs[0][c], s->xs[1][c], s->xs[2][c])
+                         : psi_c[c];
       }
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
@@ -930,7 +1080,7 @@ int orc_interp_psi(orc_sim* s, const double* off, double* out) {
   for (int k = 0; k < s->P.nz; ++k)
     for (int j = 0; j < s->P.ny; ++j)
       for (int i = 0; i < s->P.nx; ++i, ++q)
-        out[q] = psi_at(s, IX(s, i, j, k), off[q], off[N + q], off[2 * N + q]);
+        out[q] = psi_at(s, s->psi, IX(s, i, j, k), off[q], off[N + q], off[2 * N + q]);
   return ORC_OK;
 }
 

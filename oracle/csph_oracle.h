@@ -75,6 +75,8 @@ typedef struct {
   int32_t flux;            /* ORC_FLUX_* */
   int32_t face_mode;       /* ORC_FACE_* */
   double nu;               /* kinematic viscosity (0: inviscid) */
+  double grav;             /* gravitational constant G of the gas's self-gravity (0: none);
+                              needs periodic faces on every axis */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -88,6 +90,9 @@ enum {
   ORC_F_PSIS,                                        /* psi at r*             */
   ORC_F_VOL,                                         /* predicted volume / h^3 */
   ORC_F_PHIS,                                        /* phi* = sqrt(2 p*)      */
+  ORC_F_PSI,                                         /* potential of the step  */
+  ORC_F_PSIH,                                        /* self-gravity: potential
+                                                        of the predicted density */
   ORC_F_COUNT
 };
 
@@ -114,6 +119,9 @@ double   orc_limiter(int kind, double a, double b);
  * wrap of f; f and out are [nz][ny][nx] and [3][nz][ny][nx] */
 int      orc_lattice_gradient(int32_t nx, int32_t ny, int32_t nz, double h,
                               const double* f, double* out);
+/* self-gravity potential of a density field [nz][ny][nx] on the sim's periodic grid
+ * (the discrete Poisson solve of each step); writes [nz][ny][nx] */
+int      orc_self_potential(orc_sim* s, const double* rho, double* psi_out);
 /* trilinear interpolation of psi (with ghosts filled by the sim's rules) at
  * cell centre + offset; writes one value per cell */
 int      orc_interp_psi(orc_sim* s, const double* off /* [3][nz][ny][nx] */, double* out);

@@ -58,6 +58,7 @@ class Problem:
     t_end: float = math.inf
     steps: Optional[int] = None
     nu: float = 0.0                      # kinematic viscosity (0: inviscid)
+    grav: float = 0.0                    # G of the gas's self-gravity (0: none)
 
     @property
     def cells(self) -> int:
@@ -252,6 +253,25 @@ def advected_density(n=128, amp=0.2, u=(1.0, 0.0, 0.0), p0=1.0, gamma=1.4, trans
         prim[1 + d] = u[d]
     prim[4] = p0
     return Problem("advected_density", shape, h, gamma, cfl, (PERIODIC,) * 6, prim, t_end=t_end)
+
+
+def jeans_wave(n=64, G=1.5, delta=1e-5, rho0=1.0, gamma=5.0 / 3.0, axis=0, transverse=4,
+               t_end=0.5, cfl=0.4) -> Problem:
+    """A self-gravitating gas at rest with a standing density wave of one period on
+    the unit box along `axis` (periodic): rho = rho0 (1 + delta s), p = p0 + c^2
+    rho0 delta s, s = cos(2 pi x_axis), p0 = rho0 / gamma (sound speed c = 1)."""
+    shape = [transverse] * 3
+    shape[axis] = n
+    shape = tuple(shape)
+    h = 1.0 / n
+    xs = centres(shape, h)
+    s = np.broadcast_to(np.cos(2.0 * math.pi * xs[axis]), (shape[2], shape[1], shape[0]))
+    p0 = rho0 / gamma
+    prim = _prim(shape)
+    prim[0] = rho0 * (1.0 + delta * s)
+    prim[4] = p0 + rho0 * delta * s
+    return Problem("jeans_wave", shape, h, gamma, cfl, (PERIODIC,) * 6, prim, t_end=t_end,
+                   grav=G)
 
 
 def uniform_flow(shape=(8, 8, 8), u=(0.3, -0.2, 0.1), rho=1.0, p=1.0, gamma=1.4) -> Problem:

@@ -9,7 +9,7 @@ import oracle as O
 def oracle_sim(prob, **kw):
     s = O.OracleSim(prob.shape, prob.h, gamma=prob.gamma, cfl=prob.cfl, rho_vac=prob.rho_vac,
                     bc=prob.bc, inflow=prob.inflow_list(), origin=prob.origin,
-                    **dict({"nu": prob.nu}, **kw))
+                    **dict({"nu": prob.nu, "grav": prob.grav}, **kw))
     s.set_primitive(prob.prim)
     s.set_potential(prob.psi)
     return s
