@@ -165,9 +165,12 @@ csph_status csph_totals(const csph_sim* sim, double out[5]);
  * which = 0..3 m*, E* (predictor, Eq. (5)); 4..6 xi* (predicted particle
  * offset); 7..10 m~, E~ (corrector, Eq. (6)); 11..13 xi^{n+1} (final particle
  * offset); 14 phi* = sqrt(2 p*) of the predicted particle, p* its pressure over
- * its predicted volume.  The offsets are kept by FP64 simulations only: the FP32 build
- * recomputes them from rho, m^n, m* and m~ where it needs them, and returns
- * CSPH_ERR_ARG for which = 4..6 and 11..13. */
+ * its predicted volume; 15 psi, the cell-centred potential of the step (with
+ * self-gravity: the external potential plus the gas's own of rho^n); 16 (with
+ * self-gravity only) the potential the corrector samples at r*: the external
+ * one plus that of the density predicted for t^{n+1}.  The offsets are kept by
+ * FP64 simulations only: the FP32 build recomputes them from rho, m^n, m* and
+ * m~ where it needs them, and returns CSPH_ERR_ARG for which = 4..6 and 11..13. */
 csph_status csph_get_stage(const csph_sim* sim, int32_t which, double* host_out);
 
 const char* csph_last_error(void);
@@ -178,7 +181,10 @@ const char* csph_last_error(void);
  * milliseconds of one launch and the number of launches timed since enabling:
  * group 0 = stage P (predictor), 1 = stage C (corrector), 2 = stage E (Eulerian
  * update), 3 = ghost fills (three launches per step, timed together), 4 = the
- * begin/end bookkeeping launches.  n is the capacity of both arrays (<= 5). */
+ * begin/end bookkeeping launches, 5 = self-gravity (the Poisson solve, the
+ * ghosts of its two potentials and the potential at r*, timed together per
+ * step; no launches without self-gravity).  n is the capacity of both arrays
+ * (<= 6). */
 csph_status csph_profile_enable(csph_sim* sim, int32_t on);
 csph_status csph_profile_read(csph_sim* sim, double* avg_ms, int64_t* launches, int32_t n);
 
@@ -208,6 +214,28 @@ csph_status csph_get_scheme(const csph_sim* sim, int32_t* limiter, int32_t* flux
  * step is further limited to nu dt <= h^2/4.  Applies from the next step.
  * CSPH_ERR_ARG for a negative or non-finite nu or a batch member. */
 csph_status csph_set_viscosity(csph_sim* sim, double nu);
+
+/* Self-gravity (Sec. 4 names the gas's self-gravity as an extension of the
+ * method) of a periodic box, with gravitational constant G > 0 (0 switches it
+ * off; it is off by default).  Each step the gas's potential is the solution of
+ * the 7-point discrete Poisson equation L7[psi] = 4 pi G (rho - mean rho),
+ * computed by a spectral solve on the device, and the potential the Lagrangian
+ * stage sees is the external one (csph_set_potential, zero if none) plus it: the
+ * predictor, Eq. (5), takes the potential of rho^n; the corrector, Eq. (6),
+ * which evaluates Q at the end of the step, takes that of the density the
+ * continuity equation predicts for t^{n+1},
+ * rho^n - dt sum_d (m_d,i+1 - m_d,i-1) / (2h), so the step stays second order
+ * in time.  Every axis length must be a power of two (up to 4096 in FP32, 2048
+ * in FP64; the fast path) or at most 1024 (a direct transform, for small grids).
+ * Switching it on allocates the solve's device memory (about 2 complex values
+ * per cell plus two fields; released when it is switched off or the sim is
+ * destroyed) and takes the mean density of the current state; applies from the
+ * next step.  CSPH_ERR_ARG for a negative or non-finite G, a face that is not
+ * PERIODIC, an unsupported axis length, a batch member or a static simulation
+ * (csph_create_static); CSPH_ERR_NOMEM if the allocation fails.  While it is on,
+ * csph_set_boundary refuses non-periodic kinds and csph_batch_add refuses the
+ * sim. */
+csph_status csph_set_self_gravity(csph_sim* sim, double G);
 
 /* Tile depth: the stencil sweeps give each workgroup a 32 x 8 tile of an x-y
  * plane and march it through tz planes along z.  Deeper tiles reuse more of the

@@ -30,6 +30,8 @@ UNITS = [
     ("csph_kernels.hip", "k32.o", ["-DCSPH_REAL=float", "-DCSPH_IS_DOUBLE=0", "-ffp-contract=on",
                                    "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
     ("csph_kernels.hip", "k64.o", ["-DCSPH_REAL=double", "-DCSPH_IS_DOUBLE=1", "-ffp-contract=off"]),
+    ("csph_gravity.hip", "g32.o", ["-DCSPH_REAL=float", "-DCSPH_IS_DOUBLE=0", "-ffp-contract=on"]),
+    ("csph_gravity.hip", "g64.o", ["-DCSPH_REAL=double", "-DCSPH_IS_DOUBLE=1", "-ffp-contract=off"]),
     ("csph_runtime.hip", "runtime.o", ["-ffp-contract=off"]),
     ("csph_stream.hip", "stream.o", []),
 ]

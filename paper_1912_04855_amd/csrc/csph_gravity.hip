@@ -1,0 +1,398 @@
+// csph_gravity.hip -- the Poisson solve of the gas's self-gravity for gfx950.
+//
+// The self-gravity extension (arXiv:1912.04855, Sec. 4) on a periodic box: the
+// gas's potential solves the 7-point discrete Poisson equation
+//   L7[psi] = 4 pi G (rho - mean rho),
+// which the discrete Fourier transform diagonalises with eigenvalues
+//   lambda(k) = sum_d (2 cos(2 pi k_d / n_d) - 2) / h^2.
+// Each step needs two potentials: that of rho^n (the predictor, Eq. (5)) and
+// that of the density the continuity equation predicts for t^{n+1},
+//   rho^ = rho^n - dt sum_d (m_d,i+1 - m_d,i-1) / (2h)
+// (the corrector, Eq. (6), evaluates Q at the end of the step).  Both are real
+// and the Green's function 4 pi G / lambda is real and even, so one complex
+// transform carries both: rho^n in the real part, rho^ in the imaginary part,
+// and after the multiply and the inverse transform the real part is the
+// potential of rho^n and the imaginary part that of rho^.
+//
+// This translation unit is compiled twice (CSPH_REAL = float and double).  One
+// solve is five launches over a complex work array [nz][ny][nx] (x fastest):
+//   x pass, forward : forms rho^n and rho^ from U^n (constant rho_ref taken off,
+//                     which the k = 0 mode discards anyway: it keeps the FP32
+//                     transform of a near-uniform density well conditioned)
+//   y pass, forward
+//   z pass          : forward, times 4 pi G / (lambda N), inverse
+//   y pass, inverse
+//   x pass, inverse : psi = psi_ext + Re, psi^ = psi_ext + Im, interior cells
+// Each launch owns W whole lines of one axis: it loads them into LDS (element e
+// of line w at e (W + 1) + w, so the walk along lines and the walk across them
+// are both free of bank conflicts), transforms them there and writes them back.
+// Power-of-two lengths use in-place radix-2 FFTs: decimation in time (input in
+// bit-reversed order, output natural) in the x and y passes; in the z pass
+// decimation in frequency forward (natural in, bit-reversed out), the multiply
+// in that order, and decimation in time back, so the z pass permutes nothing.
+// Other lengths use a direct DFT (O(n^2) per line: correct for any length, meant
+// for small grids).  Lines of the y and z passes are W
+// neighbouring x columns, so each element row of the tile is one contiguous
+// run of W complex values in memory.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "csph_internal.h"
+
+#ifndef CSPH_REAL
+#error "CSPH_REAL must be float or double"
+#endif
+
+#if CSPH_IS_DOUBLE
+#define CSPH_GTAG g64
+#else
+#define CSPH_GTAG g32
+#endif
+
+namespace csph {
+namespace CSPH_GTAG {
+
+using Real = CSPH_REAL;
+constexpr size_t kLdsMax = 65536;  // dynamic LDS of one workgroup
+using Real2 = typename std::conditional<std::is_same<Real, double>::value, double2, float2>::type;
+constexpr int NT = 256;
+
+__device__ __forceinline__ long long cell(const GridDev& g, int i, int j, int k) {
+  return ((long long)(k + kGhost) * g.sy + (j + kGhost)) * (long long)g.sx + (i + kGhost);
+}
+
+__device__ __forceinline__ int bit_reverse(int e, int log2n) {
+  return (int)(__builtin_bitreverse32((unsigned)e) >> (32 - log2n));
+}
+
+// which pass: the axis of the lines and what the loads and stores do
+enum Pass : int { kXFwd = 0, kYFwd = 1, kZ = 2, kYInv = 3, kXInv = 4 };
+
+struct Geom {
+  long long base;  // work-array index of element 0 of line 0 of this workgroup
+  long long es;    // stride between the elements of a line
+  long long ls;    // stride between neighbouring lines
+  int n;           // line length
+  int nl;          // lines of this workgroup (<= W; fewer at a ragged edge)
+  int axis;
+  int j, k;        // x pass: first line's (j, k); y pass: k; z pass: j
+  int i0;          // y and z passes: x of line 0
+};
+
+__device__ __forceinline__ Geom geom(const GridDev& g, int pass, int W) {
+  Geom q{};
+  const int b = blockIdx.x;
+  if (pass == kXFwd || pass == kXInv) {
+    const int lines = g.ny * g.nz;
+    const int l0 = b * W;
+    q.axis = 0;
+    q.n = g.nx;
+    q.nl = min(W, lines - l0);
+    q.base = (long long)l0 * g.nx;
+    q.es = 1;
+    q.ls = g.nx;
+    q.j = l0 % g.ny;
+    q.k = l0 / g.ny;
+    q.i0 = 0;
+  } else {
+    const int tiles_x = (g.nx + W - 1) / W;
+    const int tx = b % tiles_x, other = b / tiles_x;
+    q.i0 = tx * W;
+    q.nl = min(W, g.nx - q.i0);
+    q.ls = 1;
+    if (pass == kZ) {
+      q.axis = 2;
+      q.n = g.nz;
+      q.j = other;
+      q.base = (long long)other * g.nx + q.i0;
+      q.es = (long long)g.nx * g.ny;
+    } else {
+      q.axis = 1;
+      q.n = g.ny;
+      q.k = other;
+      q.base = (long long)other * g.nx * g.ny + q.i0;
+      q.es = g.nx;
+    }
+  }
+  return q;
+}
+
+// The tile holds W lines, element e of line w at e * P + w (P = W + 1).
+// tw[k] = (cos, sin) of 2 pi k / n; sg is the sign of the exponent (-1 forward,
+// +1 inverse).
+
+// radix-2 decimation in time, in place: bit-reversed input, natural output
+__device__ __forceinline__ void fft_dit(Real* re, Real* im, int n, int W, const Real* __restrict__ tw,
+                                        Real sg) {
+  const int P = W + 1;
+  for (int half = 1; half < n; half <<= 1) {
+    const int tstride = n / (2 * half);
+    for (int q = threadIdx.x; q < (n / 2) * W; q += NT) {
+      const int w = q % W, b = q / W;
+      const int pos = b & (half - 1);
+      const int i1 = 2 * (b - pos) + pos, i2 = i1 + half;
+      const Real cr = tw[2 * pos * tstride], ci = sg * tw[2 * pos * tstride + 1];
+      const int a1 = i1 * P + w, a2 = i2 * P + w;
+      const Real br = re[a2], bi = im[a2];
+      const Real tr = cr * br - ci * bi, ti = cr * bi + ci * br;
+      const Real ar = re[a1], ai = im[a1];
+      re[a2] = ar - tr;
+      im[a2] = ai - ti;
+      re[a1] = ar + tr;
+      im[a1] = ai + ti;
+    }
+    __syncthreads();
+  }
+}
+
+// radix-2 decimation in frequency, in place: natural input, bit-reversed output
+__device__ __forceinline__ void fft_dif(Real* re, Real* im, int n, int W, const Real* __restrict__ tw,
+                                        Real sg) {
+  const int P = W + 1;
+  for (int half = n / 2; half >= 1; half >>= 1) {
+    const int tstride = n / (2 * half);
+    for (int q = threadIdx.x; q < (n / 2) * W; q += NT) {
+      const int w = q % W, b = q / W;
+      const int pos = b & (half - 1);
+      const int i1 = 2 * (b - pos) + pos, i2 = i1 + half;
+      const Real cr = tw[2 * pos * tstride], ci = sg * tw[2 * pos * tstride + 1];
+      const int a1 = i1 * P + w, a2 = i2 * P + w;
+      const Real ar = re[a1], ai = im[a1], br = re[a2], bi = im[a2];
+      const Real dr = ar - br, di = ai - bi;
+      re[a1] = ar + br;
+      im[a1] = ai + bi;
+      re[a2] = cr * dr - ci * di;
+      im[a2] = cr * di + ci * dr;
+    }
+    __syncthreads();
+  }
+}
+
+// direct DFT of any length, through the scratch tile (xr, xi), natural order
+__device__ __forceinline__ void dft_direct(Real* re, Real* im, Real* xr, Real* xi, int n, int W,
+                                           const Real* __restrict__ tw, Real sg) {
+  const int P = W + 1;
+  for (int q = threadIdx.x; q < n * W; q += NT) {
+    const int w = q % W, k = q / W;
+    Real sr = 0, si = 0;
+    int idx = 0;  // (j k) mod n
+    for (int j = 0; j < n; ++j) {
+      const Real cr = tw[2 * idx], ci = sg * tw[2 * idx + 1];
+      const Real vr = re[j * P + w], vi = im[j * P + w];
+      sr += vr * cr - vi * ci;
+      si += vr * ci + vi * cr;
+      idx += k;
+      if (idx >= n) idx -= n;
+    }
+    xr[k * P + w] = sr;
+    xi[k * P + w] = si;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n * W; q += NT) {
+    const int w = q % W, k = q / W;
+    re[k * P + w] = xr[k * P + w];
+    im[k * P + w] = xi[k * P + w];
+  }
+  __syncthreads();
+}
+
+template <int kPass>
+__global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const Ctrl* __restrict__ ctrl,
+                                                Grav<Real> gr, int W) {
+  if (!ctrl->active) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const Geom q = geom(g, kPass, W);
+  const int P = W + 1;
+  const int n = q.n;
+  const int log2n = gr.log2n[q.axis];
+  Real* re = (Real*)lds_raw;
+  Real* im = re + (size_t)n * P;
+  Real* xr = im + (size_t)n * P;   // direct DFT only
+  Real* xi = xr + (size_t)n * P;
+  const Real* __restrict__ tw = gr.tw[q.axis];
+  Real2* __restrict__ cw = (Real2*)gr.cw;
+  const int t = threadIdx.x;
+  const int tile = n * W;
+  // the x and y passes load in bit-reversed order for the DIT transform
+  const bool rev = log2n >= 0 && kPass != kZ;
+
+  // ------------------------------------------------------------------- load
+  if constexpr (kPass == kXFwd) {
+    const int par = ctrl->par;
+    const Real* __restrict__ rho = F.U[par][0];
+    const Real* __restrict__ mx = F.U[par][1];
+    const Real* __restrict__ my = F.U[par][2];
+    const Real* __restrict__ mz = F.U[par][3];
+    const double dt = ctrl->dt;
+    const Real ref = (Real)gr.rho_ref;
+    const Real h2 = (Real)(2.0 * g.h);
+    for (int idx = t; idx < tile; idx += NT) {
+      const int w = idx / n, e = idx % n;
+      Real vr = 0, vi = 0;
+      if (w < q.nl) {
+        const int l = q.j + w;  // line index within the k plane may wrap to the next plane
+        const int jj = l % g.ny, kk = q.k + l / g.ny;
+        const long long c = cell(g, e, jj, kk);
+        const Real r = rho[c];
+        Real div = 0;
+        div += (mx[c + 1] - mx[c - 1]) / h2;
+        div += (my[c + g.sx] - my[c - g.sx]) / h2;
+        div += (mz[c + g.sxy] - mz[c - g.sxy]) / h2;
+        vr = r - ref;
+        vi = (r - (Real)dt * div) - ref;
+      }
+      const int s = rev ? bit_reverse(e, log2n) : e;
+      re[s * P + w] = vr;
+      im[s * P + w] = vi;
+    }
+  } else if constexpr (kPass == kXInv) {
+    for (int idx = t; idx < tile; idx += NT) {
+      const int w = idx / n, e = idx % n;
+      Real2 v;
+      v.x = 0;
+      v.y = 0;
+      if (w < q.nl) v = cw[q.base + (long long)w * q.ls + (long long)e * q.es];
+      const int s = rev ? bit_reverse(e, log2n) : e;
+      re[s * P + w] = v.x;
+      im[s * P + w] = v.y;
+    }
+  } else {
+    for (int idx = t; idx < tile; idx += NT) {
+      const int e = idx / W, w = idx % W;
+      Real2 v;
+      v.x = 0;
+      v.y = 0;
+      if (w < q.nl) v = cw[q.base + (long long)w * q.ls + (long long)e * q.es];
+      const int s = rev ? bit_reverse(e, log2n) : e;
+      re[s * P + w] = v.x;
+      im[s * P + w] = v.y;
+    }
+  }
+  __syncthreads();
+
+  // -------------------------------------------------------------- transform
+  constexpr bool kFwd = kPass == kXFwd || kPass == kYFwd;
+  if constexpr (kPass == kZ) {
+    // forward, times the Green's function 4 pi G / (lambda(k) N), inverse; slot
+    // s of a power-of-two line holds frequency bitrev(s) between the two
+    if (log2n >= 0)
+      fft_dif(re, im, n, W, tw, (Real)-1);
+    else
+      dft_direct(re, im, xr, xi, n, W, tw, (Real)-1);
+    for (int idx = t; idx < tile; idx += NT) {
+      const int s = idx / W, w = idx % W;
+      const int kz = log2n >= 0 ? bit_reverse(s, log2n) : s;
+      const int i = q.i0 + w;
+      Real f = 0;
+      if (w < q.nl && (i | q.j | kz) != 0) {
+        const double lam = gr.lam[0][i] + gr.lam[1][q.j] + gr.lam[2][kz];
+        f = (Real)(gr.fpg_n / lam);
+      }
+      re[s * P + w] *= f;
+      im[s * P + w] *= f;
+    }
+    __syncthreads();
+    if (log2n >= 0)
+      fft_dit(re, im, n, W, tw, (Real)1);
+    else
+      dft_direct(re, im, xr, xi, n, W, tw, (Real)1);
+  } else {
+    if (log2n >= 0)
+      fft_dit(re, im, n, W, tw, kFwd ? (Real)-1 : (Real)1);
+    else
+      dft_direct(re, im, xr, xi, n, W, tw, kFwd ? (Real)-1 : (Real)1);
+  }
+
+  // ------------------------------------------------------------------ store
+  if constexpr (kPass == kXFwd) {
+    for (int idx = t; idx < tile; idx += NT) {
+      const int w = idx / n, e = idx % n;
+      if (w < q.nl) {
+        Real2 v;
+        v.x = re[e * P + w];
+        v.y = im[e * P + w];
+        cw[q.base + (long long)w * q.ls + (long long)e * q.es] = v;
+      }
+    }
+  } else if constexpr (kPass == kXInv) {
+    const Real* __restrict__ pe = gr.psi_ext;
+    for (int idx = t; idx < tile; idx += NT) {
+      const int w = idx / n, e = idx % n;
+      if (w < q.nl) {
+        const int l = q.j + w;
+        const int jj = l % g.ny, kk = q.k + l / g.ny;
+        const long long c = cell(g, e, jj, kk);
+        const Real ext = pe[c];
+        F.psi[c] = ext + re[e * P + w];
+        gr.psih[c] = ext + im[e * P + w];
+      }
+    }
+  } else {
+    for (int idx = t; idx < tile; idx += NT) {
+      const int e = idx / W, w = idx % W;
+      if (w < q.nl) {
+        Real2 v;
+        v.x = re[e * P + w];
+        v.y = im[e * P + w];
+        cw[q.base + (long long)w * q.ls + (long long)e * q.es] = v;
+      }
+    }
+  }
+}
+
+}  // namespace CSPH_GTAG
+
+using CSPH_GTAG::Real;
+using namespace CSPH_GTAG;
+
+template <>
+size_t Poisson<Real>::lds_bytes(int n, int log2n, int W) {
+  const size_t tile = (size_t)n * (W + 1) * sizeof(Real);
+  return (log2n >= 0 ? 2 : 4) * tile;
+}
+
+template <>
+int Poisson<Real>::lines(int n, int log2n) {
+  // W * n complex values per tile; W capped so a y or z tile row stays one
+  // 128-byte run (16 FP32 or 8 FP64 complex values), and so the tile's LDS
+  // stays within 64 KiB
+  constexpr int cap = std::is_same<Real, double>::value ? 2048 : 4096;
+  constexpr int wmax = std::is_same<Real, double>::value ? 8 : 16;
+  int w = cap / n;
+  if (w > wmax) w = wmax;
+  if (w < 1) w = 1;
+  while (w > 1 && lds_bytes(n, log2n, w) > kLdsMax) --w;
+  return w;
+}
+
+template <>
+bool Poisson<Real>::length_ok(int n, int log2n) {
+  if (n < 1 || (log2n < 0 && n > 1024)) return false;
+  return lds_bytes(n, log2n, 1) <= kLdsMax;
+}
+
+template <>
+hipError_t Poisson<Real>::solve(const Fields<Real>& F, const GridDev& g, const Ctrl* ctrl,
+                                const Grav<Real>& gr, hipStream_t s) {
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int W[3];
+  size_t sh[3];
+  for (int a = 0; a < 3; ++a) {
+    W[a] = lines(n[a], gr.log2n[a]);
+    sh[a] = lds_bytes(n[a], gr.log2n[a], W[a]);
+  }
+  const unsigned bx = (unsigned)((g.ny * g.nz + W[0] - 1) / W[0]);
+  const unsigned by = (unsigned)(((g.nx + W[1] - 1) / W[1]) * g.nz);
+  const unsigned bz = (unsigned)(((g.nx + W[2] - 1) / W[2]) * g.ny);
+  k_poisson<kXFwd><<<bx, NT, sh[0], s>>>(F, g, ctrl, gr, W[0]);
+  k_poisson<kYFwd><<<by, NT, sh[1], s>>>(F, g, ctrl, gr, W[1]);
+  k_poisson<kZ><<<bz, NT, sh[2], s>>>(F, g, ctrl, gr, W[2]);
+  k_poisson<kYInv><<<by, NT, sh[1], s>>>(F, g, ctrl, gr, W[1]);
+  k_poisson<kXInv><<<bx, NT, sh[0], s>>>(F, g, ctrl, gr, W[0]);
+  return hipGetLastError();
+}
+
+template struct Poisson<Real>;
+
+}  // namespace csph

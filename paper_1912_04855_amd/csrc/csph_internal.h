@@ -91,6 +91,8 @@ struct Fields {
   Real* ms[4];   // m*x, m*y, m*z, E*
   Real* xs[3];   // xi*
   Real* psis;    // psi at the predicted particle positions r* = x + xi*
+  Real* psic;    // the potential the corrector samples at r*: psi, or with
+                 // self-gravity the potential of the density predicted for t^{n+1}
   Real* phs;     // phi* = sqrt(2 p*), p* the predicted particle's pressure at its predicted volume
   Real* mt[4];   // m~x, m~y, m~z, E~
   Real* xt[3];   // xi^{n+1}
@@ -116,6 +118,32 @@ struct FillSet {
   int n;
 };
 
+// Self-gravity of a periodic box: the buffers of the Poisson solve (device
+// memory) and its constants.
+template <typename Real>
+struct Grav {
+  Real* cw;              // work array, nx*ny*nz complex values (re, im), x fastest
+  Real* psi_ext;         // the external potential (padded layout; interior read)
+  Real* psih;            // potential of the predicted density (padded layout)
+  const Real* tw[3];     // per axis: (cos, sin) of 2 pi k / n_d, k < n_d
+  const double* lam[3];  // per axis: (2 cos(2 pi k / n_d) - 2) / h^2
+  int log2n[3];          // log2 of a power-of-two axis length, else -1
+  double fpg_n;          // 4 pi G / (nx ny nz)
+  double rho_ref;        // constant taken off the density before the transform
+};
+
+template <typename Real>
+struct Poisson {
+  // psi = psi_ext + potential of rho^n and psih = psi_ext + potential of the
+  // density predicted for t^{n+1} (interior cells; ghosts are left), from U^n
+  // and the step's dt; five launches on s, skipped when the step is inactive
+  static hipError_t solve(const Fields<Real>& F, const GridDev& g, const Ctrl* ctrl,
+                          const Grav<Real>& gr, hipStream_t s);
+  static bool length_ok(int n, int log2n);  // an axis length the solve supports
+  static int lines(int n, int log2n);       // lines per workgroup of an axis pass
+  static size_t lds_bytes(int n, int log2n, int W);
+};
+
 // launchers, instantiated for float and double by the kernel translation units
 template <typename Real>
 struct Launch {
@@ -126,11 +154,14 @@ struct Launch {
                              Ctrl* ctrl, hipStream_t s);
   static hipError_t signal_max(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
                                hipStream_t s);
-  // one full step: begin, ghosts, stage P, ghosts, stage C, ghosts, stage E, end
-  // ev (nullable): 8 events recorded around the launches, for kernel timing
+  // one full step: begin, ghosts, [self-gravity potentials], stage P, [psi of
+  // the predicted density at r*], ghosts, stage C, ghosts, stage E, end
+  // gr (nullable): the self-gravity solve; ev (nullable): kStepEvents events
+  // recorded around the launches, for kernel timing
+  static constexpr int kStepEvents = 10;
   static hipError_t step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
-                         double* partials, double dt_max, double t_end, const int tz[3], hipStream_t s,
-                         hipEvent_t* ev);
+                         double* partials, double dt_max, double t_end, const int tz[3],
+                         const Grav<Real>* gr, hipStream_t s, hipEvent_t* ev);
   // one step of every active member of a batch, one launch per stage
   // tile_map[t] = (member, tile of that member); fill_map[b] = (member, first
   // ghost cell of fill block b); generic: some member uses a non-default scheme

@@ -465,9 +465,38 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
     xi_star(un, us, (Real)(0.5 * dt), xi);
   }
   {
-    const Real* P = F.psi;
+    const Real* P = F.psic;
     auto at = [&](int a, int b, int c) { return P[cg + a + (long long)b * g.sx + (long long)c * g.sxy]; };
     F.psis[cg] = psi_at(g, at, xi[0], xi[1], xi[2]);
+  }
+}
+
+// self-gravity: psi at r* of the interior particles from the potential of the
+// density predicted for t^{n+1} (F.psic), replacing the value stage P took from
+// the potential of rho^n; r* as the ghost fill forms it
+__global__ void __launch_bounds__(256) k_psis_grav(Fields<Real> F, GridDev g, const Ctrl* __restrict__ ctrl) {
+  if (!ctrl->active) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const double dt = ctrl->dt;
+  const int par = ctrl->par;
+  for (int k = blockIdx.z; k < g.nz; k += gridDim.z) {
+    const long long c = cell(g, i, j, k);
+    Real xi[3];
+    if constexpr (kKeepXiStar) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) xi[q] = F.xs[q][c];
+    } else {
+      const Real r = F.U[par][0][c];
+      Real un[3], us[3];
+      velocity(g, r, F.U[par][1][c], F.U[par][2][c], F.U[par][3][c], un);
+      velocity(g, r, F.ms[0][c], F.ms[1][c], F.ms[2][c], us);
+      xi_star(un, us, (Real)(0.5 * dt), xi);
+    }
+    const Real* P = F.psic;
+    auto at = [&](int a, int b, int cc) { return P[c + a + (long long)b * g.sx + (long long)cc * g.sxy]; };
+    F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
   }
 }
 
@@ -1699,7 +1728,7 @@ hipError_t Launch<Real>::signal_max(const Fields<Real>& F, const GridDev& g, Ctr
 template <>
 hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcDev& bc, Ctrl* ctrl,
                               double* partials, double dt_max, double t_end, const int tz[3],
-                              hipStream_t s, hipEvent_t* ev) {
+                              const Grav<Real>* gr, hipStream_t s, hipEvent_t* ev) {
   const long long ng = ghost_count(g);
   const unsigned gb = (unsigned)((ng + 255) / 256);
   // each stage has its own tile depth
@@ -1712,23 +1741,37 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
   k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(1);
+  if (gr) {
+    // the potentials of rho^n and of the predicted density, then their ghosts
+    hipError_t e = Poisson<Real>::solve(F, g, ctrl, *gr, s);
+    if (e != hipSuccess) return e;
+    FillSet<Real> fs{};
+    fs.f[0] = F.psi;
+    fs.f[1] = gr->psih;
+    fs.role[0] = fs.role[1] = kPsi;
+    fs.n = 2;
+    k_fill<<<gb, 256, 0, s>>>(fs, g, bc, ctrl, 1);
+  }
+  mark(2);
   if (g.nu > 0.0) k_stage_p<true><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
   else k_stage_p<false><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
-  mark(2);
-  k_fill_pred<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(3);
+  if (gr) k_psis_grav<<<cell_grid(g), dim3(64, 4), 0, s>>>(F, g, ctrl);
+  mark(4);
+  k_fill_pred<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
+  mark(5);
   if (g.nu > 0.0) k_stage_c<true><<<nbc, NT, 0, s>>>(F, g, bc, ctrl, tz[1]);
   else k_stage_c<false><<<nbc, NT, 0, s>>>(F, g, bc, ctrl, tz[1]);
-  mark(4);
+  mark(6);
   k_fill_corr<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
-  mark(5);
+  mark(7);
   if (default_scheme(g))
     k_stage_e<false><<<nbe, NT, 0, s>>>(F, g, bc, ctrl, partials, tz[2]);
   else
     k_stage_e<true><<<nbe, NT, 0, s>>>(F, g, bc, ctrl, partials, tz[2]);
-  mark(6);
+  mark(8);
   k_end<<<1, 64, 0, s>>>(ctrl);
-  mark(7);
+  mark(9);
   return hipGetLastError();
 }
 

@@ -243,10 +243,18 @@ struct csph_sim {
   // kernel timing: events of up to kProfSteps steps in flight, accumulated at syncs
   static constexpr int kProfSteps = 64;
   bool prof_on = false;
-  std::vector<hipEvent_t> prof_ev;  // kProfSteps x 8
+  static constexpr int kEv = Launch<float>::kStepEvents;
+  std::vector<hipEvent_t> prof_ev;  // kProfSteps x kEv
   int prof_pending = 0;
-  double prof_ms[5] = {0, 0, 0, 0, 0};
-  int64_t prof_n[5] = {0, 0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_n[6] = {0, 0, 0, 0, 0, 0};
+  // self-gravity (periodic box): G, and the Poisson solve's own device memory
+  // (work array, external potential, potential of the predicted density,
+  // twiddle and eigenvalue tables), allocated when it is switched on
+  double grav = 0.0;
+  char* gbuf = nullptr;
+  Grav<float> gr32{};
+  Grav<double> gr64{};
 
   bool is_f64() const { return desc.dtype == CSPH_F64; }
   char* field_ptr(int k) const { return buf + L.fields_off + (size_t)k * L.field_bytes; }
@@ -281,6 +289,7 @@ void bind_fields(csph_sim* s, Fields<Real>& F) {
   for (int v = 0; v < 4; ++v) F.ms[v] = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 3; ++v) F.xs[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
   F.psis = (Real*)s->field_ptr(k++);
+  F.psic = F.psi;
   F.phs = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 4; ++v) F.mt[v] = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 3; ++v) F.xt[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
@@ -355,6 +364,13 @@ template <>
 Fields<double>& fields_of<double>(csph_sim* s) { return s->f64; }
 
 template <typename Real>
+Grav<Real>& grav_of(csph_sim* s);
+template <>
+Grav<float>& grav_of<float>(csph_sim* s) { return s->gr32; }
+template <>
+Grav<double>& grav_of<double>(csph_sim* s) { return s->gr64; }
+
+template <typename Real>
 csph_status set_state_t(csph_sim* s, const double* cons) {
   Fields<Real>& F = fields_of<Real>(s);
   const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
@@ -393,16 +409,19 @@ csph_status prof_collect(csph_sim* s) {
   if (!s->prof_on || s->prof_pending == 0) return CSPH_OK;
   HIP_TRY(hipStreamSynchronize(s->stream));
   for (int k = 0; k < s->prof_pending; ++k) {
-    hipEvent_t* e = &s->prof_ev[(size_t)k * 8];
-    float ms[7];
-    for (int q = 0; q < 7; ++q) HIP_TRY(hipEventElapsedTime(&ms[q], e[q], e[q + 1]));
-    // e0-e1 begin + state fill, e1-e2 P, e2-e3 fill, e3-e4 C, e4-e5 fill, e5-e6 E, e6-e7 end
-    s->prof_ms[0] += ms[1];
-    s->prof_ms[1] += ms[3];
-    s->prof_ms[2] += ms[5];
-    s->prof_ms[3] += ms[0] + ms[2] + ms[4];
-    s->prof_ms[4] += ms[6];
+    hipEvent_t* e = &s->prof_ev[(size_t)k * csph_sim::kEv];
+    float ms[csph_sim::kEv - 1];
+    for (int q = 0; q < csph_sim::kEv - 1; ++q) HIP_TRY(hipEventElapsedTime(&ms[q], e[q], e[q + 1]));
+    // e0-e1 begin + state fill, e1-e2 Poisson solve, e2-e3 P, e3-e4 psi at r*
+    // (self-gravity), e4-e5 fill, e5-e6 C, e6-e7 fill, e7-e8 E, e8-e9 end
+    s->prof_ms[0] += ms[2];
+    s->prof_ms[1] += ms[5];
+    s->prof_ms[2] += ms[7];
+    s->prof_ms[3] += ms[0] + ms[4] + ms[6];
+    s->prof_ms[4] += ms[8];
+    s->prof_ms[5] += ms[1] + ms[3];
     for (int q = 0; q < 5; ++q) s->prof_n[q] += 1;
+    if (s->grav > 0.0) s->prof_n[5] += 1;
   }
   s->prof_pending = 0;
   return CSPH_OK;
@@ -420,11 +439,12 @@ csph_status launch_steps(csph_sim* s, int n, double dt_max, double t_end) {
         st = prof_collect(s);
         if (st) return st;
       }
-      ev = &s->prof_ev[(size_t)s->prof_pending * 8];
+      ev = &s->prof_ev[(size_t)s->prof_pending * csph_sim::kEv];
       s->prof_pending += 1;
     }
-    HIP_TRY(Launch<Real>::step(F, s->g, s->bc, s->ctrl, s->partials, dt_max, t_end, s->tz, s->stream,
-                               ev));
+    const Grav<Real>* gr = s->grav > 0.0 ? &grav_of<Real>(s) : nullptr;
+    HIP_TRY(Launch<Real>::step(F, s->g, s->bc, s->ctrl, s->partials, dt_max, t_end, s->tz, gr,
+                               s->stream, ev));
   }
   s->stepped = true;
   s->tz_last = s->tz[2];
@@ -434,6 +454,122 @@ csph_status launch_steps(csph_sim* s, int n, double dt_max, double t_end) {
 csph_status launch(csph_sim* s, int n, double dt_max, double t_end) {
   return s->is_f64() ? launch_steps<double>(s, n, dt_max, t_end)
                   : launch_steps<float>(s, n, dt_max, t_end);
+}
+
+// self-gravity: the constant taken off the density before the transform (the
+// mean density of the state; mass is conserved on the periodic box)
+void set_rho_ref(csph_sim* s, const double* cons) {
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  double a = 0.0;
+  for (size_t q = 0; q < N; ++q) a += cons[q];
+  s->gr32.rho_ref = s->gr64.rho_ref = a / (double)N;
+}
+
+int log2_exact(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return (1 << l) == n ? l : -1;
+}
+
+// allocate and fill the Poisson solve's buffers and tables (once per sim)
+template <typename Real>
+csph_status grav_setup(csph_sim* s) {
+  Grav<Real>& gr = grav_of<Real>(s);
+  const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
+  const size_t N = (size_t)n[0] * n[1] * n[2];
+  size_t off_tw[3], off_lam[3];
+  size_t total = align_up(N * 2 * sizeof(Real));  // work array
+  const size_t off_ext = total;
+  total += s->L.field_bytes;
+  const size_t off_psih = total;
+  total += s->L.field_bytes;
+  for (int a = 0; a < 3; ++a) {
+    off_tw[a] = total;
+    total += align_up((size_t)n[a] * 2 * sizeof(Real));
+    off_lam[a] = total;
+    total += align_up((size_t)n[a] * sizeof(double));
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CSPH_ERR_NOMEM, "hipMalloc of the self-gravity buffers failed");
+  }
+  s->gbuf = (char*)p;
+  HIP_TRY(hipMemsetAsync(s->gbuf, 0, total, s->stream));
+  const double kPi = 3.14159265358979323846;
+  const double h2 = s->g.h * s->g.h;
+  for (int a = 0; a < 3; ++a) {
+    std::vector<Real> tw((size_t)n[a] * 2);
+    std::vector<double> lam((size_t)n[a]);
+    for (int k = 0; k < n[a]; ++k) {
+      const double ang = 2.0 * kPi * k / n[a];
+      tw[2 * (size_t)k] = (Real)std::cos(ang);
+      tw[2 * (size_t)k + 1] = (Real)std::sin(ang);
+      lam[k] = (2.0 * std::cos(ang) - 2.0) / h2;
+    }
+    HIP_TRY(hipMemcpyAsync(s->gbuf + off_tw[a], tw.data(), tw.size() * sizeof(Real), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(s->gbuf + off_lam[a], lam.data(), lam.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    gr.tw[a] = (const Real*)(s->gbuf + off_tw[a]);
+    gr.lam[a] = (const double*)(s->gbuf + off_lam[a]);
+    gr.log2n[a] = log2_exact(n[a]);
+  }
+  gr.cw = (Real*)s->gbuf;
+  gr.psi_ext = (Real*)(s->gbuf + off_ext);
+  gr.psih = (Real*)(s->gbuf + off_psih);
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status grav_on(csph_sim* s, double G) {
+  if (!s->gbuf) {
+    csph_status st = grav_setup<Real>(s);
+    if (st) return st;
+  }
+  Grav<Real>& gr = grav_of<Real>(s);
+  Fields<Real>& F = fields_of<Real>(s);
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  gr.fpg_n = 4.0 * 3.14159265358979323846 * G / (double)N;
+  // the mean density of the current state
+  Ctrl c{};
+  csph_status st = read_ctrl(s, &c);
+  if (st) return st;
+  std::vector<double> rho(N);
+  st = download_field<Real>(s, F.U[c.par][0], rho.data());
+  if (st) return st;
+  set_rho_ref(s, rho.data());
+  // the external potential as set (zero if none)
+  std::vector<double> ext(N, 0.0);
+  if (s->has_psi) ext = s->psi_host;
+  st = upload_field<Real>(s, gr.psi_ext, ext.data());
+  if (st) return st;
+  F.psic = gr.psih;
+  s->g.psi = 1;
+  s->grav = G;
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status grav_off(csph_sim* s) {
+  Fields<Real>& F = fields_of<Real>(s);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->grav = 0.0;
+  F.psic = F.psi;
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  std::vector<double> ext(N, 0.0);
+  if (s->has_psi) ext = s->psi_host;
+  csph_status st = upload_field<Real>(s, F.psi, ext.data());
+  if (st) return st;
+  if (!s->has_psi) HIP_TRY(hipMemsetAsync(F.psis, 0, s->L.field_bytes, s->stream));
+  s->g.psi = s->has_psi ? 1 : 0;
+  s->psi_dirty = true;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  (void)hipFree(s->gbuf);
+  s->gbuf = nullptr;
+  grav_of<Real>(s) = Grav<Real>{};
+  return CSPH_OK;
 }
 
 bool periodic_pairs_ok(const csph_sim* s) {
@@ -580,6 +716,7 @@ csph_status csph_destroy(csph_sim* s) {
   (void)hipStreamSynchronize(s->stream);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->owned) (void)hipFree(s->buf);
+  if (s->gbuf) (void)hipFree(s->gbuf);
   if (s->in_static) {
     std::lock_guard<std::mutex> lk(g_static_mu);
     const int dev = s->device;
@@ -625,6 +762,7 @@ csph_status csph_set_state(csph_sim* s, csph_vars vars, const double* host) {
   }
   csph_status st = s->is_f64() ? set_state_t<double>(s, src) : set_state_t<float>(s, src);
   if (st) return st;
+  if (s->grav > 0.0) set_rho_ref(s, src);
   Ctrl c{};
   Ctrl old{};
   st = read_ctrl(s, &old);
@@ -651,6 +789,14 @@ csph_status csph_set_potential(csph_sim* s, const double* host_psi) {
   csph_status st = s->is_f64() ? upload_field<double>(s, s->f64.psi, s->psi_host.data())
                             : upload_field<float>(s, s->f32.psi, s->psi_host.data());
   if (st) return st;
+  if (s->grav > 0.0) {
+    // self-gravity: this is the external part; the step adds the gas's own
+    st = s->is_f64() ? upload_field<double>(s, s->gr64.psi_ext, s->psi_host.data())
+                     : upload_field<float>(s, s->gr32.psi_ext, s->psi_host.data());
+    if (st) return st;
+    s->psi_dirty = true;
+    return CSPH_OK;
+  }
   if (!host_psi && s->g.psi) {
     // without a potential the kernels leave psi(r*) alone: it must be 0 everywhere
     void* f = s->is_f64() ? (void*)s->f64.psis : (void*)s->f32.psis;
@@ -666,6 +812,8 @@ csph_status csph_set_boundary(csph_sim* s, int32_t face, csph_bc kind, const dou
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   if (face < 0 || face > 5) return fail(CSPH_ERR_ARG, "face must be 0..5");
   if (kind < CSPH_PERIODIC || kind > CSPH_REFLECT) return fail(CSPH_ERR_ARG, "bad boundary kind");
+  if (s->grav > 0.0 && kind != CSPH_PERIODIC)
+    return fail(CSPH_ERR_ARG, "self-gravity needs a periodic box: switch it off first");
   s->bc.kind[face] = (int)kind;
   if (kind == CSPH_INFLOW) {
     if (!inflow_prim) return fail(CSPH_ERR_ARG, "inflow state required");
@@ -824,7 +972,13 @@ csph_status csph_totals(const csph_sim* s, double out[5]) {
 
 csph_status csph_get_stage(const csph_sim* s, int32_t which, double* out) {
   if (!s || !out) return fail(CSPH_ERR_ARG, "sim or output is NULL");
-  if (which < 0 || which > 14) return fail(CSPH_ERR_ARG, "which must be 0..14");
+  if (which < 0 || which > 16) return fail(CSPH_ERR_ARG, "which must be 0..16");
+  if (which == 15)
+    return s->is_f64() ? download_field<double>(s, s->f64.psi, out) : download_field<float>(s, s->f32.psi, out);
+  if (which == 16) {
+    if (!(s->grav > 0.0)) return fail(CSPH_ERR_ARG, "the potential of the predicted density needs self-gravity");
+    return s->is_f64() ? download_field<double>(s, s->gr64.psih, out) : download_field<float>(s, s->gr32.psih, out);
+  }
   if (which == 14)
     return s->is_f64() ? download_field<double>(s, s->f64.phs, out) : download_field<float>(s, s->f32.phs, out);
   if (s->is_f64()) {
@@ -841,7 +995,7 @@ csph_status csph_get_stage(const csph_sim* s, int32_t which, double* out) {
 csph_status csph_profile_enable(csph_sim* s, int32_t on) {
   if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
   if (on && s->prof_ev.empty()) {
-    s->prof_ev.resize((size_t)csph_sim::kProfSteps * 8);
+    s->prof_ev.resize((size_t)csph_sim::kProfSteps * csph_sim::kEv);
     for (auto& e : s->prof_ev) HIP_TRY(hipEventCreate(&e));
   }
   if (!on) {
@@ -849,7 +1003,7 @@ csph_status csph_profile_enable(csph_sim* s, int32_t on) {
     if (st) return st;
   }
   s->prof_on = on != 0;
-  for (int q = 0; q < 5; ++q) {
+  for (int q = 0; q < 6; ++q) {
     s->prof_ms[q] = 0.0;
     s->prof_n[q] = 0;
   }
@@ -858,7 +1012,7 @@ csph_status csph_profile_enable(csph_sim* s, int32_t on) {
 }
 
 csph_status csph_profile_read(csph_sim* s, double* avg_ms, int64_t* launches, int32_t n) {
-  if (!s || n < 0 || n > 5) return fail(CSPH_ERR_ARG, "bad arguments");
+  if (!s || n < 0 || n > 6) return fail(CSPH_ERR_ARG, "bad arguments");
   csph_status st = prof_collect(s);
   if (st) return st;
   for (int q = 0; q < n; ++q) {
@@ -885,6 +1039,30 @@ csph_status csph_set_viscosity(csph_sim* s, double nu) {
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
   set_viscosity(s->g, nu);
   return CSPH_OK;
+}
+
+csph_status csph_set_self_gravity(csph_sim* s, double G) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (!(G >= 0.0) || !std::isfinite(G)) return fail(CSPH_ERR_ARG, "G must be finite and >= 0");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
+  if (G == 0.0) {
+    if (!(s->grav > 0.0)) return CSPH_OK;
+    return s->is_f64() ? grav_off<double>(s) : grav_off<float>(s);
+  }
+  for (int f = 0; f < 6; ++f)
+    if (s->bc.kind[f] != kPeriodic) return fail(CSPH_ERR_ARG, "self-gravity needs PERIODIC on all six faces");
+  if (s->in_static && !s->gbuf)
+    return fail(CSPH_ERR_ARG, "self-gravity allocates its own device memory: not available to a static simulation");
+  const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
+  for (int a = 0; a < 3; ++a) {
+    const int l = log2_exact(n[a]);
+    const bool ok = s->is_f64() ? Poisson<double>::length_ok(n[a], l) : Poisson<float>::length_ok(n[a], l);
+    if (!ok)
+      return fail(CSPH_ERR_ARG, "self-gravity: axis length " + std::to_string(n[a]) +
+                                    " unsupported (a power of two up to 4096 in FP32 and 2048 in FP64, "
+                                    "or any length up to 1024)");
+  }
+  return s->is_f64() ? grav_on<double>(s, G) : grav_on<float>(s, G);
 }
 
 csph_status csph_get_scheme(const csph_sim* s, int32_t* limiter, int32_t* flux) {
@@ -1271,6 +1449,7 @@ csph_status csph_batch_add(csph_batch* b, csph_sim* s, int64_t steps, double t_e
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim already belongs to a batch");
   if (steps < 0 || std::isnan(t_end)) return fail(CSPH_ERR_ARG, "bad steps or t_end");
   if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
+  if (s->grav > 0.0) return fail(CSPH_ERR_ARG, "a self-gravitating sim cannot join a batch");
   const size_t need = s->L.total;
   if (b->budget && b->used_bytes + need > b->budget) return fail(CSPH_ERR_BUDGET, "HBM budget exceeded");
   Ctrl c{};

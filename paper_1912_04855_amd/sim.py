@@ -190,6 +190,10 @@ class Sim:
         """Uniform kinematic viscosity of the Lagrangian stage (0: inviscid)."""
         check(_lib.load().csph_set_viscosity(self._h, float(nu)), "csph_set_viscosity")
 
+    def set_self_gravity(self, G):
+        """Self-gravity of the periodic box with constant G (0: off)."""
+        check(_lib.load().csph_set_self_gravity(self._h, float(G)), "csph_set_self_gravity")
+
     def scheme(self):
         lim, flux = C.c_int32(), C.c_int32()
         check(_lib.load().csph_get_scheme(self._h, C.byref(lim), C.byref(flux)), "csph_get_scheme")
@@ -223,7 +227,7 @@ class Sim:
         return tuple(int(v) for v in tz), ms.value
 
     STAGE_FIELDS = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz",
-                    "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "phis"]
+                    "mtx", "mty", "mtz", "Et", "xtx", "xty", "xtz", "phis", "psi", "psih"]
 
     def stage(self, name) -> np.ndarray:
         out = np.empty(self.shape)
@@ -242,6 +246,8 @@ def from_problem(prob, dtype="f64", torch=False, stream=None) -> Sim:
     s.set_primitive(prob.prim)
     if prob.nu:
         s.set_viscosity(prob.nu)
+    if prob.grav:
+        s.set_self_gravity(prob.grav)
     return s
 
 

@@ -1,0 +1,207 @@
+"""Self-gravity (the Sec. 4 extension) on the GPU against the oracle.
+
+The GPU solves the periodic Poisson equation with its own FFT kernels (power-of-
+two axes) or direct transforms (other lengths); the oracle with plain per-axis
+DFT sums.  The two agree to rounding, not to the bit, so the FP64 bars are
+relative (1e-12 on one step's fields: the transforms' rounding is ~1e-15 of the
+potential; 1e-10 after 100 steps).  FP32 runs the same transforms in FP32 with
+the mean density taken off first.  Properties checked at the benchmark size,
+where the oracle's O(n^2) transforms would be slow: the discrete Poisson
+residual of the GPU's potential, and its closed form for a density of modes
+that share one eigenvalue, cell by cell."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+from paper_1912_04855_amd import _lib
+from paper_1912_04855_amd import problems as P
+
+from gpu_common import announce, gpu_sim, need_gpu, rel_l1, rel_l1_vars
+from helpers import oracle_sim
+
+pytestmark = pytest.mark.gpu
+
+STAGES = ["msx", "msy", "msz", "Es", "xsx", "xsy", "xsz", "phis", "mtx", "mty", "mtz", "Et",
+          "xtx", "xty", "xtz", "psi", "psih"]
+
+
+def _random(shape, seed=21, G=0.8):
+    pr = P.random_state(shape, seed=seed, potential=True)
+    pr.grav = G
+    return pr
+
+
+def _residual(psi, rho, h, G):
+    lap = sum((np.roll(psi, 1, ax) + np.roll(psi, -1, ax) - 2 * psi) / h ** 2 for ax in range(3))
+    src = 4 * math.pi * G * (rho - rho.mean())
+    return float(np.max(np.abs(lap - src)) / np.max(np.abs(src)))
+
+
+# (12, 10, 6): direct transforms on every axis; (16, 8, 32): FFTs on every axis
+# with several lines per workgroup; (32, 12, 8): both kinds; (64, 4, 4) ragged
+# line groups of the x pass
+SHAPES = [(12, 10, 6), (16, 8, 32), (32, 12, 8), (64, 4, 4)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gravity_one_step_stages_fp64(shape):
+    need_gpu()
+    pr = _random(shape)
+    o = oracle_sim(pr)
+    dto = o.step()
+    announce("gravity_one_step_fp64", shape)
+    g = gpu_sim(pr, "f64")
+    dtg = g.step()
+    assert dtg == dto
+    for f in STAGES:
+        a, b = g.stage(f), o.field(f)
+        scale = max(np.max(np.abs(b)), 1e-300)
+        assert np.max(np.abs(a - b)) <= 1e-12 * scale, f
+    assert rel_l1_vars(g.conserved(), o.conserved()) <= 1e-13
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["random", "jeans"])
+def test_gravity_many_steps_fp64(name):
+    need_gpu()
+    if name == "random":
+        pr = _random((16, 12, 8), seed=4, G=0.5)
+    else:
+        pr = P.jeans_wave(32, 2 * math.pi, delta=1e-3)
+    o = oracle_sim(pr)
+    for _ in range(100):
+        o.step()
+    announce("gravity_many_steps_fp64", name, pr.shape)
+    g = gpu_sim(pr, "f64")
+    assert g.advance(math.inf, 100) == 100
+    Ug, Uo = g.conserved(), o.conserved()
+    if name == "jeans":
+        # the wave runs along x: the transverse momenta are rounding noise on both
+        # sides, measured against the wave's own momentum
+        err = rel_l1_vars(Ug[[0, 1, 4]], Uo[[0, 1, 4]])
+        assert np.max(np.abs(Ug[2:4] - Uo[2:4])) <= 1e-12 * np.max(np.abs(Uo[1]))
+    else:
+        err = rel_l1_vars(Ug, Uo)
+    print(f"gravity {name}: FP64 relative L1 vs oracle after 100 steps = {err:.3e}")
+    assert err <= 1e-10
+    assert g.time()[0] == pytest.approx(o.time()[0], rel=1e-12)
+    g.close()
+
+
+@pytest.mark.parametrize("G", [math.pi / 2, 2 * math.pi])
+def test_jeans_wave_fp32(G):
+    need_gpu()
+    n, delta, t_end = 64, 1e-3, 0.5
+    pr = P.jeans_wave(n, G, delta=delta, t_end=t_end)
+    o = oracle_sim(pr)
+    o.advance(t_end)
+    announce("jeans_fp32", G)
+    g = gpu_sim(pr, "f32")
+    g.advance(t_end)
+    assert g.time()[0] == t_end
+    Ug, Uo = g.conserved(), o.conserved()
+    x = (np.arange(n) + 0.5) / n
+    amp = [2 * np.mean((U[0] - 1.0)[0, 0] * np.cos(2 * math.pi * x)) / delta for U in (Ug, Uo)]
+    w2 = (2 * math.pi) ** 2 - 4 * math.pi * G
+    exact = math.cos(math.sqrt(w2) * t_end) if w2 > 0 else math.cosh(math.sqrt(-w2) * t_end)
+    drho = rel_l1(Ug[0] - 1.0, Uo[0] - 1.0)
+    print(f"Jeans FP32 G={G:.4f}: amplitude GPU {amp[0]:.6f} oracle {amp[1]:.6f} linear theory "
+          f"{exact:.6f}; relative L1 of rho - 1: {drho:.2e}")
+    # FP32 holds rho = 1 + 1e-3 s to ~6e-5 of the perturbation
+    assert abs(amp[0] - amp[1]) <= 2e-3 * abs(amp[1])
+    assert drho <= 2e-3
+    assert abs(amp[0] - exact) <= 0.02 * abs(exact)
+    g.close()
+
+
+@pytest.mark.parametrize("n,dtype", [(256, "f32"), (128, "f64")])
+def test_potential_at_size(n, dtype):
+    # the benchmark's grid.  The seeded smooth density is 1 plus a product of one
+    # sine or cosine per axis of wavenumber 2 pi: a sum of the eight Fourier
+    # modes (+-1, +-1, +-1), which share one eigenvalue of the 7-point Laplacian,
+    # lambda = 3 (2 cos(2 pi / n) - 2) / h^2, and the mean density is 1.  So the
+    # gas's potential is 4 pi G (rho - 1) / lambda, cell by cell.
+    need_gpu()
+    pr = P.smooth_state((n, n, n), seed=3)
+    pr.grav = 1.0
+    rho0 = pr.prim[0].copy()
+    announce("potential_at_size", n, dtype)
+    g = gpu_sim(pr, dtype)
+    g.step()
+    self_part = g.stage("psi") - pr.psi
+    lam = 3 * (2 * math.cos(2 * math.pi / n) - 2) / pr.h ** 2
+    exact = 4 * math.pi * pr.grav * (rho0 - 1.0) / lam
+    err = float(np.max(np.abs(self_part - exact)) / np.max(np.abs(exact)))
+    print(f"self potential {n}^3 {dtype}: max error / max |psi| = {err:.2e}")
+    assert err <= (2e-5 if dtype == "f32" else 1e-12)
+    if dtype == "f64":
+        assert _residual(self_part, rho0, pr.h, pr.grav) <= 1e-10
+    g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_switching_off_restores_the_external_potential(dtype):
+    need_gpu()
+    pr = _random((16, 8, 8), seed=9)
+    announce("gravity_off", dtype)
+    a = gpu_sim(pr, dtype)
+    a.set_self_gravity(0.0)
+    pr0 = _random((16, 8, 8), seed=9, G=0.0)
+    b = gpu_sim(pr0, dtype)
+    for s in (a, b):
+        assert s.advance(math.inf, 5) == 5
+    assert np.array_equal(a.conserved(), b.conserved())
+    a.close()
+    b.close()
+
+
+def test_gravity_refusals():
+    need_gpu()
+    from paper_1912_04855_amd.sim import Batch, Sim
+    announce("gravity_refusals")
+    pr = _random((16, 8, 8))
+    g = gpu_sim(pr, "f32")
+    with pytest.raises(_lib.CsphError):
+        g.set_boundary(0, P.REFLECT)
+    with pytest.raises(_lib.CsphError):
+        g.set_self_gravity(-1.0)
+    b = Batch("f32")
+    with pytest.raises(_lib.CsphError):
+        b.add(g, 3)
+    b.close()
+    g.close()
+    # a non-periodic box, and an axis length beyond the direct transform's
+    pr = _random((16, 8, 8), G=0.0)
+    s = gpu_sim(pr, "f32")
+    s.set_boundary(0, P.REFLECT)
+    s.set_boundary(1, P.REFLECT)
+    with pytest.raises(_lib.CsphError):
+        s.set_self_gravity(1.0)
+    s.close()
+    s = Sim((1030, 4, 4), 1.0 / 1030, dtype="f32")
+    with pytest.raises(_lib.CsphError):
+        s.set_self_gravity(1.0)
+    s.close()
+    # the static array: the solve would allocate
+    s = Sim((16, 8, 8), 1.0 / 16, dtype="f32", static=True)
+    with pytest.raises(_lib.CsphError):
+        s.set_self_gravity(1.0)
+    s.close()
+
+
+def test_profile_has_a_gravity_group():
+    need_gpu()
+    pr = _random((32, 32, 32))
+    announce("gravity_profile")
+    g = gpu_sim(pr, "f32")
+    L = _lib.load()
+    _lib.check(L.csph_profile_enable(g.handle, 1), "profile_enable")
+    g.advance(math.inf, 4)
+    avg = (C.c_double * 6)()
+    cnt = (C.c_int64 * 6)()
+    _lib.check(L.csph_profile_read(g.handle, avg, cnt, 6), "profile_read")
+    assert cnt[5] == 4 and avg[5] > 0.0
+    assert cnt[0] == 4
+    g.close()
