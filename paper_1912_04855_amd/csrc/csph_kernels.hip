@@ -767,23 +767,52 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
   // phi u in its planes instead of u (it needs no neighbour velocity otherwise).
   constexpr bool kPhiU = kCorr && !kF64 && !kVisc;
 
-  auto load = [&](int k) {
-    const int s = ring3(k);
+  // A plane's cells are fetched from memory into registers one iteration before
+  // they are formed into the LDS ring: the loads of plane k+2 are in flight while
+  // plane k is computed.  Each thread handles up to kPer halo cells of a plane.
+  constexpr int kPer = (HP + NT - 1) / NT;
+  struct Raw {
+    Real r, x, y, z, e, p;  // rho, then m (P) or m* (C), E (P) or phi* (C), psi (P) or psi* (C)
+  };
+  Raw raw[kPer];
+  auto cell_of = [&](int h, uint32_t& ob) {
+    const int q = tid + h * NT;
+    const int hx = q % HX, hy = q / HX;
+    const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
+    const bool ok = q < HP && ii <= g.nx && jj <= g.ny;
+    ob = ok ? in_plane(g, ii, jj) : 0u;
+    return ok;
+  };
+  auto fetch = [&](int k) {
     const long long pz = plane0(g, k);
-    for (int q = tid; q < HP; q += NT) {
-      const int hx = q % HX, hy = q / HX;
-      const int ii = T.x0 - 1 + hx, jj = T.y0 - 1 + hy;
-      if (ii > g.nx || jj > g.ny) continue;
-      const uint32_t ob = opaque32(in_plane(g, ii, jj));
-      const Real r = *at_plane(R, pz, ob);
+#pragma unroll
+    for (int h = 0; h < kPer; ++h) {
+      uint32_t ob0;
+      if (!cell_of(h, ob0)) continue;
+      const uint32_t ob = opaque32(ob0);
+      raw[h].r = *at_plane(R, pz, ob);
+      raw[h].x = *at_plane(LX, pz, ob);
+      raw[h].y = *at_plane(LY, pz, ob);
+      raw[h].z = *at_plane(LZ, pz, ob);
+      raw[h].e = *at_plane(LE, pz, ob);
+      raw[h].p = kPsi ? *at_plane(PS, pz, ob) : (Real)0;
+    }
+  };
+  auto put = [&](int k) {
+    const int s = ring3(k);
+#pragma unroll
+    for (int h = 0; h < kPer; ++h) {
+      uint32_t ob;
+      if (!cell_of(h, ob)) continue;
+      const int q = tid + h * NT;
+      const Real r = raw[h].r;
       Real u[3], ph;
       if constexpr (kCorr) {
-        velocity(g, r, *at_plane(LX, pz, ob), *at_plane(LY, pz, ob), *at_plane(LZ, pz, ob), u);
-        ph = *at_plane(LE, pz, ob);
+        velocity(g, r, raw[h].x, raw[h].y, raw[h].z, u);
+        ph = raw[h].e;
       } else {
         Real p;
-        primitive(g, r, *at_plane(LX, pz, ob), *at_plane(LY, pz, ob), *at_plane(LZ, pz, ob),
-                  *at_plane(LE, pz, ob), u[0], u[1], u[2], p);
+        primitive(g, r, raw[h].x, raw[h].y, raw[h].z, raw[h].e, u[0], u[1], u[2], p);
         ph = sqrt_fast((Real)2 * p);
       }
       if constexpr (kPhiU) {
@@ -795,14 +824,18 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
       S.ux[s][q] = u[0];
       S.uy[s][q] = u[1];
       S.uz[s][q] = u[2];
-      S.psi[s][q] = kPsi ? *at_plane(PS, pz, ob) : (Real)0;
+      S.psi[s][q] = raw[h].p;
     }
   };
 
-  load(T.z0 - 1);
-  load(T.z0);
+  fetch(T.z0 - 1);
+  put(T.z0 - 1);
+  fetch(T.z0);
+  put(T.z0);
+  fetch(T.z0 + 1);
   for (int k = T.z0; k < T.z1; ++k) {
-    load(k + 1);
+    put(k + 1);
+    if (k + 2 <= T.z1) fetch(k + 2);
     lds_barrier();
     if (in) {
       const int s0 = ring3(k), c0 = hidx(tx + 1, ty + 1);
