@@ -73,6 +73,7 @@ def lib():
         L.orc_lattice_gradient.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double, dp, dp]
         L.orc_interp_psi.argtypes = [vp, dp, dp]
         L.orc_self_potential.argtypes = [vp, dp, dp]
+        L.orc_set_source.argtypes = [vp, vp, C.c_double]
         L.orc_fill_ghosts_padded.argtypes = [vp, dp, C.c_int, C.c_double]
         _lib = L
     return _lib
@@ -223,6 +224,15 @@ class OracleSim:
         out = np.empty(self.shape)
         _check(lib().orc_interp_psi(self._h, off, out), "interp_psi")
         return out
+
+    def set_source(self, q, eps=0.0):
+        """Mass source rate per cell [nz, ny, nx] (< 0: sink), injected gas's specific
+        internal energy eps; None removes the sources."""
+        if q is None:
+            _check(lib().orc_set_source(self._h, None, 0.0), "set_source")
+            return
+        q = np.ascontiguousarray(np.broadcast_to(q, self.shape), dtype=np.float64)
+        _check(lib().orc_set_source(self._h, q.ctypes.data_as(C.c_void_p), float(eps)), "set_source")
 
     def self_potential(self, rho) -> np.ndarray:
         """The self-gravity potential the step would compute from this density."""

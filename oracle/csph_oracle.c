@@ -45,6 +45,9 @@ struct orc_sim {
   double *vol;        /* predicted particle volume / h^3 (Lagrangian corrector) */
   double *psi_ext;    /* the external potential as set (self-gravity adds to it) */
   double *psih;       /* self-gravity: the potential at t^{n+1}, from the predicted density */
+  double *src;        /* mass source rate per cell (mass / volume / time; < 0: sink) */
+  double eps_src;     /* specific internal energy of the injected gas */
+  int has_src;
   double *fre, *fim;  /* Poisson solve: one complex value per interior cell */
   /* Eulerian stage */
   double *slope[5], *flux[5], *acc[5];
@@ -427,7 +430,7 @@ int orc_create(const orc_params* p, orc_sim** out) {
   double** all[] = {&s->rho, &s->m[0], &s->m[1], &s->m[2], &s->E, &s->psi, &s->u[0], &s->u[1],
                     &s->u[2], &s->p, &s->phi, &s->ms[0], &s->ms[1], &s->ms[2], &s->Es, &s->xs[0],
                     &s->xs[1], &s->xs[2], &s->mt[0], &s->mt[1], &s->mt[2], &s->Et, &s->xt[0],
-                    &s->xt[1], &s->xt[2], &s->psis, &s->vol, &s->psi_ext, &s->psih, &s->fre, &s->fim, &s->slope[0], &s->slope[1], &s->slope[2],
+                    &s->xt[1], &s->xt[2], &s->psis, &s->vol, &s->psi_ext, &s->psih, &s->src, &s->fre, &s->fim, &s->slope[0], &s->slope[1], &s->slope[2],
                     &s->slope[3], &s->slope[4], &s->flux[0], &s->flux[1], &s->flux[2], &s->flux[3],
                     &s->flux[4], &s->acc[0], &s->acc[1], &s->acc[2], &s->acc[3], &s->acc[4]};
   for (size_t k = 0; k < sizeof all / sizeof all[0]; ++k) {
@@ -446,7 +449,7 @@ void orc_destroy(orc_sim* s) {
   double* all[] = {s->rho, s->m[0], s->m[1], s->m[2], s->E, s->psi, s->u[0], s->u[1], s->u[2],
                    s->p, s->phi, s->ms[0], s->ms[1], s->ms[2], s->Es, s->xs[0], s->xs[1],
                    s->xs[2], s->mt[0], s->mt[1], s->mt[2], s->Et, s->xt[0], s->xt[1], s->xt[2],
-                   s->psis, s->vol, s->psi_ext, s->psih, s->fre, s->fim, s->slope[0], s->slope[1], s->slope[2], s->slope[3], s->slope[4],
+                   s->psis, s->vol, s->psi_ext, s->psih, s->src, s->fre, s->fim, s->slope[0], s->slope[1], s->slope[2], s->slope[3], s->slope[4],
                    s->flux[0], s->flux[1], s->flux[2], s->flux[3], s->flux[4], s->acc[0],
                    s->acc[1], s->acc[2], s->acc[3], s->acc[4]};
   for (size_t k = 0; k < sizeof all / sizeof all[0]; ++k) free(all[k]);
@@ -488,6 +491,60 @@ int orc_set_primitive(orc_sim* s, const double* w) {
         s->m[2][c] = r * uz;
         s->E[c] = p / (s->P.gamma - 1.0) + 0.5 * r * (ux * ux + uy * uy + uz * uz);
       }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* sources and sinks                                                         */
+/* ------------------------------------------------------------------------ */
+/* Sec. 4 names non-stationary sources and sinks as an extension.  Reading: a
+ * mass rate q per cell (mass per volume per time), which the caller may change
+ * between any two steps.  A source (q > 0) injects gas at rest with specific
+ * internal energy eps: rho += q dt, m unchanged, E += q dt eps (momentum is
+ * conserved; the mixing of resting and moving gas heats it).  A sink (q < 0)
+ * removes gas at the local specific values: rho += q dt, limited at zero, with
+ * m and E scaled by the same factor, so u and E/rho are unchanged.  Both are
+ * exact for a stationary cell, and applying them for a and then b is applying
+ * them once for a + b.  The step applies half before and half after the
+ * hydrodynamic step (Strang splitting: second order in time; the whole source
+ * after the step is first order). */
+static void source_cell(double q, double eps, double hdt, double* r, double* mx, double* my,
+                        double* mz, double* E) {
+  if (q == 0.0) return;
+  const double d = hdt * q;
+  if (q > 0.0) {
+    *r = *r + d;
+    *E = *E + d * eps;
+    return;
+  }
+  if (!(*r > 0.0)) return;
+  double rn = *r + d;
+  if (rn < 0.0) rn = 0.0;
+  const double f = rn / *r;
+  *mx = *mx * f;
+  *my = *my * f;
+  *mz = *mz * f;
+  *E = *E * f;
+  *r = rn;
+}
+
+int orc_set_source(orc_sim* s, const double* q, double eps) {
+  if (!s) return ORC_ERR_ARG;
+  if (!q) {
+    s->has_src = 0;
+    memset(s->src, 0, s->n * sizeof(double));
+    return ORC_OK;
+  }
+  if (!isfinite(eps) || eps < 0.0) return ORC_ERR_ARG;
+  const size_t N = ninterior(s);
+  for (size_t p = 0; p < N; ++p)
+    if (!isfinite(q[p])) return ORC_ERR_ARG;
+  size_t p = 0;
+  for (int k = 0; k < s->P.nz; ++k)
+    for (int j = 0; j < s->P.ny; ++j)
+      for (int i = 0; i < s->P.nx; ++i, ++p) s->src[IX(s, i, j, k)] = q[p];
+  s->eps_src = eps;
+  s->has_src = 1;
   return ORC_OK;
 }
 
@@ -758,14 +815,6 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
   fill_ghosts(s, s->m[2], R_MZ, 0.0);
   fill_ghosts(s, s->E, R_E, 0.0);
 
-  /* self-gravity: the potential of rho^n, for the predictor */
-  if (s->P.grav > 0.0) {
-    double* rin = (double*)malloc(ninterior(s) * sizeof(double));
-    gather(s, s->rho, rin);
-    self_gravity(s, rin, s->psi);
-    free(rin);
-  }
-
   /* O3: time step */
   double smax = signal_max(s);
   double dt;
@@ -784,6 +833,30 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
     lands = 1;
   }
   if (!(dt > 0.0)) return ORC_ERR_ARG;
+
+  /* sources and sinks: the first half step, then the ghosts of U^n again */
+  if (s->has_src) {
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const size_t c = IX(s, i, j, k);
+          source_cell(s->src[c], s->eps_src, 0.5 * dt, &s->rho[c], &s->m[0][c], &s->m[1][c],
+                      &s->m[2][c], &s->E[c]);
+        }
+    fill_ghosts(s, s->rho, R_RHO, 0.0);
+    fill_ghosts(s, s->m[0], R_MX, 0.0);
+    fill_ghosts(s, s->m[1], R_MY, 0.0);
+    fill_ghosts(s, s->m[2], R_MZ, 0.0);
+    fill_ghosts(s, s->E, R_E, 0.0);
+  }
+
+  /* self-gravity: the potential of rho^n, for the predictor */
+  if (s->P.grav > 0.0) {
+    double* rin = (double*)malloc(ninterior(s) * sizeof(double));
+    gather(s, s->rho, rin);
+    self_gravity(s, rin, s->psi);
+    free(rin);
+  }
 
   /* self-gravity: the potential of the density predicted for t^{n+1}, for the
    * corrector; without it the corrector samples the potential of the step */
@@ -1000,6 +1073,8 @@ int orc_step(orc_sim* s, double dt_max, double t_end, double* dt_taken) {
         size_t c = IX(s, i, j, k);
         double nv[5];
         for (int v = 0; v < 5; ++v) nv[v] = Ut[v][c] - inv_h * s->acc[v][c];
+        /* sources and sinks: the second half step */
+        if (s->has_src) source_cell(s->src[c], s->eps_src, 0.5 * dt, &nv[0], &nv[1], &nv[2], &nv[3], &nv[4]);
         for (int v = 0; v < 5; ++v) {
           if (!isfinite(nv[v])) status = ORC_ERR_NONFINITE;
           tot[v] += nv[v];

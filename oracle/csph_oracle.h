@@ -101,6 +101,11 @@ void     orc_destroy(orc_sim* s);
 int      orc_set_conserved(orc_sim* s, const double* state);
 int      orc_set_primitive(orc_sim* s, const double* prim);
 int      orc_set_potential(orc_sim* s, const double* psi);   /* NULL: psi = 0 */
+/* sources and sinks: mass rate q per cell [nz][ny][nx] (mass / volume / time; > 0
+ * injects gas at rest with specific internal energy eps, < 0 removes gas at the
+ * local specific values, limited at zero); NULL removes them.  Applies from the
+ * next step, half before and half after the hydrodynamic step. */
+int      orc_set_source(orc_sim* s, const double* q, double eps);
 int      orc_get_conserved(const orc_sim* s, double* state);
 int      orc_get_field(const orc_sim* s, int which, double* out);
 /* one step; dt = min(CFL dt, dt_max if > 0, t_end - t if t_end is finite) */
