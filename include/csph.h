@@ -237,6 +237,23 @@ csph_status csph_set_viscosity(csph_sim* sim, double nu);
  * sim. */
 csph_status csph_set_self_gravity(csph_sim* sim, double G);
 
+/* Sources and sinks (Sec. 4 names non-stationary sources and sinks as an
+ * extension of the method): a mass rate per cell, host FP64 `[nz][ny][nx]`
+ * (mass per volume per time), copied to the device; NULL removes them.  A cell
+ * with q > 0 gains gas at rest with specific internal energy eps >= 0 (rho +=
+ * q dt, momentum unchanged, E += q dt eps); a cell with q < 0 loses gas at its
+ * own specific values (rho += q dt, limited at zero, with m and E scaled by the
+ * same factor).  The step applies half before and half after the hydrodynamic
+ * step (Strang splitting), so the step stays second order; a sim with sources
+ * runs the generic stage-E kernel, which applies the second half.  The caller
+ * may change the rates between any two steps (the sources are non-stationary
+ * that way); a call applies from the next step.  The first call allocates one
+ * device field (released by NULL or by destroying the sim).  CSPH_ERR_ARG for
+ * a non-finite rate, a negative or non-finite eps, a batch member or a static
+ * simulation; CSPH_ERR_NOMEM if the allocation fails.  csph_batch_add refuses
+ * a sim with sources. */
+csph_status csph_set_source(csph_sim* sim, const double* host_q, double eps);
+
 /* Tile depth: the stencil sweeps give each workgroup a 32 x 8 tile of an x-y
  * plane and march it through tz planes along z.  Deeper tiles reuse more of the
  * halo they stage; shallower ones give more workgroups.  Each of the three

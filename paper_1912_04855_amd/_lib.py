@@ -32,7 +32,7 @@ EXPORTS = [
     "csph_profile_read", "csph_set_tile_depth", "csph_set_tile_depths", "csph_get_tile_depths",
     "csph_autotune",
     "csph_batch_autotune", "csph_set_scheme", "csph_get_scheme", "csph_stream_probe",
-    "csph_create_static", "csph_set_viscosity", "csph_set_self_gravity",
+    "csph_create_static", "csph_set_viscosity", "csph_set_self_gravity", "csph_set_source",
 ]
 
 
@@ -68,6 +68,7 @@ def load():
         "csph_create_static": (st, [C.POINTER(GridDesc), vp, C.POINTER(vp)]),
         "csph_set_viscosity": (st, [vp, C.c_double]),
         "csph_set_self_gravity": (st, [vp, C.c_double]),
+        "csph_set_source": (st, [vp, vp, C.c_double]),
         "csph_destroy": (st, [vp]),
         "csph_set_stream": (st, [vp, vp]),
         "csph_set_state": (st, [vp, C.c_int32, vp]),

@@ -49,6 +49,9 @@ struct GridDev {
   // -2 (d . K(d)) / |d|^2 at d = -h o (the lattice pair weight of the viscous force)
   double nu, dt_visc;
   double nulam[13];
+  // sources and sinks: specific internal energy of the injected gas (the rates
+  // are the field Fields::src)
+  double eps_src;
 };
 
 enum : int { kLimMinmod = 0, kLimMC = 1, kLimVanLeer = 2, kLimSuperbee = 3 };
@@ -96,6 +99,7 @@ struct Fields {
   Real* phs;     // phi* = sqrt(2 p*), p* the predicted particle's pressure at its predicted volume
   Real* mt[4];   // m~x, m~y, m~z, E~
   Real* xt[3];   // xi^{n+1}
+  Real* src;     // sources and sinks: mass rate per cell (padded layout), or null
 };
 
 // one member of a batch, as the batched kernels see it (device memory)

@@ -171,6 +171,29 @@ __device__ __forceinline__ void primitive(const GridDev& g, Real rho, Real mx, R
   p = pp > (Real)0 ? pp : (Real)0;
 }
 
+// Sources and sinks (an extension, Sec. 4): half a step (hdt = dt/2) of the mass
+// rate q in one cell.  q > 0 injects gas at rest with specific internal energy
+// eps; q < 0 removes gas at the cell's specific values, limited at zero.
+__device__ __forceinline__ void source_cell(Real q, Real eps, Real hdt, Real& r, Real& mx, Real& my,
+                                            Real& mz, Real& E) {
+  if (q == (Real)0) return;
+  const Real d = hdt * q;
+  if (q > (Real)0) {
+    r = r + d;
+    E = E + d * eps;
+    return;
+  }
+  if (!(r > (Real)0)) return;
+  Real rn = r + d;
+  if (rn < (Real)0) rn = (Real)0;
+  const Real f = rn / r;
+  mx = mx * f;
+  my = my * f;
+  mz = mz * f;
+  E = E * f;
+  r = rn;
+}
+
 // velocity m / rho as primitive() forms it (0 in vacuum)
 __device__ __forceinline__ void velocity(const GridDev& g, Real rho, Real mx, Real my, Real mz, Real u[3]) {
   Real p_unused;
@@ -471,6 +494,29 @@ __device__ __forceinline__ void fill_pred_body(const Fields<Real>& F, const Grid
   }
 }
 
+// sources and sinks: the first half step on U^n (interior cells), before its
+// ghosts are filled
+__global__ void __launch_bounds__(256) k_source(Fields<Real> F, GridDev g, const Ctrl* __restrict__ ctrl) {
+  if (!ctrl->active) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const Real hdt = (Real)(0.5 * ctrl->dt);
+  Real* const* U = F.U[ctrl->par];
+  for (int k = blockIdx.z; k < g.nz; k += gridDim.z) {
+    const long long c = cell(g, i, j, k);
+    const Real q = F.src[c];
+    if (q == (Real)0) continue;
+    Real r = U[0][c], mx = U[1][c], my = U[2][c], mz = U[3][c], E = U[4][c];
+    source_cell(q, (Real)g.eps_src, hdt, r, mx, my, mz, E);
+    U[0][c] = r;
+    U[1][c] = mx;
+    U[2][c] = my;
+    U[3][c] = mz;
+    U[4][c] = E;
+  }
+}
+
 // self-gravity: psi at r* of the interior particles from the potential of the
 // density predicted for t^{n+1} (F.psic), replacing the value stage P took from
 // the potential of rho^n; r* as the ghost fill forms it
@@ -534,6 +580,14 @@ __device__ __forceinline__ void fill_state_body(const Fields<Real>& F, const Gri
 __global__ void __launch_bounds__(256) k_fill(FillSet<Real> fs, GridDev g, BcDev bc,
                                               const Ctrl* __restrict__ ctrl, int check_active) {
   if (check_active && !ctrl->active) return;
+  fill_body(fs, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// every ghost zone of U^n (the state copy is known on the device only)
+__global__ void __launch_bounds__(256) k_fill_u(Fields<Real> F, FillSet<Real> fs, GridDev g, BcDev bc,
+                                                const Ctrl* __restrict__ ctrl) {
+  if (!ctrl->active) return;
+  for (int v = 0; v < 5; ++v) fs.f[v] = F.U[ctrl->par][v];
   fill_body(fs, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -1494,6 +1548,12 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
           Real nv[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) nv[v] = bq[v] - (Real)g.inv_h * acc[v];
+          if constexpr (kGen) {
+            // sources and sinks: the second half step (the generic form only)
+            if (F.src)
+              source_cell(*at_col(F.src, k - 1), (Real)g.eps_src, (Real)(0.5 * ctrl->dt), nv[0], nv[1],
+                          nv[2], nv[3], nv[4]);
+          }
           const long long pz = plane0(g, k - 1);
           const uint32_t o = opaque32(oc);
 #pragma unroll
@@ -1772,7 +1832,19 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   };
   mark(0);
   k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
-  k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
+  if (F.src) {
+    // sources and sinks: the first half step, then every ghost of U^n
+    k_source<<<cell_grid(g), dim3(64, 4), 0, s>>>(F, g, ctrl);
+    FillSet<Real> fs{};
+    for (int v = 0; v < 5; ++v) {
+      fs.f[v] = nullptr;
+      fs.role[v] = v;
+    }
+    fs.n = 5;
+    k_fill_u<<<gb, 256, 0, s>>>(F, fs, g, bc, ctrl);
+  } else {
+    k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
+  }
   mark(1);
   if (gr) {
     // the potentials of rho^n and of the predicted density, then their ghosts
@@ -1798,7 +1870,7 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   mark(6);
   k_fill_corr<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(7);
-  if (default_scheme(g))
+  if (default_scheme(g) && !F.src)
     k_stage_e<false><<<nbe, NT, 0, s>>>(F, g, bc, ctrl, partials, tz[2]);
   else
     k_stage_e<true><<<nbe, NT, 0, s>>>(F, g, bc, ctrl, partials, tz[2]);

@@ -253,6 +253,8 @@ struct csph_sim {
   // twiddle and eigenvalue tables), allocated when it is switched on
   double grav = 0.0;
   char* gbuf = nullptr;
+  // sources and sinks: the rate field (padded layout, own allocation) or null
+  char* srcbuf = nullptr;
   Grav<float> gr32{};
   Grav<double> gr64{};
 
@@ -290,6 +292,7 @@ void bind_fields(csph_sim* s, Fields<Real>& F) {
   for (int v = 0; v < 3; ++v) F.xs[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
   F.psis = (Real*)s->field_ptr(k++);
   F.psic = F.psi;
+  F.src = nullptr;
   F.phs = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 4; ++v) F.mt[v] = (Real*)s->field_ptr(k++);
   for (int v = 0; v < 3; ++v) F.xt[v] = offsets ? (Real*)s->field_ptr(k++) : nullptr;
@@ -717,6 +720,7 @@ csph_status csph_destroy(csph_sim* s) {
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->owned) (void)hipFree(s->buf);
   if (s->gbuf) (void)hipFree(s->gbuf);
+  if (s->srcbuf) (void)hipFree(s->srcbuf);
   if (s->in_static) {
     std::lock_guard<std::mutex> lk(g_static_mu);
     const int dev = s->device;
@@ -1063,6 +1067,45 @@ csph_status csph_set_self_gravity(csph_sim* s, double G) {
                                     "or any length up to 1024)");
   }
   return s->is_f64() ? grav_on<double>(s, G) : grav_on<float>(s, G);
+}
+
+csph_status csph_set_source(csph_sim* s, const double* host_q, double eps) {
+  if (!s) return fail(CSPH_ERR_ARG, "sim is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it first");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (!host_q) {
+    if (s->srcbuf) (void)hipFree(s->srcbuf);
+    s->srcbuf = nullptr;
+    s->f32.src = nullptr;
+    s->f64.src = nullptr;
+    s->g.eps_src = 0.0;
+    return CSPH_OK;
+  }
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(CSPH_ERR_ARG, "eps must be finite and >= 0");
+  const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
+  for (size_t q = 0; q < N; ++q)
+    if (!std::isfinite(host_q[q])) return fail(CSPH_ERR_ARG, "source rates must be finite");
+  if (!s->srcbuf) {
+    if (s->in_static)
+      return fail(CSPH_ERR_ARG, "sources allocate a device field: not available to a static simulation");
+    void* p = nullptr;
+    if (hipMalloc(&p, s->L.field_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CSPH_ERR_NOMEM, "hipMalloc of the source field failed");
+    }
+    s->srcbuf = (char*)p;
+    HIP_TRY(hipMemsetAsync(s->srcbuf, 0, s->L.field_bytes, s->stream));
+  }
+  csph_status st = s->is_f64() ? upload_field<double>(s, (double*)s->srcbuf, host_q)
+                               : upload_field<float>(s, (float*)s->srcbuf, host_q);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (s->is_f64())
+    s->f64.src = (double*)s->srcbuf;
+  else
+    s->f32.src = (float*)s->srcbuf;
+  s->g.eps_src = eps;
+  return CSPH_OK;
 }
 
 csph_status csph_get_scheme(const csph_sim* s, int32_t* limiter, int32_t* flux) {
@@ -1450,6 +1493,7 @@ csph_status csph_batch_add(csph_batch* b, csph_sim* s, int64_t steps, double t_e
   if (steps < 0 || std::isnan(t_end)) return fail(CSPH_ERR_ARG, "bad steps or t_end");
   if (!periodic_pairs_ok(s)) return fail(CSPH_ERR_ARG, "PERIODIC must be set on both faces of an axis");
   if (s->grav > 0.0) return fail(CSPH_ERR_ARG, "a self-gravitating sim cannot join a batch");
+  if (s->srcbuf) return fail(CSPH_ERR_ARG, "a sim with sources or sinks cannot join a batch");
   const size_t need = s->L.total;
   if (b->budget && b->used_bytes + need > b->budget) return fail(CSPH_ERR_BUDGET, "HBM budget exceeded");
   Ctrl c{};

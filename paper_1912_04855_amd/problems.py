@@ -59,6 +59,8 @@ class Problem:
     steps: Optional[int] = None
     nu: float = 0.0                      # kinematic viscosity (0: inviscid)
     grav: float = 0.0                    # G of the gas's self-gravity (0: none)
+    src: Optional[np.ndarray] = None     # mass source rate per cell [nz, ny, nx] (< 0: sink)
+    eps_src: float = 0.0                 # specific internal energy of injected gas
 
     @property
     def cells(self) -> int:

@@ -190,6 +190,15 @@ class Sim:
         """Uniform kinematic viscosity of the Lagrangian stage (0: inviscid)."""
         check(_lib.load().csph_set_viscosity(self._h, float(nu)), "csph_set_viscosity")
 
+    def set_source(self, q, eps=0.0):
+        """Mass source rate per cell [nz, ny, nx] (< 0: sink) and the injected gas's
+        specific internal energy; None removes the sources."""
+        if q is None:
+            check(_lib.load().csph_set_source(self._h, None, 0.0), "csph_set_source")
+            return
+        q = np.ascontiguousarray(np.broadcast_to(q, self.shape), dtype=np.float64)
+        check(_lib.load().csph_set_source(self._h, _ptr(q), float(eps)), "csph_set_source")
+
     def set_self_gravity(self, G):
         """Self-gravity of the periodic box with constant G (0: off)."""
         check(_lib.load().csph_set_self_gravity(self._h, float(G)), "csph_set_self_gravity")
@@ -248,6 +257,8 @@ def from_problem(prob, dtype="f64", torch=False, stream=None) -> Sim:
         s.set_viscosity(prob.nu)
     if prob.grav:
         s.set_self_gravity(prob.grav)
+    if prob.src is not None:
+        s.set_source(prob.src, prob.eps_src)
     return s
 
 

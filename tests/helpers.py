@@ -12,6 +12,8 @@ def oracle_sim(prob, **kw):
                     **dict({"nu": prob.nu, "grav": prob.grav}, **kw))
     s.set_primitive(prob.prim)
     s.set_potential(prob.psi)
+    if prob.src is not None:
+        s.set_source(prob.src, prob.eps_src)
     return s
 
 
