@@ -66,6 +66,24 @@ __device__ __forceinline__ int bit_reverse(int e, int log2n) {
   return (int)(__builtin_bitreverse32((unsigned)e) >> (32 - log2n));
 }
 
+// x / d and x mod d for a runtime divisor: a shift and a mask when d is a
+// power of two (the tile loops' index arithmetic), else a division
+struct DivMod {
+  int d, sh;
+  __device__ __forceinline__ void operator()(int x, int& q, int& r) const {
+    if (sh >= 0) {
+      q = x >> sh;
+      r = x & (d - 1);
+    } else {
+      q = x / d;
+      r = x - q * d;
+    }
+  }
+};
+__device__ __forceinline__ DivMod divmod_by(int d) {
+  return DivMod{d, (d & (d - 1)) == 0 ? __builtin_ctz((unsigned)d) : -1};
+}
+
 // which pass: the axis of the lines and what the loads and stores do
 enum Pass : int { kXFwd = 0, kYFwd = 1, kZ = 2, kYInv = 3, kXInv = 4 };
 
@@ -197,6 +215,143 @@ __device__ __forceinline__ void dft_direct(Real* re, Real* im, Real* xr, Real* x
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- register FFT
+// Power-of-two lines from kEl to NT kEl long: Stockham passes of radix R <= kEl
+// (kEl, then the remainder), each thread holding kEl values of one line in
+// registers: T = n / kEl threads per line, each doing kEl / R butterflies of a
+// pass.  A pass reads its butterflies' inputs j + r n/R from the LDS tile,
+// multiplies by exp(sg 2 pi i (j mod Ns) r / (Ns R)) (Ns: the product of the
+// earlier radices), takes the R-point DFT in registers and writes the outputs
+// to (j - j mod Ns) R + (j mod Ns) + r Ns: input and output in natural order,
+// log_kEl(n) passes with two barriers each instead of log2(n) LDS stages.
+constexpr int kEl = std::is_same<Real, double>::value ? 8 : 16;
+
+// cos and sin of 2 pi k / 16 (any integer k)
+__host__ __device__ constexpr double cos16_0to8(int k) {
+  return k == 0 ? 1.0 : k == 1 ? 0.92387953251128674 : k == 2 ? 0.70710678118654752
+       : k == 3 ? 0.38268343236508977 : k == 4 ? 0.0 : k == 5 ? -0.38268343236508977
+       : k == 6 ? -0.70710678118654752 : k == 7 ? -0.92387953251128674 : -1.0;
+}
+__host__ __device__ constexpr double cos16(int k) {
+  return cos16_0to8((k & 15) <= 8 ? (k & 15) : 16 - (k & 15));
+}
+__host__ __device__ constexpr double sin16(int k) { return cos16(k + 12); }  // sin x = cos(x - pi/2)
+
+__host__ __device__ constexpr int brev(int r, int bits) {
+  return bits == 0 ? 0 : ((r & 1) << (bits - 1)) | brev(r >> 1, bits - 1);
+}
+
+// R-point DFT of (vr, vi) in registers, exponent sign kSg, natural order out
+template <int R, int kSg>
+__device__ __forceinline__ void dft_reg(Real (&vr)[R], Real (&vi)[R]) {
+  constexpr int B = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+  Real ur[R], ui[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ur[brev(r, B)] = vr[r];
+    ui[brev(r, B)] = vi[r];
+  }
+#pragma unroll
+  for (int half = 1; half < R; half *= 2) {
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const int pos = k % half, i1 = (k / half) * 2 * half + pos, i2 = i1 + half;
+      const int widx = pos * (16 / (2 * half));  // W_{2 half}^pos = W_16^widx
+      Real tr, ti;
+      if (widx == 0) {
+        tr = ur[i2];
+        ti = ui[i2];
+      } else if (widx == 4) {  // kSg i
+        tr = (Real)(-kSg) * ui[i2];
+        ti = (Real)kSg * ur[i2];
+      } else {
+        const Real c = (Real)cos16(widx), sn = (Real)(kSg * sin16(widx));
+        tr = c * ur[i2] - sn * ui[i2];
+        ti = c * ui[i2] + sn * ur[i2];
+      }
+      ur[i2] = ur[i1] - tr;
+      ui[i2] = ui[i1] - ti;
+      ur[i1] = ur[i1] + tr;
+      ui[i1] = ui[i1] + ti;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    vr[r] = ur[r];
+    vi[r] = ui[r];
+  }
+}
+
+// one Stockham pass of radix R on the tile (line w, thread tl of the line)
+template <int R, int kSg>
+__device__ __forceinline__ void stockham_pass(Real* re, Real* im, int n, int P, int Ns, int w, int tl,
+                                              int T, bool active, const Real* __restrict__ tw) {
+  constexpr int kU = kEl / R;
+  Real vr[kU][R], vi[kU][R];
+  const int nR = n / R;
+  if (active) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = tl + u * T;
+      const int jm = j & (Ns - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = j + r * nR;
+        vr[u][r] = re[e * P + w];
+        vi[u][r] = im[e * P + w];
+      }
+      if (Ns > 1) {
+        const int step = jm * (n / (Ns * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int k = step * r;
+          const Real c = tw[2 * k], sn = (Real)kSg * tw[2 * k + 1];
+          const Real xr = vr[u][r], xi = vi[u][r];
+          vr[u][r] = c * xr - sn * xi;
+          vi[u][r] = c * xi + sn * xr;
+        }
+      }
+      dft_reg<R, kSg>(vr[u], vi[u]);
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = tl + u * T;
+      const int jm = j & (Ns - 1);
+      const int base = (j - jm) * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = base + r * Ns;
+        re[e * P + w] = vr[u][r];
+        im[e * P + w] = vi[u][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// the whole transform of the tile's W lines (W a power of two, W T <= NT)
+template <int kSg>
+__device__ __forceinline__ void stockham(Real* re, Real* im, int n, int W, const Real* __restrict__ tw) {
+  const int P = W + 1;
+  const int T = n / kEl;
+  const int t = threadIdx.x;
+  const int w = t & (W - 1), tl = t >> __builtin_ctz((unsigned)W);
+  const bool active = tl < T;
+  int Ns = 1;
+  for (int m = n; m > 1;) {
+    const int R = m > kEl ? kEl : m;
+    if (R == 2) stockham_pass<2, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    else if (R == 4) stockham_pass<4, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    else if (R == 8) stockham_pass<8, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    else if constexpr (kEl >= 16) stockham_pass<16, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    Ns *= R;
+    m /= R;
+  }
+}
+
 template <int kPass>
 __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const Ctrl* __restrict__ ctrl,
                                                 Grav<Real> gr, int W) {
@@ -214,8 +369,11 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
   Real2* __restrict__ cw = (Real2*)gr.cw;
   const int t = threadIdx.x;
   const int tile = n * W;
-  // the x and y passes load in bit-reversed order for the DIT transform
-  const bool rev = log2n >= 0 && kPass != kZ;
+  // register FFT (power-of-two lines in its range), else the LDS radix-2 FFT
+  // or the direct DFT; the radix-2 x and y passes load in bit-reversed order
+  const bool fast = gr.fast[q.axis] != 0;
+  const DivMod dn = divmod_by(n), dW = divmod_by(W), dny = divmod_by(g.ny);
+  const bool rev = log2n >= 0 && kPass != kZ && !fast;
 
   // ------------------------------------------------------------------- load
   if constexpr (kPass == kXFwd) {
@@ -228,11 +386,14 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     const Real ref = (Real)gr.rho_ref;
     const Real h2 = (Real)(2.0 * g.h);
     for (int idx = t; idx < tile; idx += NT) {
-      const int w = idx / n, e = idx % n;
+      int w, e;
+      dn(idx, w, e);
       Real vr = 0, vi = 0;
       if (w < q.nl) {
         const int l = q.j + w;  // line index within the k plane may wrap to the next plane
-        const int jj = l % g.ny, kk = q.k + l / g.ny;
+        int kq, jj;
+        dny(l, kq, jj);
+        const int kk = q.k + kq;
         const long long c = cell(g, e, jj, kk);
         const Real r = rho[c];
         Real div = 0;
@@ -248,7 +409,8 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     }
   } else if constexpr (kPass == kXInv) {
     for (int idx = t; idx < tile; idx += NT) {
-      const int w = idx / n, e = idx % n;
+      int w, e;
+      dn(idx, w, e);
       Real2 v;
       v.x = 0;
       v.y = 0;
@@ -259,7 +421,8 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     }
   } else {
     for (int idx = t; idx < tile; idx += NT) {
-      const int e = idx / W, w = idx % W;
+      int e, w;
+      dW(idx, e, w);
       Real2 v;
       v.x = 0;
       v.y = 0;
@@ -273,7 +436,27 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
 
   // -------------------------------------------------------------- transform
   constexpr bool kFwd = kPass == kXFwd || kPass == kYFwd;
-  if constexpr (kPass == kZ) {
+  if (fast) {
+    if constexpr (kPass == kZ) {
+      stockham<-1>(re, im, n, W, tw);
+      for (int idx = t; idx < tile; idx += NT) {
+        int kz, w;
+        dW(idx, kz, w);
+        const int i = q.i0 + w;
+        Real f = 0;
+        if (w < q.nl && (i | q.j | kz) != 0) {
+          const double lam = gr.lam[0][i] + gr.lam[1][q.j] + gr.lam[2][kz];
+          f = (Real)(gr.fpg_n / lam);
+        }
+        re[kz * P + w] *= f;
+        im[kz * P + w] *= f;
+      }
+      __syncthreads();
+      stockham<1>(re, im, n, W, tw);
+    } else {
+      stockham<kFwd ? -1 : 1>(re, im, n, W, tw);
+    }
+  } else if constexpr (kPass == kZ) {
     // forward, times the Green's function 4 pi G / (lambda(k) N), inverse; slot
     // s of a power-of-two line holds frequency bitrev(s) between the two
     if (log2n >= 0)
@@ -281,7 +464,8 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     else
       dft_direct(re, im, xr, xi, n, W, tw, (Real)-1);
     for (int idx = t; idx < tile; idx += NT) {
-      const int s = idx / W, w = idx % W;
+      int s, w;
+      dW(idx, s, w);
       const int kz = log2n >= 0 ? bit_reverse(s, log2n) : s;
       const int i = q.i0 + w;
       Real f = 0;
@@ -303,11 +487,13 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     else
       dft_direct(re, im, xr, xi, n, W, tw, kFwd ? (Real)-1 : (Real)1);
   }
+  __syncthreads();
 
   // ------------------------------------------------------------------ store
   if constexpr (kPass == kXFwd) {
     for (int idx = t; idx < tile; idx += NT) {
-      const int w = idx / n, e = idx % n;
+      int w, e;
+      dn(idx, w, e);
       if (w < q.nl) {
         Real2 v;
         v.x = re[e * P + w];
@@ -318,10 +504,13 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
   } else if constexpr (kPass == kXInv) {
     const Real* __restrict__ pe = gr.psi_ext;
     for (int idx = t; idx < tile; idx += NT) {
-      const int w = idx / n, e = idx % n;
+      int w, e;
+      dn(idx, w, e);
       if (w < q.nl) {
         const int l = q.j + w;
-        const int jj = l % g.ny, kk = q.k + l / g.ny;
+        int kq, jj;
+        dny(l, kq, jj);
+        const int kk = q.k + kq;
         const long long c = cell(g, e, jj, kk);
         const Real ext = pe[c];
         F.psi[c] = ext + re[e * P + w];
@@ -330,7 +519,8 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     }
   } else {
     for (int idx = t; idx < tile; idx += NT) {
-      const int e = idx / W, w = idx % W;
+      int e, w;
+      dW(idx, e, w);
       if (w < q.nl) {
         Real2 v;
         v.x = re[e * P + w];
@@ -347,6 +537,11 @@ using CSPH_GTAG::Real;
 using namespace CSPH_GTAG;
 
 template <>
+bool Poisson<Real>::fast_ok(int n, int log2n) {
+  return log2n >= 0 && n >= kEl && n <= NT * kEl;
+}
+
+template <>
 size_t Poisson<Real>::lds_bytes(int n, int log2n, int W) {
   const size_t tile = (size_t)n * (W + 1) * sizeof(Real);
   return (log2n >= 0 ? 2 : 4) * tile;
@@ -357,6 +552,11 @@ int Poisson<Real>::lines(int n, int log2n) {
   // W * n complex values per tile; W capped so a y or z tile row stays one
   // 128-byte run (16 FP32 or 8 FP64 complex values), and so the tile's LDS
   // stays within 64 KiB
+  if (fast_ok(n, log2n)) {
+    // one line per T = n / kEl threads, at most 64 lines
+    const int w = NT * kEl / n;
+    return w > 64 ? 64 : w;
+  }
   constexpr int cap = std::is_same<Real, double>::value ? 2048 : 4096;
   constexpr int wmax = std::is_same<Real, double>::value ? 8 : 16;
   int w = cap / n;

@@ -132,6 +132,7 @@ struct Grav {
   const Real* tw[3];     // per axis: (cos, sin) of 2 pi k / n_d, k < n_d
   const double* lam[3];  // per axis: (2 cos(2 pi k / n_d) - 2) / h^2
   int log2n[3];          // log2 of a power-of-two axis length, else -1
+  int fast[3];           // the axis uses the register FFT
   double fpg_n;          // 4 pi G / (nx ny nz)
   double rho_ref;        // constant taken off the density before the transform
 };
@@ -144,6 +145,7 @@ struct Poisson {
   static hipError_t solve(const Fields<Real>& F, const GridDev& g, const Ctrl* ctrl,
                           const Grav<Real>& gr, hipStream_t s);
   static bool length_ok(int n, int log2n);  // an axis length the solve supports
+  static bool fast_ok(int n, int log2n);    // an axis length of the register FFT
   static int lines(int n, int log2n);       // lines per workgroup of an axis pass
   static size_t lds_bytes(int n, int log2n, int W);
 };

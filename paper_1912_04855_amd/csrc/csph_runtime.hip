@@ -518,6 +518,7 @@ csph_status grav_setup(csph_sim* s) {
     gr.tw[a] = (const Real*)(s->gbuf + off_tw[a]);
     gr.lam[a] = (const double*)(s->gbuf + off_lam[a]);
     gr.log2n[a] = log2_exact(n[a]);
+    gr.fast[a] = Poisson<Real>::fast_ok(n[a], gr.log2n[a]) ? 1 : 0;
   }
   gr.cw = (Real*)s->gbuf;
   gr.psi_ext = (Real*)(s->gbuf + off_ext);
