@@ -127,6 +127,22 @@ csph_status csph_set_stream(csph_sim* sim, void* hip_stream);
  * rho < 0 or (PRIMITIVE) p < 0 with CSPH_ERR_ARG.  Clears a sticky error. */
 csph_status csph_set_state(csph_sim* sim, csph_vars vars, const double* host);
 
+/* Large grids without a full host copy (all of the state lives in HBM; a
+ * 1024^3 FP32 grid holds about 91 GB).  csph_fill_state sets every cell, ghosts
+ * included, to one state (5 values in `vars`), on the device; the time is kept,
+ * the sticky error bits are cleared.  csph_set_state_box and csph_get_state_box
+ * write and read a box of the interior: lo = first cell (x, y, z), n = extent
+ * (x, y, z), host array [5][n_z][n_y][n_x] (one 2D copy per plane and variable);
+ * the rest of the state is untouched.  A write clears the sticky error bits and
+ * applies from the next step (ghosts and the signal-speed maximum are formed
+ * again).  CSPH_ERR_ARG for a box outside the interior, negative density or
+ * pressure, non-finite values, or (for the writes) a batch member. */
+csph_status csph_fill_state(csph_sim* sim, csph_vars vars, const double state[5]);
+csph_status csph_set_state_box(csph_sim* sim, csph_vars vars, const int32_t lo[3], const int32_t n[3],
+                               const double* host);
+csph_status csph_get_state_box(const csph_sim* sim, csph_vars vars, const int32_t lo[3],
+                               const int32_t n[3], double* host_out);
+
 /* Set the cell-centred potential psi `[nz][ny][nx]`; NULL means psi = 0.  Its
  * ghost cells follow the boundary rules with inflow faces copying like outflow,
  * so set the boundaries first (or call this again after changing them). */

@@ -33,6 +33,7 @@ EXPORTS = [
     "csph_autotune",
     "csph_batch_autotune", "csph_set_scheme", "csph_get_scheme", "csph_stream_probe",
     "csph_create_static", "csph_set_viscosity", "csph_set_self_gravity", "csph_set_source",
+    "csph_fill_state", "csph_set_state_box", "csph_get_state_box",
 ]
 
 
@@ -69,6 +70,9 @@ def load():
         "csph_set_viscosity": (st, [vp, C.c_double]),
         "csph_set_self_gravity": (st, [vp, C.c_double]),
         "csph_set_source": (st, [vp, vp, C.c_double]),
+        "csph_fill_state": (st, [vp, C.c_int32, vp]),
+        "csph_set_state_box": (st, [vp, C.c_int32, vp, vp, vp]),
+        "csph_get_state_box": (st, [vp, C.c_int32, vp, vp, vp]),
         "csph_destroy": (st, [vp]),
         "csph_set_stream": (st, [vp, vp]),
         "csph_set_state": (st, [vp, C.c_int32, vp]),

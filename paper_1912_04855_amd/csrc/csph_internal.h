@@ -160,6 +160,8 @@ struct Launch {
                              Ctrl* ctrl, hipStream_t s);
   static hipError_t signal_max(const Fields<Real>& F, const GridDev& g, Ctrl* ctrl,
                                hipStream_t s);
+  // every element of f[0..n) set to v
+  static hipError_t fill_const(Real* f, double v, long long n, hipStream_t s);
   // one full step: begin, ghosts, [self-gravity potentials], stage P, [psi of
   // the predicted density at r*], ghosts, stage C, ghosts, stage E, end
   // gr (nullable): the self-gravity solve; ev (nullable): kStepEvents events

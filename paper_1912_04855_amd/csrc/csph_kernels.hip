@@ -35,6 +35,7 @@
 // run of tiles, which keeps the halo reads of neighbouring tiles in one L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -1808,6 +1809,19 @@ hipError_t Launch<Real>::fill_state(const Fields<Real>& F, const GridDev& g, con
   fs.n = 5;
   const long long n = ghost_count(g);
   k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fs, g, bc, ctrl, 0);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_fill_const(Real* __restrict__ f, Real v, long long n) {
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (long long)gridDim.x * blockDim.x)
+    f[q] = v;
+}
+
+template <>
+hipError_t Launch<Real>::fill_const(Real* f, double v, long long n, hipStream_t s) {
+  const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+  k_fill_const<<<(unsigned)blocks, 256, 0, s>>>(f, (Real)v, n);
   return hipGetLastError();
 }
 

@@ -384,6 +384,66 @@ csph_status set_state_t(csph_sim* s, const double* cons) {
   return CSPH_OK;
 }
 
+// a box of the interior (lo: first cell, n: extent, both (x, y, z)) of one
+// field from / to a host array [n_z][n_y][n_x], one 2D copy per z plane
+template <typename Real>
+csph_status box_upload(csph_sim* s, Real* field, const int32_t lo[3], const int32_t n[3],
+                       const double* host) {
+  const GridDev& g = s->g;
+  const size_t plane = (size_t)n[0] * n[1];
+  std::vector<Real> stage(plane * n[2]);
+  for (size_t q = 0; q < stage.size(); ++q) stage[q] = (Real)host[q];
+  for (int k = 0; k < n[2]; ++k) {
+    Real* dst = field + ((size_t)(lo[2] + k + kGhost) * g.sy + (lo[1] + kGhost)) * g.sx + (lo[0] + kGhost);
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)g.sx * sizeof(Real), stage.data() + plane * k,
+                             (size_t)n[0] * sizeof(Real), (size_t)n[0] * sizeof(Real), (size_t)n[1],
+                             hipMemcpyHostToDevice, s->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CSPH_OK;
+}
+
+template <typename Real>
+csph_status box_download(const csph_sim* s, const Real* field, const int32_t lo[3], const int32_t n[3],
+                         double* host) {
+  const GridDev& g = s->g;
+  const size_t plane = (size_t)n[0] * n[1];
+  std::vector<Real> stage(plane * n[2]);
+  for (int k = 0; k < n[2]; ++k) {
+    const Real* src =
+        field + ((size_t)(lo[2] + k + kGhost) * g.sy + (lo[1] + kGhost)) * g.sx + (lo[0] + kGhost);
+    HIP_TRY(hipMemcpy2DAsync(stage.data() + plane * k, (size_t)n[0] * sizeof(Real), src,
+                             (size_t)g.sx * sizeof(Real), (size_t)n[0] * sizeof(Real), (size_t)n[1],
+                             hipMemcpyDeviceToHost, s->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (size_t q = 0; q < stage.size(); ++q) host[q] = (double)stage[q];
+  return CSPH_OK;
+}
+
+bool box_ok(const csph_sim* s, const int32_t lo[3], const int32_t n[3]) {
+  if (!lo || !n) return false;
+  const int ext[3] = {s->g.nx, s->g.ny, s->g.nz};
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] < 0 || n[a] < 1 || (long long)lo[a] + n[a] > ext[a]) return false;
+  return true;
+}
+
+// conserved variables of primitive (rho, u, v, w, p) values, in place
+csph_status to_conserved(double gamma, double* st, size_t count, size_t stride) {
+  for (size_t q = 0; q < count; ++q) {
+    const double r = st[q], ux = st[stride + q], uy = st[2 * stride + q], uz = st[3 * stride + q],
+                 p = st[4 * stride + q];
+    if (!(r >= 0.0)) return fail(CSPH_ERR_ARG, "density must be >= 0");
+    if (!(p >= 0.0)) return fail(CSPH_ERR_ARG, "pressure must be >= 0");
+    st[stride + q] = r * ux;
+    st[2 * stride + q] = r * uy;
+    st[3 * stride + q] = r * uz;
+    st[4 * stride + q] = p / (gamma - 1.0) + 0.5 * r * (ux * ux + uy * uy + uz * uz);
+  }
+  return CSPH_OK;
+}
+
 template <typename Real>
 csph_status prepare(csph_sim* s) {
   Fields<Real>& F = fields_of<Real>(s);
@@ -781,6 +841,106 @@ csph_status csph_set_state(csph_sim* s, csph_vars vars, const double* host) {
   s->need_smax = true;
   s->x_stale = true;
   s->stepped = false;
+  return CSPH_OK;
+}
+
+// the state was changed from the host: ghosts, signal speed and totals are stale
+static void state_changed(csph_sim* s) {
+  s->need_smax = true;
+  s->x_stale = true;
+  s->stepped = false;
+}
+
+csph_status csph_fill_state(csph_sim* s, csph_vars vars, const double state[5]) {
+  if (!s || !state) return fail(CSPH_ERR_ARG, "sim or state is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
+  if (vars != CSPH_CONSERVED && vars != CSPH_PRIMITIVE) return fail(CSPH_ERR_ARG, "bad vars");
+  double st[5];
+  for (int v = 0; v < 5; ++v) st[v] = state[v];
+  if (!(st[0] >= 0.0)) return fail(CSPH_ERR_ARG, "density must be >= 0");
+  if (vars == CSPH_PRIMITIVE) {
+    csph_status e = to_conserved(s->desc.gamma, st, 1, 1);
+    if (e) return e;
+  }
+  for (int v = 0; v < 5; ++v) {
+    if (!std::isfinite(st[v])) return fail(CSPH_ERR_ARG, "state must be finite");
+    HIP_TRY(s->is_f64() ? Launch<double>::fill_const(s->f64.U[0][v], st[v], s->g.ncell, s->stream)
+                        : Launch<float>::fill_const(s->f32.U[0][v], st[v], s->g.ncell, s->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  Ctrl c{}, old{};
+  csph_status e = read_ctrl(s, &old);
+  if (e) return e;
+  c.t = old.t;
+  c.nsteps = old.nsteps;
+  c.step_limit = old.step_limit;
+  c.t_end = old.t_end;
+  e = write_ctrl(s, c);
+  if (e) return e;
+  if (s->grav > 0.0) set_rho_ref(s, st);
+  state_changed(s);
+  return CSPH_OK;
+}
+
+csph_status csph_set_state_box(csph_sim* s, csph_vars vars, const int32_t lo[3], const int32_t n[3],
+                               const double* host) {
+  if (!s || !host) return fail(CSPH_ERR_ARG, "sim or host array is NULL");
+  if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
+  if (vars != CSPH_CONSERVED && vars != CSPH_PRIMITIVE) return fail(CSPH_ERR_ARG, "bad vars");
+  if (!box_ok(s, lo, n)) return fail(CSPH_ERR_ARG, "box outside the interior");
+  const size_t M = (size_t)n[0] * n[1] * n[2];
+  std::vector<double> st(host, host + 5 * M);
+  for (size_t q = 0; q < M; ++q)
+    if (!(st[q] >= 0.0)) return fail(CSPH_ERR_ARG, "density must be >= 0");
+  if (vars == CSPH_PRIMITIVE) {
+    csph_status e = to_conserved(s->desc.gamma, st.data(), M, M);
+    if (e) return e;
+  }
+  Ctrl c{};
+  csph_status e = read_ctrl(s, &c);
+  if (e) return e;
+  for (int v = 0; v < 5; ++v) {
+    e = s->is_f64() ? box_upload<double>(s, s->f64.U[c.par][v], lo, n, st.data() + (size_t)v * M)
+                    : box_upload<float>(s, s->f32.U[c.par][v], lo, n, st.data() + (size_t)v * M);
+    if (e) return e;
+  }
+  // the sticky error bits and the signal-speed maximum describe the old state
+  c.status = 0;
+  c.smax_valid = 0;
+  c.smax_bits[c.cur] = 0ULL;
+  e = write_ctrl(s, c);
+  if (e) return e;
+  state_changed(s);
+  return CSPH_OK;
+}
+
+csph_status csph_get_state_box(const csph_sim* s, csph_vars vars, const int32_t lo[3], const int32_t n[3],
+                               double* out) {
+  if (!s || !out) return fail(CSPH_ERR_ARG, "sim or output is NULL");
+  if (vars != CSPH_CONSERVED && vars != CSPH_PRIMITIVE) return fail(CSPH_ERR_ARG, "bad vars");
+  if (!box_ok(s, lo, n)) return fail(CSPH_ERR_ARG, "box outside the interior");
+  Ctrl c{};
+  csph_status e = read_ctrl(s, &c);
+  if (e) return e;
+  const size_t M = (size_t)n[0] * n[1] * n[2];
+  for (int v = 0; v < 5; ++v) {
+    e = s->is_f64() ? box_download<double>(s, s->f64.U[c.par][v], lo, n, out + (size_t)v * M)
+                    : box_download<float>(s, s->f32.U[c.par][v], lo, n, out + (size_t)v * M);
+    if (e) return e;
+  }
+  if (vars == CSPH_PRIMITIVE) {
+    const double gm1 = s->desc.gamma - 1.0;
+    for (size_t q = 0; q < M; ++q) {
+      const double r = out[q];
+      double u[3] = {0.0, 0.0, 0.0};
+      if (r > s->desc.rho_vac)
+        for (int d = 0; d < 3; ++d) u[d] = out[(1 + d) * M + q] / r;
+      const double ke = 0.5 * (out[M + q] * u[0] + out[2 * M + q] * u[1] + out[3 * M + q] * u[2]);
+      const double p = gm1 * (out[4 * M + q] - ke);
+      for (int d = 0; d < 3; ++d) out[(1 + d) * M + q] = u[d];
+      out[4 * M + q] = p > 0.0 ? p : 0.0;
+    }
+  }
   return CSPH_OK;
 }
 

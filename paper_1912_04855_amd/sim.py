@@ -190,6 +190,30 @@ class Sim:
         """Uniform kinematic viscosity of the Lagrangian stage (0: inviscid)."""
         check(_lib.load().csph_set_viscosity(self._h, float(nu)), "csph_set_viscosity")
 
+    def fill_state(self, state, vars=PRIMITIVE):
+        """Every cell set to one state (5 values), on the device."""
+        st = np.ascontiguousarray(state, dtype=np.float64)
+        assert st.shape == (5,)
+        check(_lib.load().csph_fill_state(self._h, int(vars), _ptr(st)), "csph_fill_state")
+
+    def set_box(self, lo, arr, vars=PRIMITIVE):
+        """Write a box of the interior: lo = (i, j, k) of its first cell, arr
+        [5, n_z, n_y, n_x]."""
+        arr = np.ascontiguousarray(arr, dtype=np.float64)
+        assert arr.ndim == 4 and arr.shape[0] == 5
+        lo_ = (C.c_int32 * 3)(*[int(v) for v in lo])
+        n_ = (C.c_int32 * 3)(arr.shape[3], arr.shape[2], arr.shape[1])
+        check(_lib.load().csph_set_state_box(self._h, int(vars), lo_, n_, _ptr(arr)), "csph_set_state_box")
+
+    def get_box(self, lo, n, vars=CONSERVED) -> np.ndarray:
+        """Read a box of the interior: lo = (i, j, k) of its first cell, n = (n_x,
+        n_y, n_z); returns [5, n_z, n_y, n_x]."""
+        out = np.empty((5, int(n[2]), int(n[1]), int(n[0])))
+        lo_ = (C.c_int32 * 3)(*[int(v) for v in lo])
+        n_ = (C.c_int32 * 3)(*[int(v) for v in n])
+        check(_lib.load().csph_get_state_box(self._h, int(vars), lo_, n_, _ptr(out)), "csph_get_state_box")
+        return out
+
     def set_source(self, q, eps=0.0):
         """Mass source rate per cell [nz, ny, nx] (< 0: sink) and the injected gas's
         specific internal energy; None removes the sources."""
