@@ -135,6 +135,47 @@ def run_gpu(prob, dtype, steps, warmup, autotune=True, tile_depth=0):
     return {"wall_s": wall, "event_ms": gpu_ms, "profile": prof, "t": t, "tile_depth": tz}
 
 
+def run_large(n=1024, steps=10, warmup=2, tile_depth=0):
+    """The potential-well flow on an n^3 FP32 grid (1024^3: about 91 GB of HBM),
+    set up without a host copy of the state: every cell is filled with the
+    inflow state on the device, the potential is uploaded; events around
+    `steps` steps (autotuning would need a second grid, so the tile depths are
+    the ones given)."""
+    import torch
+    from paper_1912_04855_amd import problems as P
+    from paper_1912_04855_amd.sim import Sim
+
+    pr = P.well_flow(8)  # the workload's constants (state, boundaries)
+    state = np.array(pr.inflow[0], dtype=np.float64)
+    sim = Sim((n, n, n), 1.0 / n, gamma=pr.gamma, cfl=pr.cfl, rho_vac=pr.rho_vac, dtype="f32",
+              torch=True)
+    for f in range(6):
+        sim.set_boundary(f, pr.bc[f], state if pr.bc[f] == P.INFLOW else None)
+    sim.fill_state(state)
+    psi = P.gaussian_well((n, n, n), 1.0 / n)
+    sim.set_potential(psi)
+    del psi
+    if tile_depth:
+        sim.tile_depth = tile_depth
+    stream = torch.cuda.current_stream()
+    sim.advance(math.inf, warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    k = sim.advance(math.inf, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    assert k == steps, (k, steps)
+    ms = ev0.elapsed_time(ev1)
+    tz = sim.tile_depth
+    sim.close()
+    return {"value": round(n ** 3 * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
+            "ms_per_step": round(ms / steps, 4), "steps": steps, "cells": n ** 3, "dtype": "f32",
+            "tile": _tile(tz),
+            "workload": f"potential-well flow {n}^3 (the headline workload's state, potential "
+                        "and boundaries on a 64x larger grid; state filled on the device)"}
+
+
 def _counters(kernel, dtype, cells):
     """rocprofv3 counter summary of this kernel build and workload, if one was
     taken of the current kernel source (else None)."""
@@ -438,6 +479,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=1.2,
                     help="mean arrival rate of the serving workload (requests per second)")
     ap.add_argument("--no-cloud", action="store_true", help="skip the gas-vacuum cloud workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 well-flow workload")
     ap.add_argument("--cloud-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for the HBM "
@@ -521,6 +563,13 @@ def main():
             del prc
         except Exception as e:
             out["cloud"] = {"error": repr(e)}
+    if not args.no_large:
+        log("[bench] potential-well flow 1024^3 f32: 10 steps")
+        try:
+            out["large"] = run_large(1024, 10, tile_depth=r["tile_depth"])
+            log(f"[bench] large: {out['large']['value']:.3e} cell-updates/s")
+        except Exception as e:
+            out["large"] = {"error": repr(e)}
     if not args.no_batch:
         log(f"[bench] batched workload: {args.batch_count} instances")
         try:

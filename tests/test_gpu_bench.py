@@ -20,7 +20,7 @@ def test_bench_record_small_well():
     need_gpu()
     announce("bench", "well 64^3, 4 steps")
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--n", "64", "--steps", "4", "--warmup", "1",
-           "--tile-depth", "16", "--no-cpu", "--no-fp64", "--no-batch", "--no-serve"]
+           "--tile-depth", "16", "--no-cpu", "--no-fp64", "--no-batch", "--no-serve", "--no-large"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=180)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
