@@ -317,9 +317,9 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-__device__ __forceinline__ double signal_speed(const GridDev& g, Real r, Real mx, Real my, Real mz,
+__device__ __forceinline__ Real signal_speed_r(const GridDev& g, Real r, Real mx, Real my, Real mz,
                                                Real E) {
-  if (!(r > (Real)g.rho_vac)) return 0.0;
+  if (!(r > (Real)g.rho_vac)) return (Real)0;
   Real ux, uy, uz, p;
   primitive(g, r, mx, my, mz, E, ux, uy, uz, p);
   Real cs;
@@ -328,8 +328,11 @@ __device__ __forceinline__ double signal_speed(const GridDev& g, Real r, Real mx
   } else {
     cs = sqrtf((Real)g.gamma * p * __builtin_amdgcn_rcpf(r));
   }
-  const Real sp = cs + fabs(ux) + fabs(uy) + fabs(uz);
-  return (double)sp;
+  return cs + fabs(ux) + fabs(uy) + fabs(uz);
+}
+__device__ __forceinline__ double signal_speed(const GridDev& g, Real r, Real mx, Real my, Real mz,
+                                               Real E) {
+  return (double)signal_speed_r(g, r, mx, my, mz, E);
 }
 
 // ==================================================================== ghost cells
@@ -1360,7 +1363,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
   const Real xc[4] = {(Real)(0.5 * ctrl->dt), (Real)(0.25 * ctrl->dt), (Real)(0.5 * g.h), (Real)g.inv_h};
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  double smax = 0.0;
+  Real smr = (Real)0;  // max signal speed of this thread's cells
   int bad = 0;
   if (tid == 0) redb = 0;
   {
@@ -1572,7 +1575,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
             });
           }
           if ((double)nv[0] < -g.neg_tol) bad |= kBadNegDensity;
-          if (!bad) smax = fmax(smax, signal_speed(g, nv[0], nv[1], nv[2], nv[3], nv[4]));
+          if (!bad) smr = fmax(smr, signal_speed_r(g, nv[0], nv[1], nv[2], nv[3], nv[4]));
         }
         // advance the column by one plane
 #pragma unroll
@@ -1597,7 +1600,7 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
   const int lane = tid % kWave, w = tid / kWave;
 #pragma unroll
   for (int v = 0; v < 5; ++v) tot[v] = wave_sum(tot[v]);
-  smax = wave_max(smax);
+  double smax = wave_max((double)smr);
   lds_barrier();
   if (bad) atomicOr(&redb, bad);
   if (lane == 0) {
