@@ -224,7 +224,7 @@ __device__ __forceinline__ void dft_direct(Real* re, Real* im, Real* xr, Real* x
 // earlier radices), takes the R-point DFT in registers and writes the outputs
 // to (j - j mod Ns) R + (j mod Ns) + r Ns: input and output in natural order,
 // log_kEl(n) passes with two barriers each instead of log2(n) LDS stages.
-constexpr int kEl = std::is_same<Real, double>::value ? 8 : 16;
+constexpr int kEl = 8;
 
 // cos and sin of 2 pi k / 16 (any integer k)
 __host__ __device__ constexpr double cos16_0to8(int k) {
@@ -343,10 +343,15 @@ __device__ __forceinline__ void stockham(Real* re, Real* im, int n, int W, const
   int Ns = 1;
   for (int m = n; m > 1;) {
     const int R = m > kEl ? kEl : m;
-    if (R == 2) stockham_pass<2, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
-    else if (R == 4) stockham_pass<4, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
-    else if (R == 8) stockham_pass<8, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
-    else if constexpr (kEl >= 16) stockham_pass<16, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    if (R == 2) {
+      stockham_pass<2, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    } else if (R == 4) {
+      if constexpr (kEl >= 4) stockham_pass<4, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    } else if (R == 8) {
+      if constexpr (kEl >= 8) stockham_pass<8, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    } else {
+      if constexpr (kEl >= 16) stockham_pass<16, kSg>(re, im, n, P, Ns, w, tl, T, active, tw);
+    }
     Ns *= R;
     m /= R;
   }
