@@ -162,8 +162,8 @@ struct Launch {
                                hipStream_t s);
   // every element of f[0..n) set to v
   static hipError_t fill_const(Real* f, double v, long long n, hipStream_t s);
-  // one full step: begin, ghosts, [self-gravity potentials], stage P, [psi of
-  // the predicted density at r*], ghosts, stage C, ghosts, stage E, end
+  // one full step: begin, [first half of the sources], ghosts, [self-gravity
+  // potentials], stage P, ghosts, stage C, ghosts, stage E, end
   // gr (nullable): the self-gravity solve; ev (nullable): kStepEvents events
   // recorded around the launches, for kernel timing
   static constexpr int kStepEvents = 10;

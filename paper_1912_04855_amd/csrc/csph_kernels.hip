@@ -521,35 +521,6 @@ __global__ void __launch_bounds__(256) k_source(Fields<Real> F, GridDev g, const
   }
 }
 
-// self-gravity: psi at r* of the interior particles from the potential of the
-// density predicted for t^{n+1} (F.psic), replacing the value stage P took from
-// the potential of rho^n; r* as the ghost fill forms it
-__global__ void __launch_bounds__(256) k_psis_grav(Fields<Real> F, GridDev g, const Ctrl* __restrict__ ctrl) {
-  if (!ctrl->active) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= g.nx || j >= g.ny) return;
-  const double dt = ctrl->dt;
-  const int par = ctrl->par;
-  for (int k = blockIdx.z; k < g.nz; k += gridDim.z) {
-    const long long c = cell(g, i, j, k);
-    Real xi[3];
-    if constexpr (kKeepXiStar) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) xi[q] = F.xs[q][c];
-    } else {
-      const Real r = F.U[par][0][c];
-      Real un[3], us[3];
-      velocity(g, r, F.U[par][1][c], F.U[par][2][c], F.U[par][3][c], un);
-      velocity(g, r, F.ms[0][c], F.ms[1][c], F.ms[2][c], us);
-      xi_star(un, us, (Real)(0.5 * dt), xi);
-    }
-    const Real* P = F.psic;
-    auto at = [&](int a, int b, int cc) { return P[c + a + (long long)b * g.sx + (long long)cc * g.sxy]; };
-    F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
-  }
-}
-
 // ghosts of the post-Lagrange particles
 __device__ __forceinline__ void fill_corr_body(const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                                const Ctrl* ctrl, unsigned t) {
@@ -798,7 +769,9 @@ struct PlaneL {
 // and psi(r*) stays 0.  The plane buffers S belong to the kernel, so every form
 // shares them.
 // kVisc: a viscosity is set (g.nu > 0): the viscous force and its work join the sums.
-template <bool kCorr, bool kPsi, bool kVisc>
+// kGrav (predictor with self-gravity): psi at r* is sampled from the potential
+// of the predicted density (F.psic, in memory) instead of the planes' psi.
+template <bool kCorr, bool kPsi, bool kVisc, bool kGrav = false>
 __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
                                              const Ctrl* __restrict__ ctrl, const Tile& T) {
   const int par = ctrl->par;
@@ -1091,7 +1064,13 @@ __device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, c
 #pragma unroll
           for (int d = 0; d < 3; ++d) F.xs[d][c] = xi[d];
         }
-        if constexpr (kPsi) {
+        if constexpr (kGrav) {
+          const Real* Pc = F.psic;
+          auto at = [&](int a_, int b_, int c_) {
+            return Pc[c + a_ + (long long)b_ * g.sx + (long long)c_ * g.sxy];
+          };
+          F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
+        } else if constexpr (kPsi) {
           auto at = [&](int a_, int b_, int c_) { return psi_[nb(a_, b_, c_)]; };
           F.psis[c] = psi_at(g, at, xi[0], xi[1], xi[2]);
         }
@@ -1640,7 +1619,7 @@ __device__ __forceinline__ void lattice_sweep_any(PlaneL& S, const Fields<Real>&
   else lattice_sweep<kCorr, false>(S, F, g, bc, ctrl, T);
 }
 
-template <bool kVisc>
+template <bool kVisc, bool kGrav = false>
 __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev bc,
                                                 const Ctrl* __restrict__ ctrl, int tz) {
   if (!ctrl->active) return;
@@ -1648,7 +1627,10 @@ __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev
   int id;
   if (!single_tile(g, tz, T, id)) return;
   __shared__ PlaneL S;
-  lattice_sweep<false, kVisc>(S, F, g, bc, ctrl, T);
+  if constexpr (kGrav)
+    stage_l_body<false, true, kVisc, true>(S, F, g, bc, ctrl, T);  // a potential is always set
+  else
+    lattice_sweep<false, kVisc>(S, F, g, bc, ctrl, T);
 }
 
 template <bool kVisc>
@@ -1875,10 +1857,15 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
     k_fill<<<gb, 256, 0, s>>>(fs, g, bc, ctrl, 1);
   }
   mark(2);
-  if (g.nu > 0.0) k_stage_p<true><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
-  else k_stage_p<false><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
+  if (gr) {
+    // self-gravity: the sweep samples psi at r* from the predicted density's potential
+    if (g.nu > 0.0) k_stage_p<true, true><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
+    else k_stage_p<false, true><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
+  } else {
+    if (g.nu > 0.0) k_stage_p<true><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
+    else k_stage_p<false><<<nbp, NT, 0, s>>>(F, g, bc, ctrl, tz[0]);
+  }
   mark(3);
-  if (gr) k_psis_grav<<<cell_grid(g), dim3(64, 4), 0, s>>>(F, g, ctrl);
   mark(4);
   k_fill_pred<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   mark(5);

@@ -475,8 +475,8 @@ csph_status prof_collect(csph_sim* s) {
     hipEvent_t* e = &s->prof_ev[(size_t)k * csph_sim::kEv];
     float ms[csph_sim::kEv - 1];
     for (int q = 0; q < csph_sim::kEv - 1; ++q) HIP_TRY(hipEventElapsedTime(&ms[q], e[q], e[q + 1]));
-    // e0-e1 begin + state fill, e1-e2 Poisson solve, e2-e3 P, e3-e4 psi at r*
-    // (self-gravity), e4-e5 fill, e5-e6 C, e6-e7 fill, e7-e8 E, e8-e9 end
+    // e0-e1 begin + state fill, e1-e2 Poisson solve (self-gravity), e2-e3 P,
+    // e3-e4 nothing, e4-e5 fill, e5-e6 C, e6-e7 fill, e7-e8 E, e8-e9 end
     s->prof_ms[0] += ms[2];
     s->prof_ms[1] += ms[5];
     s->prof_ms[2] += ms[7];
