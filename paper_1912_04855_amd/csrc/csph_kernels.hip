@@ -81,6 +81,16 @@ constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);        // x and y faces 
 // a row boundary (no bank conflicts), and its y faces start on a half-wave
 constexpr int NFXP = EX * TY;
 
+// Tile shapes of the Lagrangian sweeps: a single grid's stages P and C take
+// 64 x 4 tiles (longer rows: fewer halo cells per row and wider loads); the
+// batched sweeps keep stage E's 32 x 8, which also fits members 32 cells wide.
+template <int kTX>
+struct Shape {
+  static constexpr int TX = kTX, TY = NT / kTX;
+  static constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
+};
+constexpr int kTxL = 64;  // single-grid stages P and C
+
 // ------------------------------------------------------------------ indexing
 __device__ __forceinline__ long long cell(const GridDev& g, int i, int j, int k) {
   return ((long long)(k + kGhost) * g.sy + (j + kGhost)) * (long long)g.sx + (i + kGhost);
@@ -108,25 +118,30 @@ struct Tile {
   int x0, y0, z0, z1;
 };
 
+template <int kTX = TX>
 __device__ __forceinline__ int tiles_of(const GridDev& g, int tz) {
-  return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + tz - 1) / tz);
+  constexpr int ty = NT / kTX;
+  return ((g.nx + kTX - 1) / kTX) * ((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz);
 }
 
 // tile number -> tile origin; tiles are numbered x fastest, then y, then z
+template <int kTX = TX>
 __device__ __forceinline__ void tile_at(const GridDev& g, int tz, int id, Tile& t) {
-  const int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY;
+  constexpr int ty = NT / kTX;
+  const int nbx = (g.nx + kTX - 1) / kTX, nby = (g.ny + ty - 1) / ty;
   const int bx = id % nbx, r = id / nbx, by = r % nby, bz = r / nby;
-  t.x0 = bx * TX;
-  t.y0 = by * TY;
+  t.x0 = bx * kTX;
+  t.y0 = by * ty;
   t.z0 = bz * tz;
   t.z1 = min(t.z0 + tz, g.nz);
 }
 
 // tile of this workgroup in a single-simulation launch (grid padded to 8k)
+template <int kTX = TX>
 __device__ __forceinline__ bool single_tile(const GridDev& g, int tz, Tile& t, int& id) {
   id = xcd_tile(blockIdx.x, gridDim.x);
-  if (id < 0 || id >= tiles_of(g, tz)) return false;
-  tile_at(g, tz, id, t);
+  if (id < 0 || id >= tiles_of<kTX>(g, tz)) return false;
+  tile_at<kTX>(g, tz, id, t);
   return true;
 }
 
@@ -761,7 +776,9 @@ __device__ __forceinline__ int hidx(int hx, int hy) { return hy * HX + hx; }
 //     phi*, psi*): m~ = (m + m*)/2 - (dt/2) A*, E~ likewise, and in FP64
 //     xi^{n+1} = xi*/2 + dt (u^n + u~)/4 (FP32 forms it in stage E).
 // ux, uy, uz hold the velocity, or phi u in the FP32 corrector (see kPhiU)
+template <class Sh>
 struct PlaneL {
+  static constexpr int HP = Sh::HP;
   Real rho[3][HP], phi[3][HP], ux[3][HP], uy[3][HP], uz[3][HP], psi[3][HP];
 };
 
@@ -771,9 +788,12 @@ struct PlaneL {
 // kVisc: a viscosity is set (g.nu > 0): the viscous force and its work join the sums.
 // kGrav (predictor with self-gravity): psi at r* is sampled from the potential
 // of the predicted density (F.psic, in memory) instead of the planes' psi.
-template <bool kCorr, bool kPsi, bool kVisc, bool kGrav = false>
-__device__ __forceinline__ void stage_l_body(PlaneL& S, const Fields<Real>& F, const GridDev& g, const BcDev& bc,
-                                             const Ctrl* __restrict__ ctrl, const Tile& T) {
+// Sh: the tile shape.
+template <bool kCorr, bool kPsi, bool kVisc, bool kGrav, class Sh>
+__device__ __forceinline__ void stage_l_body(PlaneL<Sh>& S, const Fields<Real>& F, const GridDev& g,
+                                             const BcDev& bc, const Ctrl* __restrict__ ctrl, const Tile& T) {
+  constexpr int TX = Sh::TX, HX = Sh::HX, HP = Sh::HP;
+  auto hidx = [](int hx, int hy) { return hy * HX + hx; };
   const int par = ctrl->par;
   const Real* __restrict__ R = F.U[par][0];
   const Real* __restrict__ MX = F.U[par][1];
@@ -1606,14 +1626,14 @@ __device__ __forceinline__ void stage_e_body(const Fields<Real>& F, const GridDe
 // one Lagrangian sweep in the form the grid needs (with or without a potential;
 // kVisc fixed by the caller, so that the inviscid kernels are not given the
 // viscous form's registers)
-template <bool kCorr, bool kVisc>
-__device__ __forceinline__ void lattice_sweep(PlaneL& S, const Fields<Real>& F, const GridDev& g,
+template <bool kCorr, bool kVisc, class Sh>
+__device__ __forceinline__ void lattice_sweep(PlaneL<Sh>& S, const Fields<Real>& F, const GridDev& g,
                                               const BcDev& bc, const Ctrl* ctrl, const Tile& T) {
-  if (g.psi) stage_l_body<kCorr, true, kVisc>(S, F, g, bc, ctrl, T);
-  else stage_l_body<kCorr, false, kVisc>(S, F, g, bc, ctrl, T);
+  if (g.psi) stage_l_body<kCorr, true, kVisc, false>(S, F, g, bc, ctrl, T);
+  else stage_l_body<kCorr, false, kVisc, false>(S, F, g, bc, ctrl, T);
 }
-template <bool kCorr>
-__device__ __forceinline__ void lattice_sweep_any(PlaneL& S, const Fields<Real>& F, const GridDev& g,
+template <bool kCorr, class Sh>
+__device__ __forceinline__ void lattice_sweep_any(PlaneL<Sh>& S, const Fields<Real>& F, const GridDev& g,
                                                   const BcDev& bc, const Ctrl* ctrl, const Tile& T) {
   if (g.nu > 0.0) lattice_sweep<kCorr, true>(S, F, g, bc, ctrl, T);
   else lattice_sweep<kCorr, false>(S, F, g, bc, ctrl, T);
@@ -1625,8 +1645,8 @@ __global__ void __launch_bounds__(NT) k_stage_p(Fields<Real> F, GridDev g, BcDev
   if (!ctrl->active) return;
   Tile T;
   int id;
-  if (!single_tile(g, tz, T, id)) return;
-  __shared__ PlaneL S;
+  if (!single_tile<kTxL>(g, tz, T, id)) return;
+  __shared__ PlaneL<Shape<kTxL>> S;
   if constexpr (kGrav)
     stage_l_body<false, true, kVisc, true>(S, F, g, bc, ctrl, T);  // a potential is always set
   else
@@ -1639,8 +1659,8 @@ __global__ void __launch_bounds__(NT) k_stage_c(Fields<Real> F, GridDev g, BcDev
   if (!ctrl->active) return;
   Tile T;
   int id;
-  if (!single_tile(g, tz, T, id)) return;
-  __shared__ PlaneL S;
+  if (!single_tile<kTxL>(g, tz, T, id)) return;
+  __shared__ PlaneL<Shape<kTxL>> S;
   lattice_sweep<true, kVisc>(S, F, g, bc, ctrl, T);
 }
 
@@ -1673,11 +1693,11 @@ __global__ void __launch_bounds__(NT, kStage == 2 ? e_blocks(kGen) : 2)
   Tile T;
   tile_at(I.g, I.tz, w.y, T);
   if constexpr (kStage == 0) {
-    __shared__ PlaneL S;
+    __shared__ PlaneL<Shape<TX>> S;
     if constexpr (kGen) lattice_sweep_any<false>(S, I.F, I.g, I.bc, I.ctrl, T);
     else lattice_sweep<false, false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if constexpr (kStage == 1) {
-    __shared__ PlaneL S;
+    __shared__ PlaneL<Shape<TX>> S;
     if constexpr (kGen) lattice_sweep_any<true>(S, I.F, I.g, I.bc, I.ctrl, T);
     else lattice_sweep<true, false>(S, I.F, I.g, I.bc, I.ctrl, T);
   } else if (!kGen || default_scheme(I.g))
@@ -1713,12 +1733,15 @@ int pick_tz(const GridDev& g) {
   return tz;
 }
 
+template <int kTX = TX>
 int sweep_tiles(const GridDev& g, int tz) {
-  return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + tz - 1) / tz);
+  constexpr int ty = NT / kTX;
+  return ((g.nx + kTX - 1) / kTX) * ((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz);
 }
 
+template <int kTX = TX>
 int sweep_blocks(const GridDev& g, int tz) {
-  return (sweep_tiles(g, tz) + kXcd - 1) / kXcd * kXcd;
+  return (sweep_tiles<kTX>(g, tz) + kXcd - 1) / kXcd * kXcd;
 }
 
 dim3 cell_grid(const GridDev& g) {
@@ -1824,7 +1847,7 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
   const long long ng = ghost_count(g);
   const unsigned gb = (unsigned)((ng + 255) / 256);
   // each stage has its own tile depth
-  const unsigned nbp = (unsigned)sweep_blocks(g, tz[0]), nbc = (unsigned)sweep_blocks(g, tz[1]),
+  const unsigned nbp = (unsigned)sweep_blocks<kTxL>(g, tz[0]), nbc = (unsigned)sweep_blocks<kTxL>(g, tz[1]),
                  nbe = (unsigned)sweep_blocks(g, tz[2]);
   auto mark = [&](int q) {
     if (ev) (void)hipEventRecord(ev[q], s);
