@@ -90,9 +90,11 @@ def _depths(text):
     return v[0] if len(v) == 1 else tuple(v)
 
 
-def _tile(depths):
-    """Tile shape and the z-depth of each stage's sweep."""
-    return "32x8, z-depth P/C/E " + "/".join(str(d) for d in depths)
+def _tile(depths, dtype="f32"):
+    """Tile shapes and the z-depth of each stage's sweep (single grid: FP32 stages
+    P and C take 64x4 tiles, FP64 and stage E 32x8)."""
+    shapes = "P/C 64x4, E 32x8" if dtype == "f32" else "32x8"
+    return shapes + ", z-depth P/C/E " + "/".join(str(d) for d in depths)
 
 
 def run_gpu(prob, dtype, steps, warmup, autotune=True, tile_depth=0):
@@ -533,7 +535,7 @@ def main():
         "config": {"workload": f"potential-well flow {args.n}^3 (Mach-2 inflow, "
                                f"psi=-exp(-r^2/0.01), gamma=5/3)",
                    "cells": cells, "dtype": args.dtype, "parallelism": "single GPU",
-                   "tile": _tile(r["tile_depth"])},
+                   "tile": _tile(r["tile_depth"], args.dtype)},
         "roofline": rl,
         "algorithmic_hbm_frac": round(value * (44 if args.dtype == "f32" else 88) / HBM_PEAK, 4),
     }
@@ -543,7 +545,7 @@ def main():
         r64 = run_gpu(pr, "f64", k64, args.warmup, autotune=not args.no_autotune)
         v64 = cells * k64 / (r64["event_ms"] * 1e-3)
         out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(r64["event_ms"] / k64, 4),
-                       "steps": k64, "tile": _tile(r64["tile_depth"]),
+                       "steps": k64, "tile": _tile(r64["tile_depth"], "f64"),
                        "roofline": roofline(r64["profile"], cells, "f64")}
     if not args.no_cloud:
         log(f"[bench] gas-vacuum cloud 384^3 f32: {args.cloud_steps} steps")

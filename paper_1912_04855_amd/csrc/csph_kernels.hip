@@ -81,15 +81,16 @@ constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);        // x and y faces 
 // a row boundary (no bank conflicts), and its y faces start on a half-wave
 constexpr int NFXP = EX * TY;
 
-// Tile shapes of the Lagrangian sweeps: a single grid's stages P and C take
-// 64 x 4 tiles (longer rows: fewer halo cells per row and wider loads); the
-// batched sweeps keep stage E's 32 x 8, which also fits members 32 cells wide.
+// Tile shapes of the Lagrangian sweeps: in FP32 a single grid's stages P and C
+// take 64 x 4 tiles (longer rows in the loads); FP64 keeps 32 x 8 there (its
+// planes of 64 x 4 tiles would hold 57 KB of LDS, two workgroups per CU), and
+// the batched sweeps keep stage E's 32 x 8, which also fits members 32 cells wide.
 template <int kTX>
 struct Shape {
   static constexpr int TX = kTX, TY = NT / kTX;
   static constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
 };
-constexpr int kTxL = 64;  // single-grid stages P and C
+constexpr int kTxL = kF64 ? 32 : 64;  // single-grid stages P and C
 
 // ------------------------------------------------------------------ indexing
 __device__ __forceinline__ long long cell(const GridDev& g, int i, int j, int k) {

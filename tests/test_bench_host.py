@@ -33,7 +33,8 @@ def test_tile_depth_argument():
     assert bench._depths("64,16,32") == (64, 16, 32)
     with pytest.raises(Exception):
         bench._depths("8,8")
-    assert bench._tile((64, 16, 32)) == "32x8, z-depth P/C/E 64/16/32"
+    assert bench._tile((64, 16, 32)) == "P/C 64x4, E 32x8, z-depth P/C/E 64/16/32"
+    assert bench._tile((8, 8, 8), "f64") == "32x8, z-depth P/C/E 8/8/8"
 
 
 def test_roofline_of_an_hbm_bound_kernel(monkeypatch):
