@@ -269,8 +269,9 @@ csph_status csph_set_self_gravity(csph_sim* sim, double G);
  * a sim with sources. */
 csph_status csph_set_source(csph_sim* sim, const double* host_q, double eps);
 
-/* Tile depth: the stencil sweeps give each workgroup a 32 x 8 tile of an x-y
- * plane and march it through tz planes along z.  Deeper tiles reuse more of the
+/* Tile depth: the stencil sweeps give each workgroup a tile of an x-y plane
+ * (stages P and C of a single FP32 grid 64 x 4, otherwise 32 x 8) and march it
+ * through tz planes along z.  Deeper tiles reuse more of the
  * halo they stage; shallower ones give more workgroups.  Each of the three
  * sweeps (stage P, stage C, stage E, in that order in tz[3]) has its own depth;
  * valid depths are 2..64.  A new simulation starts from a built-in rule, or from

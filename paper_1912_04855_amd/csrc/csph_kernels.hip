@@ -24,8 +24,8 @@
 //            U^{n+1}, FP64 block totals, error flags
 //   end    : swap the state copies
 //
-// Stages P, C and E are 2.5D stencil sweeps: a workgroup owns a TX x TY tile of
-// an x-y plane and marches along z through TZ planes.  P and C are one sweep
+// Stages P, C and E are 2.5D stencil sweeps: a workgroup owns a tile of an x-y
+// plane (see Shape below) and marches along z through tz planes.  P and C are one sweep
 // (stage_l_body) that keeps three planes of per-cell values (density, phi,
 // velocity, potential) with a one-cell halo in LDS, so each cell's values are
 // formed once per sweep instead of once per neighbour.  E keeps a register queue
