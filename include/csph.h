@@ -196,10 +196,11 @@ const char* csph_last_error(void);
  * synchronises and returns, per kernel group, the average duration in
  * milliseconds of one launch and the number of launches timed since enabling:
  * group 0 = stage P (predictor), 1 = stage C (corrector), 2 = stage E (Eulerian
- * update), 3 = ghost fills (three launches per step, timed together), 4 = the
- * begin/end bookkeeping launches, 5 = self-gravity (the Poisson solve and the
- * ghosts of its two potentials, timed together per step; no launches without
- * self-gravity).  n is the capacity of both arrays (<= 6). */
+ * update), 3 = ghost fills (three launches per step, timed together; the first
+ * also starts the step), 4 = the launch that ends the step, 5 = self-gravity
+ * (the Poisson solve and the ghosts of its two potentials, timed together per
+ * step; no launches without self-gravity).  n is the capacity of both arrays
+ * (<= 6). */
 csph_status csph_profile_enable(csph_sim* sim, int32_t on);
 csph_status csph_profile_read(csph_sim* sim, double* avg_ms, int64_t* launches, int32_t n);
 

@@ -10,8 +10,8 @@
 // the time step and the conservation totals.
 //
 // Per step:
-//   begin  : dt from the max signal speed of U^n (FP64), CFL and viscous limits
-//   fill   : ghost cells of U^n
+//   begin  : dt from the max signal speed of U^n (FP64), CFL and viscous limits,
+//            in the same launch as the ghost cells of U^n
 //   stage P: predictor, Eq. (5) with Q of Eq. (7) on the lattice; the predicted
 //            particle's phi* over its predicted volume, psi at r*
 //   fill   : ghost cells of m*, phi*, xi* and of psi at r*
@@ -594,11 +594,6 @@ __global__ void __launch_bounds__(256) k_fill_corr(Fields<Real> F, GridDev g, Bc
   fill_corr_body(F, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ void __launch_bounds__(256) k_fill_state(Fields<Real> F, GridDev g, BcDev bc,
-                                                    const Ctrl* __restrict__ ctrl) {
-  if (!ctrl->active) return;
-  fill_state_body(F, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
-}
 
 // batched ghost fills: every instance's ghost range is padded to whole blocks
 // of 256, and a host-built map gives each block its (instance, first ghost)
@@ -735,6 +730,16 @@ __global__ void k_begin(Ctrl* ctrl, GridDev g, double dt_max, double t_end) {
 __global__ void k_end(Ctrl* ctrl) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   end_body(ctrl);
+}
+
+// the step's start and the ghosts of U^n in one launch: thread 0 of block 0
+// takes the step's dt (and whether it runs); every thread fills its ghost cell
+// from the interior either way (the fill only restates the ghost rules, so a
+// step that does not run leaves the state as it was)
+__global__ void __launch_bounds__(256) k_begin_fill(Fields<Real> F, GridDev g, BcDev bc, Ctrl* ctrl,
+                                                    double dt_max, double t_end) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) begin_body(ctrl, g, dt_max, t_end);
+  fill_state_body(F, g, bc, ctrl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // batch members: each stops at its own step limit or end time
@@ -1854,8 +1859,9 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
     if (ev) (void)hipEventRecord(ev[q], s);
   };
   mark(0);
-  k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
+  if (!F.src) k_begin_fill<<<gb, 256, 0, s>>>(F, g, bc, ctrl, dt_max, t_end);
   if (F.src) {
+    k_begin<<<1, 64, 0, s>>>(ctrl, g, dt_max, t_end);
     // sources and sinks: the first half step, then every ghost of U^n
     k_source<<<cell_grid(g), dim3(64, 4), 0, s>>>(F, g, ctrl);
     FillSet<Real> fs{};
@@ -1865,8 +1871,6 @@ hipError_t Launch<Real>::step(const Fields<Real>& F, const GridDev& g, const BcD
     }
     fs.n = 5;
     k_fill_u<<<gb, 256, 0, s>>>(F, fs, g, bc, ctrl);
-  } else {
-    k_fill_state<<<gb, 256, 0, s>>>(F, g, bc, ctrl);
   }
   mark(1);
   if (gr) {

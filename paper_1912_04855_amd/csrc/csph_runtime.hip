@@ -1181,7 +1181,7 @@ csph_status csph_profile_read(csph_sim* s, double* avg_ms, int64_t* launches, in
   csph_status st = prof_collect(s);
   if (st) return st;
   for (int q = 0; q < n; ++q) {
-    const int64_t cnt = q == 3 ? 3 * s->prof_n[q] : q == 4 ? 2 * s->prof_n[q] : s->prof_n[q];
+    const int64_t cnt = q == 3 ? 3 * s->prof_n[q] : s->prof_n[q];
     if (avg_ms) avg_ms[q] = cnt ? s->prof_ms[q] / (double)cnt : 0.0;
     if (launches) launches[q] = cnt;
   }
