@@ -877,7 +877,7 @@ csph_status csph_fill_state(csph_sim* s, csph_vars vars, const double state[5]) 
   c.t_end = old.t_end;
   e = write_ctrl(s, c);
   if (e) return e;
-  if (s->grav > 0.0) set_rho_ref(s, st);
+  if (s->grav > 0.0) s->gr32.rho_ref = s->gr64.rho_ref = st[0];  // the uniform density
   state_changed(s);
   return CSPH_OK;
 }

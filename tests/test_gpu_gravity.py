@@ -205,3 +205,22 @@ def test_profile_has_a_gravity_group():
     assert cnt[5] == 4 and avg[5] > 0.0
     assert cnt[0] == 4
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_uniform_fill_under_self_gravity(dtype):
+    # a uniform state has no self potential (its mean is removed): filled on the
+    # device under self-gravity it stays uniform while it moves
+    need_gpu()
+    from paper_1912_04855_amd.sim import Sim
+    announce("gravity_uniform_fill", dtype)
+    s = Sim((32, 16, 16), 1.0 / 32, dtype=dtype)
+    s.set_self_gravity(1.0)
+    st = np.array([1.3, 0.2, 0.0, 0.0, 1.0])
+    s.fill_state(st)
+    assert s.advance(math.inf, 3) == 3
+    W = s.primitive()
+    for v in range(5):
+        assert np.max(np.abs(W[v] - st[v])) <= (1e-12 if dtype == "f64" else 2e-6), v
+    assert np.max(np.abs(s.stage("psi"))) <= 1e-6
+    s.close()
