@@ -402,9 +402,12 @@ int orc_create(const orc_params* p, orc_sim** out) {
   if (p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->h > 0.0) || !(p->gamma > 1.0) ||
       !(p->cfl > 0.0) || !(p->rho_vac >= 0.0) || !(p->nu >= 0.0) || !(p->grav >= 0.0))
     return ORC_ERR_ARG;
-  if (p->grav > 0.0)
-    for (int f = 0; f < 6; ++f)
-      if (p->bc[f] != ORC_PERIODIC) return ORC_ERR_ARG;
+  if (p->grav > 0.0) {
+    /* a periodic box, or one with no periodic face (isolated) */
+    int np = 0;
+    for (int f = 0; f < 6; ++f) np += p->bc[f] == ORC_PERIODIC;
+    if (np != 0 && np != 6) return ORC_ERR_ARG;
+  }
   for (int ax = 0; ax < 3; ++ax) {
     int lo = p->bc[2 * ax], hi = p->bc[2 * ax + 1];
     if (lo < 0 || lo > 3 || hi < 0 || hi > 3) return ORC_ERR_ARG;
@@ -648,13 +651,47 @@ static void poisson(orc_sim* s, const double* rho_in, double* out) {
   for (size_t p = 0; p < N; ++p) out[p] = s->fre[p];
 }
 
+/* Isolated boxes (no periodic face).  Reading: the gas's potential is that of
+ * its mass in free space, each cell a uniform cube of side h,
+ *   psi_i = -G h^3 sum_j rho_j phi(r_i - r_j),
+ * phi(d) = 1/|d| between different cells (the cubes' mutual potential to
+ * O((h/|d|)^2)) and phi(0) = C / h for a cell's own cube, C = 3 ln(2 + sqrt 3)
+ * - pi/2 = 2.3800772..., the integral of 1/|x| over a unit cube about its
+ * centre.  Written out as the direct O(N^2) sum. */
+static void free_space(const orc_sim* s, const double* rho_in, double* out) {
+  const int nx = s->P.nx, ny = s->P.ny, nz = s->P.nz;
+  const double h = s->P.h, grav = s->P.grav;
+  const double self = (3.0 * log(2.0 + sqrt(3.0)) - 0.5 * ORC_PI) / h;
+  size_t q = 0;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i, ++q) {
+        double acc = 0.0;
+        size_t p = 0;
+        for (int c = 0; c < nz; ++c)
+          for (int b = 0; b < ny; ++b)
+            for (int a = 0; a < nx; ++a, ++p) {
+              const double dx = (double)(i - a) * h, dy = (double)(j - b) * h, dz = (double)(k - c) * h;
+              const double r = sqrt(dx * dx + dy * dy + dz * dz);
+              acc += rho_in[p] * (p == q ? self : 1.0 / r);
+            }
+        out[q] = -grav * h * h * h * acc;
+      }
+}
+
 static void gather(const orc_sim* s, const double* src, double* out);
 
-/* out = psi_ext + the potential of the interior density rho_in; ghosts by wrap */
+static int isolated(const orc_sim* s) { return s->P.bc[0] != ORC_PERIODIC; }
+
+/* out = psi_ext + the potential of the interior density rho_in; ghosts by the
+ * potential's boundary rules */
 static void self_gravity(orc_sim* s, const double* rho_in, double* out) {
   const size_t N = ninterior(s);
   double* pout = (double*)malloc(N * sizeof(double));
-  poisson(s, rho_in, pout);
+  if (isolated(s))
+    free_space(s, rho_in, pout);
+  else
+    poisson(s, rho_in, pout);
   size_t q = 0;
   for (int k = 0; k < s->P.nz; ++k)
     for (int j = 0; j < s->P.ny; ++j)
@@ -682,7 +719,10 @@ static void predicted_density(const orc_sim* s, double dt, double* out) {
 
 int orc_self_potential(orc_sim* s, const double* rho, double* psi_out) {
   if (!s || !rho || !psi_out) return ORC_ERR_ARG;
-  poisson(s, rho, psi_out);
+  if (isolated(s))
+    free_space(s, rho, psi_out);
+  else
+    poisson(s, rho, psi_out);
   return ORC_OK;
 }
 

@@ -18,7 +18,12 @@ predicts for t^{n+1}.  The pins:
   * the stage fields: the potential of the step is the external one plus the
     self potential of rho^n, and the corrector's is that of the predicted
     density;
-  * a uniform gas feels no self-gravity; non-periodic faces are refused.
+  * a uniform gas feels no self-gravity; partly periodic boxes are refused;
+  * isolated boxes (no periodic face): the self term of a cell is the integral
+    of 1/|x| over its cube (against numerical quadrature), the potential at the
+    centre of a uniform cube converges to the continuum value at second order,
+    the far field is the monopole, and a cold uniform sphere falls in at the
+    Newtonian rate -(4/3) pi G rho r.
 """
 import math
 
@@ -119,11 +124,94 @@ def test_uniform_gas_stays_at_rest():
     assert np.max(np.abs(U[0] - 1.0)) <= 1e-14
 
 
-@pytest.mark.parametrize("face", range(6))
-def test_self_gravity_needs_a_periodic_box(face):
+@pytest.mark.parametrize("axis", range(3))
+def test_self_gravity_refuses_a_partly_periodic_box(axis):
     bc = [P.PERIODIC] * 6
-    bc[face] = P.REFLECT
+    bc[2 * axis] = bc[2 * axis + 1] = P.REFLECT
     with pytest.raises(RuntimeError):
         O.OracleSim((8, 8, 8), 0.1, bc=tuple(bc), grav=1.0)
     with pytest.raises(RuntimeError):
         O.OracleSim((8, 8, 8), 0.1, grav=-1.0)
+
+
+# --------------------------------------------------------------- isolated boxes
+# Reading: with no periodic face the gas's potential is that of its mass in free
+# space, psi_i = -G h^3 sum_j rho_j phi_ij with phi = 1/|r_i - r_j| between
+# cells and C/h within a cell, C the integral of 1/|x| over a unit cube.
+
+def _isolated(n, G=1.0):
+    return O.OracleSim((n, n, n), 1.0 / n, bc=(P.OUTFLOW,) * 6, grav=G)
+
+
+def test_isolated_self_term_is_the_cube_integral():
+    from scipy import integrate
+    quad, _ = integrate.tplquad(lambda z, y, x: 1.0 / math.sqrt(x * x + y * y + z * z),
+                                0, 0.5, 0, 0.5, 0, 0.5, epsabs=1e-12, epsrel=1e-12)
+    n, G = 8, 0.7
+    o = _isolated(n, G)
+    rho = np.zeros((n, n, n))
+    rho[3, 4, 5] = 2.0
+    psi = o.self_potential(rho)
+    h = 1.0 / n
+    assert psi[3, 4, 5] == pytest.approx(-G * 2.0 * h * h * 8 * quad, rel=1e-9)
+
+
+def test_isolated_cube_centre_potential_converges_at_second_order():
+    # the potential at the centre of a uniform unit cube is -G rho C (C = the
+    # integral of 1/|x| over it); the sum over n^3 cells converges to it
+    C = 3 * math.log(2 + math.sqrt(3)) - math.pi / 2
+    errs = []
+    for n in (4, 8, 16):
+        psi = _isolated(n).self_potential(np.ones((n, n, n)))
+        c = n // 2
+        errs.append(abs(psi[c - 1:c + 1, c - 1:c + 1, c - 1:c + 1].mean() + C))
+    assert min(orders(errs)) >= 1.9
+    assert errs[-1] <= 0.01 * C
+
+
+def test_isolated_far_field_is_the_monopole():
+    n, G = 16, 1.3
+    o = _isolated(n, G)
+    rho = np.zeros((n, n, n))
+    rho[:3, :3, :3] = 1.5
+    psi = o.self_potential(rho)
+    h = 1.0 / n
+    M = 1.5 * 27 * h ** 3
+    centre = np.array([1.5, 1.5, 1.5]) * h
+    far = (np.array([n - 1, n - 1, n - 1]) + 0.5) * h
+    expect = -G * M / np.linalg.norm(far - centre)
+    # the quadrupole of a cube vanishes: the first correction is (L / r)^4
+    assert psi[n - 1, n - 1, n - 1] == pytest.approx(expect, rel=2e-4)
+
+
+def test_cold_sphere_falls_in_at_the_newtonian_rate():
+    # a cold uniform sphere in vacuum: at first every shell falls with
+    # acceleration -G M(r) / r^2 = -(4/3) pi G rho r
+    n, R, G = 16, 0.3, 1.0
+    shape = (n, n, n)
+    h = 1.0 / n
+    x, y, z = P.centres(shape, h)
+    r = np.broadcast_to(np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2), (n, n, n))
+    prim = np.zeros((5, n, n, n))
+    prim[0] = np.where(r < R, 1.0, 1e-8)
+    prim[4] = np.where(r < R, 1e-6, 0.0)
+    pr = P.Problem("cold_sphere", shape, h, 5 / 3, 0.4, (P.OUTFLOW,) * 6, prim, grav=G, rho_vac=1e-7)
+    o = oracle_sim(pr)
+    for _ in range(3):
+        o.step(dt_max=0.01)
+    t = o.time()[0]
+    U = o.conserved()
+    off = [np.broadcast_to(c - 0.5, (n, n, n)) for c in (x, y, z)]
+    ur = (U[1] * off[0] + U[2] * off[1] + U[3] * off[2]) / r / U[0]
+    sel = (r > 0.08) & (r < 0.2)
+    ratio = ur[sel] / (-(4 / 3) * math.pi * G * r[sel] * t)
+    assert abs(ratio.mean() - 1.0) <= 0.01
+    assert np.all(np.abs(ratio - 1.0) <= 0.03)
+
+
+def test_self_gravity_box_classes():
+    # all faces periodic (spectral solve) or none (free space); a mix is refused
+    O.OracleSim((8, 8, 8), 0.1, bc=(P.OUTFLOW, P.INFLOW, P.REFLECT, P.REFLECT, P.OUTFLOW, P.OUTFLOW),
+                grav=1.0)
+    with pytest.raises(RuntimeError):
+        O.OracleSim((8, 8, 8), 0.1, bc=(P.OUTFLOW, P.OUTFLOW) + (P.PERIODIC,) * 4, grav=1.0)
