@@ -232,25 +232,36 @@ csph_status csph_get_scheme(const csph_sim* sim, int32_t* limiter, int32_t* flux
 csph_status csph_set_viscosity(csph_sim* sim, double nu);
 
 /* Self-gravity (Sec. 4 names the gas's self-gravity as an extension of the
- * method) of a periodic box, with gravitational constant G > 0 (0 switches it
- * off; it is off by default).  Each step the gas's potential is the solution of
- * the 7-point discrete Poisson equation L7[psi] = 4 pi G (rho - mean rho),
- * computed by a spectral solve on the device, and the potential the Lagrangian
- * stage sees is the external one (csph_set_potential, zero if none) plus it: the
- * predictor, Eq. (5), takes the potential of rho^n; the corrector, Eq. (6),
- * which evaluates Q at the end of the step, takes that of the density the
- * continuity equation predicts for t^{n+1},
- * rho^n - dt sum_d (m_d,i+1 - m_d,i-1) / (2h), so the step stays second order
- * in time.  Every axis length must be a power of two (up to 4096 in FP32, 2048
- * in FP64; the fast path) or at most 1024 (a direct transform, for small grids).
- * Switching it on allocates the solve's device memory (about 2 complex values
- * per cell plus two fields; released when it is switched off or the sim is
- * destroyed) and takes the mean density of the current state; applies from the
- * next step.  CSPH_ERR_ARG for a negative or non-finite G, a face that is not
- * PERIODIC, an unsupported axis length, a batch member or a static simulation
- * (csph_create_static); CSPH_ERR_NOMEM if the allocation fails.  While it is on,
- * csph_set_boundary refuses non-periodic kinds and csph_batch_add refuses the
- * sim. */
+ * method), with gravitational constant G > 0 (0 switches it off; it is off by
+ * default).  The box must be periodic (all six faces PERIODIC) or isolated (no
+ * face PERIODIC).  Each step the gas's potential is computed on the device:
+ *   periodic box: the solution of the 7-point discrete Poisson equation
+ *     L7[psi] = 4 pi G (rho - mean rho), by a spectral solve;
+ *   isolated box (gas in vacuum): the free-space potential of the cells,
+ *     psi_i = -G h^3 sum_j rho_j phi(r_i - r_j), phi(d) = 1/|d| and phi(0) =
+ *     C/h with C = 3 ln(2 + sqrt 3) - pi/2 (the integral of 1/|x| over a unit
+ *     cube), as a convolution over the box zero-padded to power-of-two lengths
+ *     >= 2 n_d per axis.
+ * The potential the Lagrangian stage sees is the external one
+ * (csph_set_potential, zero if none) plus it: the predictor, Eq. (5), takes the
+ * potential of rho^n; the corrector, Eq. (6), which evaluates Q at the end of
+ * the step, takes that of the density the continuity equation predicts for
+ * t^{n+1}, rho^n - dt sum_d (m_d,i+1 - m_d,i-1) / (2h), so the step stays second
+ * order in time; ghost cells of the potential follow the faces' rules.  Axis
+ * lengths: periodic box, a power of two up to 4096 in FP32 and 2048 in FP64, or
+ * any length up to 1024 (a direct transform, for small grids); isolated box, up
+ * to 2048 in FP32 and 1024 in FP64.  Switching it on allocates the solve's
+ * device memory (periodic: about 2 complex values per cell plus two fields;
+ * isolated: mx my nz complex values plus two fields and the Green's function's
+ * transform on (mx/2+1)(my/2+1)(mz/2+1) values, computed once in FP64 through
+ * two such FP64 arrays of scratch; released when it is switched off or the sim
+ * is destroyed) and, on a periodic box, takes the mean density of the current
+ * state; applies from the next step.  CSPH_ERR_ARG for a negative or non-finite
+ * G, a box with some but not all faces PERIODIC, an unsupported axis length, a
+ * batch member or a static simulation (csph_create_static); CSPH_ERR_NOMEM if an
+ * allocation fails.  While it is on, csph_set_boundary refuses a kind that
+ * would change the box's class (PERIODIC on an isolated box, any other kind on a
+ * periodic one) and csph_batch_add refuses the sim. */
 csph_status csph_set_self_gravity(csph_sim* sim, double G);
 
 /* Sources and sinks (Sec. 4 names non-stationary sources and sinks as an

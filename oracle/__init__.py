@@ -73,6 +73,7 @@ def lib():
         L.orc_lattice_gradient.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double, dp, dp]
         L.orc_interp_psi.argtypes = [vp, dp, dp]
         L.orc_self_potential.argtypes = [vp, dp, dp]
+        L.orc_self_potential_at.argtypes = [vp, dp, C.POINTER(C.c_int32), C.c_int64, dp]
         L.orc_set_source.argtypes = [vp, vp, C.c_double]
         L.orc_fill_ghosts_padded.argtypes = [vp, dp, C.c_int, C.c_double]
         _lib = L
@@ -239,6 +240,16 @@ class OracleSim:
         rho = np.ascontiguousarray(rho, dtype=np.float64)
         out = np.empty(self.shape)
         _check(lib().orc_self_potential(self._h, rho, out), "self_potential")
+        return out
+
+    def self_potential_at(self, rho, cells) -> np.ndarray:
+        """Isolated box: the self potential of rho at the cells (i, j, k) given,
+        each by its direct sum."""
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 3)
+        out = np.empty(len(cells))
+        _check(lib().orc_self_potential_at(self._h, rho, cells.ctypes.data_as(C.POINTER(C.c_int32)),
+                                           len(cells), out), "self_potential_at")
         return out
 
     def fill_ghosts_padded(self, padded, role, dt=0.0):

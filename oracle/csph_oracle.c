@@ -658,25 +658,27 @@ static void poisson(orc_sim* s, const double* rho_in, double* out) {
  * O((h/|d|)^2)) and phi(0) = C / h for a cell's own cube, C = 3 ln(2 + sqrt 3)
  * - pi/2 = 2.3800772..., the integral of 1/|x| over a unit cube about its
  * centre.  Written out as the direct O(N^2) sum. */
-static void free_space(const orc_sim* s, const double* rho_in, double* out) {
+static double free_space_cell(const orc_sim* s, const double* rho_in, int i, int j, int k) {
   const int nx = s->P.nx, ny = s->P.ny, nz = s->P.nz;
   const double h = s->P.h, grav = s->P.grav;
   const double self = (3.0 * log(2.0 + sqrt(3.0)) - 0.5 * ORC_PI) / h;
-  size_t q = 0;
-  for (int k = 0; k < nz; ++k)
-    for (int j = 0; j < ny; ++j)
-      for (int i = 0; i < nx; ++i, ++q) {
-        double acc = 0.0;
-        size_t p = 0;
-        for (int c = 0; c < nz; ++c)
-          for (int b = 0; b < ny; ++b)
-            for (int a = 0; a < nx; ++a, ++p) {
-              const double dx = (double)(i - a) * h, dy = (double)(j - b) * h, dz = (double)(k - c) * h;
-              const double r = sqrt(dx * dx + dy * dy + dz * dz);
-              acc += rho_in[p] * (p == q ? self : 1.0 / r);
-            }
-        out[q] = -grav * h * h * h * acc;
+  double acc = 0.0;
+  size_t p = 0;
+  for (int c = 0; c < nz; ++c)
+    for (int b = 0; b < ny; ++b)
+      for (int a = 0; a < nx; ++a, ++p) {
+        const double dx = (double)(i - a) * h, dy = (double)(j - b) * h, dz = (double)(k - c) * h;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        acc += rho_in[p] * ((a == i && b == j && c == k) ? self : 1.0 / r);
       }
+  return -grav * h * h * h * acc;
+}
+
+static void free_space(const orc_sim* s, const double* rho_in, double* out) {
+  size_t q = 0;
+  for (int k = 0; k < s->P.nz; ++k)
+    for (int j = 0; j < s->P.ny; ++j)
+      for (int i = 0; i < s->P.nx; ++i, ++q) out[q] = free_space_cell(s, rho_in, i, j, k);
 }
 
 static void gather(const orc_sim* s, const double* src, double* out);
@@ -715,6 +717,16 @@ static void predicted_density(const orc_sim* s, double dt, double* out) {
         for (int d = 0; d < 3; ++d) div += (s->m[d][c + st[d]] - s->m[d][c - st[d]]) / (2.0 * s->P.h);
         out[q] = s->rho[c] - dt * div;
       }
+}
+
+int orc_self_potential_at(orc_sim* s, const double* rho, const int32_t* cells, int64_t n, double* out) {
+  if (!s || !rho || !cells || !out || n < 0 || !isolated(s) || !(s->P.grav > 0.0)) return ORC_ERR_ARG;
+  for (int64_t q = 0; q < n; ++q) {
+    const int i = cells[3 * q], j = cells[3 * q + 1], k = cells[3 * q + 2];
+    if (i < 0 || i >= s->P.nx || j < 0 || j >= s->P.ny || k < 0 || k >= s->P.nz) return ORC_ERR_ARG;
+    out[q] = free_space_cell(s, rho, i, j, k);
+  }
+  return ORC_OK;
 }
 
 int orc_self_potential(orc_sim* s, const double* rho, double* psi_out) {

@@ -76,7 +76,7 @@ typedef struct {
   int32_t face_mode;       /* ORC_FACE_* */
   double nu;               /* kinematic viscosity (0: inviscid) */
   double grav;             /* gravitational constant G of the gas's self-gravity (0: none);
-                              needs periodic faces on every axis */
+                              needs all six faces periodic or none (isolated box) */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -124,9 +124,14 @@ double   orc_limiter(int kind, double a, double b);
  * wrap of f; f and out are [nz][ny][nx] and [3][nz][ny][nx] */
 int      orc_lattice_gradient(int32_t nx, int32_t ny, int32_t nz, double h,
                               const double* f, double* out);
-/* self-gravity potential of a density field [nz][ny][nx] on the sim's periodic grid
- * (the discrete Poisson solve of each step); writes [nz][ny][nx] */
+/* self-gravity potential of a density field [nz][ny][nx] (the periodic box's
+ * discrete Poisson solve, or the isolated box's free-space sum, of each step);
+ * writes [nz][ny][nx] */
 int      orc_self_potential(orc_sim* s, const double* rho, double* psi_out);
+/* isolated box only: the self potential of rho at n cells (i, j, k) = cells[3q..3q+2],
+ * each summed directly (O(N) per cell); writes out[n] */
+int      orc_self_potential_at(orc_sim* s, const double* rho, const int32_t* cells, int64_t n,
+                               double* out);
 /* trilinear interpolation of psi (with ghosts filled by the sim's rules) at
  * cell centre + offset; writes one value per cell */
 int      orc_interp_psi(orc_sim* s, const double* off /* [3][nz][ny][nx] */, double* out);

@@ -34,6 +34,12 @@
 // for small grids).  Lines of the y and z passes are W
 // neighbouring x columns, so each element row of the tile is one contiguous
 // run of W complex values in memory.
+//
+// An isolated box (no periodic face: gas in vacuum) takes the free-space
+// potential of its cells instead; the same five passes compute it as a
+// convolution over the box zero-padded to power-of-two lengths m_d >= 2 n_d,
+// with a tabulated Green's function in place of 4 pi G / lambda and no
+// constant taken off the density.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -87,53 +93,86 @@ __device__ __forceinline__ DivMod divmod_by(int d) {
 // which pass: the axis of the lines and what the loads and stores do
 enum Pass : int { kXFwd = 0, kYFwd = 1, kZ = 2, kYInv = 3, kXInv = 4 };
 
+// The work array is [nz][my][mx] (m the transform lengths; m = n on a periodic
+// box).  On an isolated box the density occupies the corner i < nx, j < ny,
+// k < nz of the zero-padded box: the x passes transform only the ny nz lines
+// that hold data; the y pass loads ny elements of its lines and the z pass nz,
+// the rest of each line being zero; the z pass keeps only k < nz of its result,
+// the y inverse only j < ny, the x inverse only i < nx.
 struct Geom {
-  long long base;  // work-array index of element 0 of line 0 of this workgroup
-  long long es;    // stride between the elements of a line
-  long long ls;    // stride between neighbouring lines
-  int n;           // line length
+  long long base;  // y and z passes: work-array index of element 0 of line 0
+  long long es;    // y and z passes: stride between the elements of a line
+  int n;           // transform length
+  int nin, nout;   // elements loaded (the rest zero) and stored
   int nl;          // lines of this workgroup (<= W; fewer at a ragged edge)
   int axis;
   int j, k;        // x pass: first line's (j, k); y pass: k; z pass: j
   int i0;          // y and z passes: x of line 0
 };
 
-__device__ __forceinline__ Geom geom(const GridDev& g, int pass, int W) {
+// Workgroups go to the 8 XCDs in turn (block b to XCD b mod 8), each XCD with
+// its own L2.  The y and z passes' neighbouring tiles share 128-byte lines (a
+// tile row is W complex values), so give each XCD a contiguous range of tiles:
+// block b takes tile (b mod 8) (nb / 8) + b / 8, the ragged last nb mod 8
+// blocks keep their own index.  A permutation of [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int per = nb / kXcd;
+  return b < per * kXcd ? (b % kXcd) * per + b / kXcd : b;
+}
+
+__device__ __forceinline__ Geom geom(const GridDev& g, const Grav<Real>& gr, int pass, int W) {
   Geom q{};
-  const int b = blockIdx.x;
+  const int b = (pass == kXFwd || pass == kXInv) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+  const int mx = gr.m[0], my = gr.m[1];
   if (pass == kXFwd || pass == kXInv) {
     const int lines = g.ny * g.nz;
     const int l0 = b * W;
     q.axis = 0;
-    q.n = g.nx;
+    q.n = mx;
+    q.nin = pass == kXFwd ? g.nx : mx;
+    q.nout = pass == kXFwd ? mx : g.nx;
     q.nl = min(W, lines - l0);
-    q.base = (long long)l0 * g.nx;
-    q.es = 1;
-    q.ls = g.nx;
     q.j = l0 % g.ny;
     q.k = l0 / g.ny;
     q.i0 = 0;
   } else {
-    const int tiles_x = (g.nx + W - 1) / W;
+    const int tiles_x = (mx + W - 1) / W;
     const int tx = b % tiles_x, other = b / tiles_x;
     q.i0 = tx * W;
-    q.nl = min(W, g.nx - q.i0);
-    q.ls = 1;
+    q.nl = min(W, mx - q.i0);
     if (pass == kZ) {
       q.axis = 2;
-      q.n = g.nz;
+      q.n = gr.m[2];
+      q.nin = q.nout = g.nz;
       q.j = other;
-      q.base = (long long)other * g.nx + q.i0;
-      q.es = (long long)g.nx * g.ny;
+      q.base = (long long)other * mx + q.i0;
+      q.es = (long long)mx * my;
     } else {
       q.axis = 1;
-      q.n = g.ny;
+      q.n = my;
+      q.nin = pass == kYFwd ? g.ny : my;
+      q.nout = pass == kYFwd ? my : g.ny;
       q.k = other;
-      q.base = (long long)other * g.nx * g.ny + q.i0;
-      q.es = g.nx;
+      q.base = (long long)other * mx * my + q.i0;
+      q.es = mx;
     }
   }
   return q;
+}
+
+// the Green's function at frequency (i, j, kz): periodic box 4 pi G / (lambda
+// N) (0 for the mean), isolated box G times the tabulated transform
+__device__ __forceinline__ Real green_at(const Grav<Real>& gr, int i, int j, int kz) {
+  if (gr.iso) {
+    const int hx = gr.m[0] >> 1, hy = gr.m[1] >> 1, hz = gr.m[2] >> 1;
+    const int a = i <= hx ? i : gr.m[0] - i, b = j <= hy ? j : gr.m[1] - j,
+              c = kz <= hz ? kz : gr.m[2] - kz;
+    return (Real)gr.fpg_n * gr.khat[((long long)c * (hy + 1) + b) * (hx + 1) + a];
+  }
+  if ((i | j | kz) == 0) return 0;
+  const double lam = gr.lam[0][i] + gr.lam[1][j] + gr.lam[2][kz];
+  return (Real)(gr.fpg_n / lam);
 }
 
 // The tile holds W lines, element e of line w at e * P + w (P = W + 1).
@@ -362,7 +401,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
                                                 Grav<Real> gr, int W) {
   if (!ctrl->active) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const Geom q = geom(g, kPass, W);
+  const Geom q = geom(g, gr, kPass, W);
   const int P = W + 1;
   const int n = q.n;
   const int log2n = gr.log2n[q.axis];
@@ -379,6 +418,12 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
   const bool fast = gr.fast[q.axis] != 0;
   const DivMod dn = divmod_by(n), dW = divmod_by(W), dny = divmod_by(g.ny);
   const bool rev = log2n >= 0 && kPass != kZ && !fast;
+  // x passes: work-array index of element 0 of line w of this workgroup
+  auto xline = [&](int w) -> long long {
+    int kq, jj;
+    dny(q.j + w, kq, jj);
+    return ((long long)(q.k + kq) * gr.m[1] + jj) * gr.m[0];
+  };
 
   // ------------------------------------------------------------------- load
   if constexpr (kPass == kXFwd) {
@@ -394,7 +439,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
       int w, e;
       dn(idx, w, e);
       Real vr = 0, vi = 0;
-      if (w < q.nl) {
+      if (w < q.nl && e < q.nin) {
         const int l = q.j + w;  // line index within the k plane may wrap to the next plane
         int kq, jj;
         dny(l, kq, jj);
@@ -419,7 +464,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
       Real2 v;
       v.x = 0;
       v.y = 0;
-      if (w < q.nl) v = cw[q.base + (long long)w * q.ls + (long long)e * q.es];
+      if (w < q.nl) v = cw[xline(w) + e];
       const int s = rev ? bit_reverse(e, log2n) : e;
       re[s * P + w] = v.x;
       im[s * P + w] = v.y;
@@ -431,7 +476,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
       Real2 v;
       v.x = 0;
       v.y = 0;
-      if (w < q.nl) v = cw[q.base + (long long)w * q.ls + (long long)e * q.es];
+      if (w < q.nl && e < q.nin) v = cw[q.base + w + (long long)e * q.es];
       const int s = rev ? bit_reverse(e, log2n) : e;
       re[s * P + w] = v.x;
       im[s * P + w] = v.y;
@@ -447,12 +492,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
       for (int idx = t; idx < tile; idx += NT) {
         int kz, w;
         dW(idx, kz, w);
-        const int i = q.i0 + w;
-        Real f = 0;
-        if (w < q.nl && (i | q.j | kz) != 0) {
-          const double lam = gr.lam[0][i] + gr.lam[1][q.j] + gr.lam[2][kz];
-          f = (Real)(gr.fpg_n / lam);
-        }
+        const Real f = w < q.nl ? green_at(gr, q.i0 + w, q.j, kz) : (Real)0;
         re[kz * P + w] *= f;
         im[kz * P + w] *= f;
       }
@@ -472,12 +512,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
       int s, w;
       dW(idx, s, w);
       const int kz = log2n >= 0 ? bit_reverse(s, log2n) : s;
-      const int i = q.i0 + w;
-      Real f = 0;
-      if (w < q.nl && (i | q.j | kz) != 0) {
-        const double lam = gr.lam[0][i] + gr.lam[1][q.j] + gr.lam[2][kz];
-        f = (Real)(gr.fpg_n / lam);
-      }
+      const Real f = w < q.nl ? green_at(gr, q.i0 + w, q.j, kz) : (Real)0;
       re[s * P + w] *= f;
       im[s * P + w] *= f;
     }
@@ -503,7 +538,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
         Real2 v;
         v.x = re[e * P + w];
         v.y = im[e * P + w];
-        cw[q.base + (long long)w * q.ls + (long long)e * q.es] = v;
+        cw[xline(w) + e] = v;
       }
     }
   } else if constexpr (kPass == kXInv) {
@@ -511,7 +546,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     for (int idx = t; idx < tile; idx += NT) {
       int w, e;
       dn(idx, w, e);
-      if (w < q.nl) {
+      if (w < q.nl && e < q.nout) {
         const int l = q.j + w;
         int kq, jj;
         dny(l, kq, jj);
@@ -526,11 +561,11 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
     for (int idx = t; idx < tile; idx += NT) {
       int e, w;
       dW(idx, e, w);
-      if (w < q.nl) {
+      if (w < q.nl && e < q.nout) {
         Real2 v;
         v.x = re[e * P + w];
         v.y = im[e * P + w];
-        cw[q.base + (long long)w * q.ls + (long long)e * q.es] = v;
+        cw[q.base + w + (long long)e * q.es] = v;
       }
     }
   }
@@ -580,21 +615,100 @@ bool Poisson<Real>::length_ok(int n, int log2n) {
 template <>
 hipError_t Poisson<Real>::solve(const Fields<Real>& F, const GridDev& g, const Ctrl* ctrl,
                                 const Grav<Real>& gr, hipStream_t s) {
-  const int n[3] = {g.nx, g.ny, g.nz};
   int W[3];
   size_t sh[3];
   for (int a = 0; a < 3; ++a) {
-    W[a] = lines(n[a], gr.log2n[a]);
-    sh[a] = lds_bytes(n[a], gr.log2n[a], W[a]);
+    W[a] = lines(gr.m[a], gr.log2n[a]);
+    sh[a] = lds_bytes(gr.m[a], gr.log2n[a], W[a]);
   }
+  // x passes: the ny nz lines that hold data; y passes: mx columns of nz
+  // planes; z pass: mx columns of my rows
   const unsigned bx = (unsigned)((g.ny * g.nz + W[0] - 1) / W[0]);
-  const unsigned by = (unsigned)(((g.nx + W[1] - 1) / W[1]) * g.nz);
-  const unsigned bz = (unsigned)(((g.nx + W[2] - 1) / W[2]) * g.ny);
+  const unsigned by = (unsigned)(((gr.m[0] + W[1] - 1) / W[1]) * g.nz);
+  const unsigned bz = (unsigned)(((gr.m[0] + W[2] - 1) / W[2]) * gr.m[1]);
   k_poisson<kXFwd><<<bx, NT, sh[0], s>>>(F, g, ctrl, gr, W[0]);
   k_poisson<kYFwd><<<by, NT, sh[1], s>>>(F, g, ctrl, gr, W[1]);
   k_poisson<kZ><<<bz, NT, sh[2], s>>>(F, g, ctrl, gr, W[2]);
   k_poisson<kYInv><<<by, NT, sh[1], s>>>(F, g, ctrl, gr, W[1]);
   k_poisson<kXInv><<<bx, NT, sh[0], s>>>(F, g, ctrl, gr, W[0]);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ isolated box: Green's function
+// The free-space potential of the cells, psi_i = -G h^3 sum_j rho_j phi(r_i -
+// r_j) with phi(d) = 1/|d| and phi(0) = C/h (C = 3 ln(2 + sqrt 3) - pi/2, the
+// integral of 1/|x| over a unit cube), is a linear convolution over the box.
+// With every transform length m_d >= 2 n_d it equals the circular convolution
+// of the zero-padded density with the kernel taken at the wrapped distance
+// min(t, m_d - t) along each axis (Hockney's method).  That kernel is real and
+// even in every axis, so its transform is real and even too: along one axis
+//   K(k) = g(0) + g(m/2) cos(pi k) + 2 sum_{0<t<m/2} g(t) cos(2 pi k t / m),
+// k <= m/2, applied axis by axis to the octant of distances.  Computed once, in
+// FP64, by direct sums (O(m/2) per value), then stored as Real.
+namespace CSPH_GTAG {
+
+__global__ void __launch_bounds__(256) k_green_fill(double* __restrict__ A, int hx, int hy, int hz,
+                                                    double scale) {
+  const long long n = (long long)(hx + 1) * (hy + 1) * (hz + 1);
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int a = (int)(q % (hx + 1));
+  const long long r = q / (hx + 1);
+  const int b = (int)(r % (hy + 1)), c = (int)(r / (hy + 1));
+  const double d2 = (double)a * a + (double)b * b + (double)c * c;
+  A[q] = scale * (d2 == 0.0 ? 3.0 * log(2.0 + sqrt(3.0)) - 0.5 * 3.14159265358979323846 : 1.0 / sqrt(d2));
+}
+
+// out = the cosine transform of in along axis ax, over the (hx+1)(hy+1)(hz+1)
+// octant, x fastest; ct[t] = cos(2 pi t / m), m = 2 h_ax
+__global__ void __launch_bounds__(256) k_green_axis(const double* __restrict__ in, double* __restrict__ out,
+                                                    int hx, int hy, int hz, int ax,
+                                                    const double* __restrict__ ct) {
+  const long long n = (long long)(hx + 1) * (hy + 1) * (hz + 1);
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int a = (int)(q % (hx + 1));
+  const long long r = q / (hx + 1);
+  const int b = (int)(r % (hy + 1)), c = (int)(r / (hy + 1));
+  const int H = ax == 0 ? hx : ax == 1 ? hy : hz;
+  const int m = 2 * H;
+  const int k = ax == 0 ? a : ax == 1 ? b : c;
+  const long long stride = ax == 0 ? 1 : ax == 1 ? (long long)(hx + 1) : (long long)(hx + 1) * (hy + 1);
+  const long long base = q - (long long)k * stride;
+  double acc = in[base] + in[base + (long long)H * stride] * ct[(long long)k * H % m];
+  double sum = 0.0;
+  int t = k;  // (k j) mod m
+  for (int j = 1; j < H; ++j, t += k) {
+    if (t >= m) t -= m;
+    sum += in[base + (long long)j * stride] * ct[t];
+  }
+  out[q] = acc + 2.0 * sum;
+}
+
+__global__ void __launch_bounds__(256) k_green_store(const double* __restrict__ in, Real* __restrict__ out,
+                                                     long long n) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) out[q] = (Real)in[q];
+}
+
+}  // namespace CSPH_GTAG
+
+template <>
+hipError_t Poisson<Real>::green(const Grav<Real>& gr, double h, double* tmp, const double* const ctab[3],
+                                hipStream_t s) {
+  const int hx = gr.m[0] / 2, hy = gr.m[1] / 2, hz = gr.m[2] / 2;
+  const long long n = (long long)(hx + 1) * (hy + 1) * (hz + 1);
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  double* A = tmp;
+  double* B = tmp + n;
+  // unit G: -h^3 phi = -h^2 (C or 1/sqrt(a^2+b^2+c^2)), with the inverse
+  // transform's 1/(mx my mz) folded in
+  const double scale = -h * h / ((double)gr.m[0] * gr.m[1] * gr.m[2]);
+  k_green_fill<<<nb, 256, 0, s>>>(A, hx, hy, hz, scale);
+  k_green_axis<<<nb, 256, 0, s>>>(A, B, hx, hy, hz, 0, ctab[0]);
+  k_green_axis<<<nb, 256, 0, s>>>(B, A, hx, hy, hz, 1, ctab[1]);
+  k_green_axis<<<nb, 256, 0, s>>>(A, B, hx, hy, hz, 2, ctab[2]);
+  k_green_store<<<nb, 256, 0, s>>>(B, const_cast<Real*>(gr.khat), n);
   return hipGetLastError();
 }
 

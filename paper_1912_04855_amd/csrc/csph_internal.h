@@ -126,14 +126,21 @@ struct FillSet {
 // memory) and its constants.
 template <typename Real>
 struct Grav {
-  Real* cw;              // work array, nx*ny*nz complex values (re, im), x fastest
+  // periodic box: transform lengths m_d = n_d.  Isolated box (no periodic
+  // face): the free-space potential as a circular convolution over the box
+  // zero-padded to m_d, the next power of two >= 2 n_d
+  int iso;
+  int m[3];              // transform length per axis
+  Real* cw;              // work array [nz][my][mx] complex values (re, im), x fastest
   Real* psi_ext;         // the external potential (padded layout; interior read)
   Real* psih;            // potential of the predicted density (padded layout)
-  const Real* tw[3];     // per axis: (cos, sin) of 2 pi k / n_d, k < n_d
-  const double* lam[3];  // per axis: (2 cos(2 pi k / n_d) - 2) / h^2
-  int log2n[3];          // log2 of a power-of-two axis length, else -1
+  const Real* tw[3];     // per axis: (cos, sin) of 2 pi k / m_d, k < m_d
+  const double* lam[3];  // periodic: per axis (2 cos(2 pi k / n_d) - 2) / h^2
+  const Real* khat;      // isolated: transform of the unit-G Green's function over
+                         // (mx/2+1)(my/2+1)(mz/2+1) frequencies (it is even), / (mx my mz)
+  int log2n[3];          // log2 of m_d (a power of two), else -1
   int fast[3];           // the axis uses the register FFT
-  double fpg_n;          // 4 pi G / (nx ny nz)
+  double fpg_n;          // periodic: 4 pi G / (nx ny nz); isolated: G
   double rho_ref;        // constant taken off the density before the transform
 };
 
@@ -144,10 +151,15 @@ struct Poisson {
   // and the step's dt; five launches on s, skipped when the step is inactive
   static hipError_t solve(const Fields<Real>& F, const GridDev& g, const Ctrl* ctrl,
                           const Grav<Real>& gr, hipStream_t s);
-  static bool length_ok(int n, int log2n);  // an axis length the solve supports
-  static bool fast_ok(int n, int log2n);    // an axis length of the register FFT
+  static bool length_ok(int n, int log2n);  // a transform length the solve supports
+  static bool fast_ok(int n, int log2n);    // a transform length of the register FFT
   static int lines(int n, int log2n);       // lines per workgroup of an axis pass
   static size_t lds_bytes(int n, int log2n, int W);
+  // isolated box: fills gr.khat for transform lengths gr.m and cell size h,
+  // in FP64 on s; tmp: 2 (mx/2+1)(my/2+1)(mz/2+1) doubles, ctab[d]: cos(2 pi t
+  // / m_d) for t < m_d (device); the caller waits on s before freeing them
+  static hipError_t green(const Grav<Real>& gr, double h, double* tmp, const double* const ctab[3],
+                          hipStream_t s);
 };
 
 // launchers, instantiated for float and double by the kernel translation units

@@ -248,10 +248,12 @@ struct csph_sim {
   int prof_pending = 0;
   double prof_ms[6] = {0, 0, 0, 0, 0, 0};
   int64_t prof_n[6] = {0, 0, 0, 0, 0, 0};
-  // self-gravity (periodic box): G, and the Poisson solve's own device memory
-  // (work array, external potential, potential of the predicted density,
-  // twiddle and eigenvalue tables), allocated when it is switched on
+  // self-gravity: G, and the Poisson solve's own device memory (work array,
+  // external potential, potential of the predicted density, twiddle and
+  // eigenvalue tables or, on an isolated box, the Green's function),
+  // allocated when it is switched on; grav_iso: the box has no periodic face
   double grav = 0.0;
+  bool grav_iso = false;
   char* gbuf = nullptr;
   // sources and sinks: the rate field (padded layout, own allocation) or null
   char* srcbuf = nullptr;
@@ -520,12 +522,13 @@ csph_status launch(csph_sim* s, int n, double dt_max, double t_end) {
 }
 
 // self-gravity: the constant taken off the density before the transform (the
-// mean density of the state; mass is conserved on the periodic box)
+// mean density of the state, which the periodic solve discards anyway and
+// mass conservation keeps; none on an isolated box, where the mean matters)
 void set_rho_ref(csph_sim* s, const double* cons) {
   const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
   double a = 0.0;
   for (size_t q = 0; q < N; ++q) a += cons[q];
-  s->gr32.rho_ref = s->gr64.rho_ref = a / (double)N;
+  s->gr32.rho_ref = s->gr64.rho_ref = s->grav_iso ? 0.0 : a / (double)N;
 }
 
 int log2_exact(int n) {
@@ -534,23 +537,46 @@ int log2_exact(int n) {
   return (1 << l) == n ? l : -1;
 }
 
+// transform length of an axis of n cells: n on a periodic box, the next power
+// of two >= 2 n on an isolated one
+int grav_length(int n, bool iso) {
+  if (!iso) return n;
+  int m = 1;
+  while (m < 2 * n) m <<= 1;
+  return m;
+}
+
+// faces PERIODIC: 6 (periodic box), 0 (isolated box), else a mix
+int periodic_faces(const csph_sim* s) {
+  int np = 0;
+  for (int f = 0; f < 6; ++f) np += s->bc.kind[f] == kPeriodic;
+  return np;
+}
+
 // allocate and fill the Poisson solve's buffers and tables (once per sim)
 template <typename Real>
 csph_status grav_setup(csph_sim* s) {
   Grav<Real>& gr = grav_of<Real>(s);
+  const bool iso = periodic_faces(s) == 0;
   const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
-  const size_t N = (size_t)n[0] * n[1] * n[2];
+  int m[3];
+  for (int a = 0; a < 3; ++a) m[a] = grav_length(n[a], iso);
+  // work array [nz][my][mx] complex; isolated: the Green's function on
+  // (mx/2+1)(my/2+1)(mz/2+1) frequencies
+  const size_t octant = (size_t)(m[0] / 2 + 1) * (m[1] / 2 + 1) * (m[2] / 2 + 1);
   size_t off_tw[3], off_lam[3];
-  size_t total = align_up(N * 2 * sizeof(Real));  // work array
+  size_t total = align_up((size_t)m[0] * m[1] * n[2] * 2 * sizeof(Real));
   const size_t off_ext = total;
   total += s->L.field_bytes;
   const size_t off_psih = total;
   total += s->L.field_bytes;
+  const size_t off_khat = total;
+  if (iso) total += align_up(octant * sizeof(Real));
   for (int a = 0; a < 3; ++a) {
     off_tw[a] = total;
-    total += align_up((size_t)n[a] * 2 * sizeof(Real));
+    total += align_up((size_t)m[a] * 2 * sizeof(Real));
     off_lam[a] = total;
-    total += align_up((size_t)n[a] * sizeof(double));
+    total += align_up((size_t)m[a] * sizeof(double));  // isolated: cos(2 pi t / m) for the set-up
   }
   void* p = nullptr;
   if (hipMalloc(&p, total) != hipSuccess) {
@@ -558,31 +584,58 @@ csph_status grav_setup(csph_sim* s) {
     return fail(CSPH_ERR_NOMEM, "hipMalloc of the self-gravity buffers failed");
   }
   s->gbuf = (char*)p;
+  s->grav_iso = iso;
+  gr.iso = iso ? 1 : 0;
   HIP_TRY(hipMemsetAsync(s->gbuf, 0, total, s->stream));
   const double kPi = 3.14159265358979323846;
   const double h2 = s->g.h * s->g.h;
   for (int a = 0; a < 3; ++a) {
-    std::vector<Real> tw((size_t)n[a] * 2);
-    std::vector<double> lam((size_t)n[a]);
-    for (int k = 0; k < n[a]; ++k) {
-      const double ang = 2.0 * kPi * k / n[a];
+    std::vector<Real> tw((size_t)m[a] * 2);
+    std::vector<double> lam((size_t)m[a]);
+    for (int k = 0; k < m[a]; ++k) {
+      const double ang = 2.0 * kPi * k / m[a];
       tw[2 * (size_t)k] = (Real)std::cos(ang);
       tw[2 * (size_t)k + 1] = (Real)std::sin(ang);
-      lam[k] = (2.0 * std::cos(ang) - 2.0) / h2;
+      lam[k] = iso ? std::cos(ang) : (2.0 * std::cos(ang) - 2.0) / h2;
     }
     HIP_TRY(hipMemcpyAsync(s->gbuf + off_tw[a], tw.data(), tw.size() * sizeof(Real), hipMemcpyHostToDevice,
                            s->stream));
     HIP_TRY(hipMemcpyAsync(s->gbuf + off_lam[a], lam.data(), lam.size() * sizeof(double),
                            hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    gr.m[a] = m[a];
     gr.tw[a] = (const Real*)(s->gbuf + off_tw[a]);
-    gr.lam[a] = (const double*)(s->gbuf + off_lam[a]);
-    gr.log2n[a] = log2_exact(n[a]);
-    gr.fast[a] = Poisson<Real>::fast_ok(n[a], gr.log2n[a]) ? 1 : 0;
+    gr.lam[a] = iso ? nullptr : (const double*)(s->gbuf + off_lam[a]);
+    gr.log2n[a] = log2_exact(m[a]);
+    gr.fast[a] = Poisson<Real>::fast_ok(m[a], gr.log2n[a]) ? 1 : 0;
   }
   gr.cw = (Real*)s->gbuf;
   gr.psi_ext = (Real*)(s->gbuf + off_ext);
   gr.psih = (Real*)(s->gbuf + off_psih);
+  gr.khat = iso ? (const Real*)(s->gbuf + off_khat) : nullptr;
+  if (iso) {
+    // the Green's function, through two FP64 octants of scratch
+    double* tmp = nullptr;
+    if (hipMalloc((void**)&tmp, 2 * octant * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(s->gbuf);
+      s->gbuf = nullptr;
+      gr = Grav<Real>{};
+      return fail(CSPH_ERR_NOMEM, "hipMalloc of the Green's function scratch failed");
+    }
+    const double* ctab[3];
+    for (int a = 0; a < 3; ++a) ctab[a] = (const double*)(s->gbuf + off_lam[a]);
+    hipError_t e = Poisson<Real>::green(gr, s->g.h, tmp, ctab, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s->stream);
+      (void)hipFree(s->gbuf);
+      s->gbuf = nullptr;
+      gr = Grav<Real>{};
+      return fail(CSPH_ERR_DEVICE, std::string("the Green's function: ") + hipGetErrorString(e));
+    }
+  }
   return CSPH_OK;
 }
 
@@ -595,7 +648,7 @@ csph_status grav_on(csph_sim* s, double G) {
   Grav<Real>& gr = grav_of<Real>(s);
   Fields<Real>& F = fields_of<Real>(s);
   const size_t N = (size_t)s->g.nx * s->g.ny * s->g.nz;
-  gr.fpg_n = 4.0 * 3.14159265358979323846 * G / (double)N;
+  gr.fpg_n = s->grav_iso ? G : 4.0 * 3.14159265358979323846 * G / (double)N;
   // the mean density of the current state
   Ctrl c{};
   csph_status st = read_ctrl(s, &c);
@@ -632,6 +685,7 @@ csph_status grav_off(csph_sim* s) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   (void)hipFree(s->gbuf);
   s->gbuf = nullptr;
+  s->grav_iso = false;
   grav_of<Real>(s) = Grav<Real>{};
   return CSPH_OK;
 }
@@ -877,7 +931,7 @@ csph_status csph_fill_state(csph_sim* s, csph_vars vars, const double state[5]) 
   c.t_end = old.t_end;
   e = write_ctrl(s, c);
   if (e) return e;
-  if (s->grav > 0.0) s->gr32.rho_ref = s->gr64.rho_ref = st[0];  // the uniform density
+  if (s->grav > 0.0 && !s->grav_iso) s->gr32.rho_ref = s->gr64.rho_ref = st[0];  // the uniform density
   state_changed(s);
   return CSPH_OK;
 }
@@ -977,8 +1031,9 @@ csph_status csph_set_boundary(csph_sim* s, int32_t face, csph_bc kind, const dou
   if (s->in_batch) return fail(CSPH_ERR_ARG, "sim is a batch member: remove it from the batch first");
   if (face < 0 || face > 5) return fail(CSPH_ERR_ARG, "face must be 0..5");
   if (kind < CSPH_PERIODIC || kind > CSPH_REFLECT) return fail(CSPH_ERR_ARG, "bad boundary kind");
-  if (s->grav > 0.0 && kind != CSPH_PERIODIC)
-    return fail(CSPH_ERR_ARG, "self-gravity needs a periodic box: switch it off first");
+  if (s->grav > 0.0 && (kind == CSPH_PERIODIC) == s->grav_iso)
+    return fail(CSPH_ERR_ARG, s->grav_iso ? "self-gravity on an isolated box: no face may become PERIODIC"
+                                          : "self-gravity on a periodic box: every face stays PERIODIC");
   s->bc.kind[face] = (int)kind;
   if (kind == CSPH_INFLOW) {
     if (!inflow_prim) return fail(CSPH_ERR_ARG, "inflow state required");
@@ -1214,18 +1269,22 @@ csph_status csph_set_self_gravity(csph_sim* s, double G) {
     if (!(s->grav > 0.0)) return CSPH_OK;
     return s->is_f64() ? grav_off<double>(s) : grav_off<float>(s);
   }
-  for (int f = 0; f < 6; ++f)
-    if (s->bc.kind[f] != kPeriodic) return fail(CSPH_ERR_ARG, "self-gravity needs PERIODIC on all six faces");
+  const int np = periodic_faces(s);
+  if (np != 0 && np != 6)
+    return fail(CSPH_ERR_ARG, "self-gravity needs PERIODIC on all six faces (a periodic box) or on none "
+                              "(an isolated box)");
   if (s->in_static && !s->gbuf)
     return fail(CSPH_ERR_ARG, "self-gravity allocates its own device memory: not available to a static simulation");
   const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
   for (int a = 0; a < 3; ++a) {
-    const int l = log2_exact(n[a]);
-    const bool ok = s->is_f64() ? Poisson<double>::length_ok(n[a], l) : Poisson<float>::length_ok(n[a], l);
+    const int m = grav_length(n[a], np == 0);
+    const int l = log2_exact(m);
+    const bool ok = s->is_f64() ? Poisson<double>::length_ok(m, l) : Poisson<float>::length_ok(m, l);
     if (!ok)
       return fail(CSPH_ERR_ARG, "self-gravity: axis length " + std::to_string(n[a]) +
-                                    " unsupported (a power of two up to 4096 in FP32 and 2048 in FP64, "
-                                    "or any length up to 1024)");
+                                    (np == 0 ? " unsupported on an isolated box (up to 2048 in FP32 and 1024 in FP64)"
+                                             : " unsupported (a power of two up to 4096 in FP32 and 2048 in "
+                                               "FP64, or any length up to 1024)"));
   }
   return s->is_f64() ? grav_on<double>(s, G) : grav_on<float>(s, G);
 }

@@ -202,6 +202,22 @@ def cloud(n=384, seed=0, R=0.3, eps=0.05, rho_c=1.0, amp=0.01, gamma=5.0 / 3.0, 
                    np.ascontiguousarray(psi), steps=steps, rho_vac=rho_vac * rho_c)
 
 
+def cold_sphere(n=16, R=0.3, G=1.0, rho_in=1.0, p_in=1e-6, gamma=5.0 / 3.0, cfl=0.4,
+                rho_vac=1e-7) -> Problem:
+    """A cold uniform sphere of radius R (rho_in, pressure p_in) in near vacuum
+    (rho = 1e-8 rho_in, p = 0) with its own gravity on an isolated box (every
+    face OUTFLOW).  At first every shell falls at -(4/3) pi G rho_in r."""
+    shape = (n, n, n)
+    h = 1.0 / n
+    x, y, z = centres(shape, h)
+    r = np.broadcast_to(np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2), shape[::-1])
+    prim = _prim(shape)
+    prim[0] = np.where(r < R, rho_in, 1e-8 * rho_in)
+    prim[4] = np.where(r < R, p_in, 0.0)
+    return Problem("cold_sphere", shape, h, gamma, cfl, (OUTFLOW,) * 6, prim, grav=G,
+                   rho_vac=rho_vac * rho_in)
+
+
 # --------------------------------------------------------------------------
 # point blast
 # --------------------------------------------------------------------------

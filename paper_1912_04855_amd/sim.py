@@ -224,7 +224,9 @@ class Sim:
         check(_lib.load().csph_set_source(self._h, _ptr(q), float(eps)), "csph_set_source")
 
     def set_self_gravity(self, G):
-        """Self-gravity of the periodic box with constant G (0: off)."""
+        """Self-gravity with constant G (0: off): on a periodic box (all six
+        faces PERIODIC) by the discrete Poisson equation, on an isolated box (no
+        face PERIODIC) as the free-space potential of the cells."""
         check(_lib.load().csph_set_self_gravity(self._h, float(G)), "csph_set_self_gravity")
 
     def scheme(self):

@@ -187,15 +187,10 @@ def test_isolated_far_field_is_the_monopole():
 def test_cold_sphere_falls_in_at_the_newtonian_rate():
     # a cold uniform sphere in vacuum: at first every shell falls with
     # acceleration -G M(r) / r^2 = -(4/3) pi G rho r
-    n, R, G = 16, 0.3, 1.0
-    shape = (n, n, n)
-    h = 1.0 / n
-    x, y, z = P.centres(shape, h)
+    n, G = 16, 1.0
+    pr = P.cold_sphere(n, R=0.3, G=G)
+    x, y, z = P.centres(pr.shape, pr.h)
     r = np.broadcast_to(np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2), (n, n, n))
-    prim = np.zeros((5, n, n, n))
-    prim[0] = np.where(r < R, 1.0, 1e-8)
-    prim[4] = np.where(r < R, 1e-6, 0.0)
-    pr = P.Problem("cold_sphere", shape, h, 5 / 3, 0.4, (P.OUTFLOW,) * 6, prim, grav=G, rho_vac=1e-7)
     o = oracle_sim(pr)
     for _ in range(3):
         o.step(dt_max=0.01)
@@ -207,6 +202,18 @@ def test_cold_sphere_falls_in_at_the_newtonian_rate():
     ratio = ur[sel] / (-(4 / 3) * math.pi * G * r[sel] * t)
     assert abs(ratio.mean() - 1.0) <= 0.01
     assert np.all(np.abs(ratio - 1.0) <= 0.03)
+
+
+def test_potential_at_sampled_cells():
+    n = 10
+    o = O.OracleSim((n, 8, 6), 0.1, bc=(P.OUTFLOW,) * 6, grav=0.8)
+    rho = np.random.default_rng(4).uniform(0.1, 2.0, (6, 8, n))
+    full = o.self_potential(rho)
+    cells = [(0, 0, 0), (9, 7, 5), (3, 4, 2)]
+    got = o.self_potential_at(rho, cells)
+    assert np.array_equal(got, [full[k, j, i] for i, j, k in cells])
+    with pytest.raises(O.OracleError):
+        o.self_potential_at(rho, [(10, 0, 0)])
 
 
 def test_self_gravity_box_classes():
