@@ -178,6 +178,28 @@ def run_large(n=1024, steps=10, warmup=2, tile_depth=0):
                         "and boundaries on a 64x larger grid; state filled on the device)"}
 
 
+def run_share(n=256, gpus=8, steps=100, warmup=5):
+    """One GPU's share of the n^3 potential-well flow split into `gpus` z-slabs:
+    n/gpus owned planes plus 3 overlap planes on either side (one step reads
+    U^n at most 3 cells away, so the owned planes advance exactly as in the
+    whole grid), z faces OUTFLOW standing in for the halo.  Only the owned cells
+    count as cell-updates; the overlap planes are the redundant halo compute."""
+    from paper_1912_04855_amd import problems as P
+    planes, overlap = n // gpus, 3
+    pr = P.z_slab(P.well_flow(n), 0, planes, overlap)
+    r = run_gpu(pr, "f32", steps, warmup)  # its own tile depths: 38 planes, not 256
+    owned = n * n * planes
+    halo = 2 * overlap * 5 * n * n * 4  # U^n planes received per step (both neighbours), FP32
+    return {"value": round(owned * steps / (r["event_ms"] * 1e-3), 1), "unit": "cell-updates/s",
+            "ms_per_step": round(r["event_ms"] / steps, 4), "steps": steps, "shape": list(pr.shape),
+            "owned_cells": owned, "dtype": "f32", "tile": _tile(r["tile_depth"]),
+            "halo_bytes_per_step": halo,
+            "kernels_ms": {k: round(v[0], 5) for k, v in r["profile"].items()},
+            "workload": f"one GPU's share of the potential-well flow {n}^3 in {gpus} z-slabs: "
+                        f"{planes} owned planes + {overlap} overlap planes each side "
+                        f"({n}x{n}x{planes + 2 * overlap}); the halo exchange itself is not run"}
+
+
 def _counters(kernel, dtype, cells):
     """rocprofv3 counter summary of this kernel build and workload, if one was
     taken of the current kernel source (else None)."""
@@ -485,6 +507,8 @@ def main():
                     help="mean arrival rate of the serving workload (requests per second)")
     ap.add_argument("--no-cloud", action="store_true", help="skip the gas-vacuum cloud workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 well-flow workload")
+    ap.add_argument("--no-share", action="store_true",
+                    help="skip one GPU's z-slab share of the well flow (8 slabs)")
     ap.add_argument("--cloud-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for the HBM "
@@ -568,6 +592,13 @@ def main():
             del prc
         except Exception as e:
             out["cloud"] = {"error": repr(e)}
+    if not args.no_share:
+        log(f"[bench] one GPU's z-slab share of the {args.n}^3 well flow (8 slabs)")
+        try:
+            out["share"] = run_share(args.n, 8, args.steps, args.warmup)
+            log(f"[bench] share: {out['share']['value']:.3e} owned cell-updates/s")
+        except Exception as e:
+            out["share"] = {"error": repr(e)}
     if not args.no_large:
         log("[bench] potential-well flow 1024^3 f32: 10 steps")
         try:

@@ -218,6 +218,33 @@ def cold_sphere(n=16, R=0.3, G=1.0, rho_in=1.0, p_in=1e-6, gamma=5.0 / 3.0, cfl=
                    rho_vac=rho_vac * rho_in)
 
 
+def z_cut(arr, k0: int, planes: int, overlap: int = 3) -> np.ndarray:
+    """Planes k0 - overlap .. k0 + planes + overlap - 1 of a z-periodic array
+    [..., nz, ny, nx], taken through the periodic wrap."""
+    nz = arr.shape[-3]
+    ks = np.arange(k0 - overlap, k0 + planes + overlap) % nz
+    return np.ascontiguousarray(np.take(arr, ks, axis=-3))
+
+
+def z_slab(prob: Problem, k0: int, planes: int, overlap: int = 3) -> Problem:
+    """One GPU's share of a z-periodic problem split into z-slabs: the owned
+    planes k0 .. k0+planes-1 plus ``overlap`` planes on either side taken
+    through the periodic wrap, with OUTFLOW z faces standing in for the halo.
+    One step of the method reads U^n at most 3 cells away along an axis, so
+    with overlap >= 3 the owned planes advance exactly as in the whole grid
+    (given the same dt); afterwards the overlap planes are stale and would be
+    refreshed from the neighbours."""
+    assert prob.bc[4] == PERIODIC and prob.bc[5] == PERIODIC
+    nx, ny, nz = prob.shape
+    shape = (nx, ny, planes + 2 * overlap)
+    bc = prob.bc[:4] + (OUTFLOW, OUTFLOW)
+    psi = None if prob.psi is None else z_cut(prob.psi, k0, planes, overlap)
+    origin = (prob.origin[0], prob.origin[1], prob.origin[2] + (k0 - overlap) * prob.h)
+    return Problem(prob.name + "_slab", shape, prob.h, prob.gamma, prob.cfl, bc,
+                   z_cut(prob.prim, k0, planes, overlap), psi, inflow=dict(prob.inflow),
+                   origin=origin, rho_vac=prob.rho_vac, nu=prob.nu)
+
+
 # --------------------------------------------------------------------------
 # point blast
 # --------------------------------------------------------------------------
