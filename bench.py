@@ -200,6 +200,30 @@ def run_share(n=256, gpus=8, steps=100, warmup=5):
                         f"({n}x{n}x{planes + 2 * overlap}); the halo exchange itself is not run"}
 
 
+def run_gravity(n=256, steps=50, warmup=3, tile_depth=0, boxes=("periodic", "isolated")):
+    """The self-gravity extension on an n^3 FP32 grid: the seeded smooth state
+    (rho, p in [0.7, 1.3], |u| <= 0.3, a smooth external potential) with G = 1,
+    once on a periodic box (spectral solve of the discrete Poisson equation) and
+    once with every face OUTFLOW (the free-space potential through the box
+    zero-padded to 2n per axis).  Per box: time per step and the self-gravity
+    group's time (the Poisson solve and the ghosts of its two potentials)."""
+    from paper_1912_04855_amd import problems as P
+    out = {}
+    for name, bc in (("periodic", None), ("isolated", (P.OUTFLOW,) * 6)):
+        if name not in boxes:
+            continue
+        pr = P.smooth_state((n, n, n), seed=3, bc=bc)
+        pr.grav = 1.0
+        r = run_gpu(pr, "f32", steps, warmup, autotune=False, tile_depth=tile_depth)
+        out[name] = {"value": round(pr.cells * steps / (r["event_ms"] * 1e-3), 1), "unit": "cell-updates/s",
+                     "ms_per_step": round(r["event_ms"] / steps, 4), "steps": steps,
+                     "self_gravity_ms": round(r["profile"]["self_gravity"][0], 4),
+                     "kernels_ms": {k: round(v[0], 5) for k, v in r["profile"].items()}}
+    out["workload"] = (f"self-gravitating smooth state {n}^3 FP32, G = 1: periodic box and isolated "
+                       "box (every face OUTFLOW)")
+    return out
+
+
 def _counters(kernel, dtype, cells):
     """rocprofv3 counter summary of this kernel build and workload, if one was
     taken of the current kernel source (else None)."""
@@ -507,6 +531,11 @@ def main():
                     help="mean arrival rate of the serving workload (requests per second)")
     ap.add_argument("--no-cloud", action="store_true", help="skip the gas-vacuum cloud workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 well-flow workload")
+    ap.add_argument("--no-gravity", action="store_true",
+                    help="skip the self-gravity workload (periodic and isolated boxes)")
+    ap.add_argument("--gravity-only", action="store_true",
+                    help="only the self-gravity workload, --steps steps (for profiling)")
+    ap.add_argument("--gravity-box", default="both", choices=["both", "periodic", "isolated"])
     ap.add_argument("--no-share", action="store_true",
                     help="skip one GPU's z-slab share of the well flow (8 slabs)")
     ap.add_argument("--cloud-steps", type=int, default=50)
@@ -536,6 +565,11 @@ def main():
     if args.batch_only:
         r = run_batch(count=args.batch_count, steps=args.steps, tile_depth=args.batch_tile_depth)
         print(json.dumps({"batched": r}), flush=True)
+        return
+    if args.gravity_only:
+        boxes = ("periodic", "isolated") if args.gravity_box == "both" else (args.gravity_box,)
+        r = run_gravity(args.n, args.steps, args.warmup, tile_depth=args.tile_depth, boxes=boxes)
+        print(json.dumps({"gravity": r}), flush=True)
         return
     pr = P.well_flow(args.n, steps=args.steps)
     cells = pr.cells
@@ -592,6 +626,14 @@ def main():
             del prc
         except Exception as e:
             out["cloud"] = {"error": repr(e)}
+    if not args.no_gravity:
+        log(f"[bench] self-gravity {args.n}^3 f32: periodic and isolated boxes")
+        try:
+            out["gravity"] = run_gravity(args.n, 50, 3, tile_depth=r["tile_depth"])
+            log(f"[bench] gravity: periodic {out['gravity']['periodic']['ms_per_step']} ms/step, "
+                f"isolated {out['gravity']['isolated']['ms_per_step']} ms/step")
+        except Exception as e:
+            out["gravity"] = {"error": repr(e)}
     if not args.no_share:
         log(f"[bench] one GPU's z-slab share of the {args.n}^3 well flow (8 slabs)")
         try:

@@ -169,17 +169,18 @@ class Sim:
         check(_lib.load().csph_totals(self._h, _ptr(out)), "csph_totals")
         return out
 
-    PROFILE_GROUPS = ["stage_p", "stage_c", "stage_e", "ghost_fill", "bookkeeping"]
+    PROFILE_GROUPS = ["stage_p", "stage_c", "stage_e", "ghost_fill", "bookkeeping", "self_gravity"]
 
     def profile(self, on=True):
         check(_lib.load().csph_profile_enable(self._h, int(bool(on))), "csph_profile_enable")
 
     def profile_read(self):
         """{group: (average ms per launch, launches)} of the steps since profile(True)."""
-        ms = np.zeros(5)
-        n = np.zeros(5, dtype=np.int64)
-        check(_lib.load().csph_profile_read(self._h, _ptr(ms), _ptr(n), 5), "csph_profile_read")
-        return {g: (float(ms[q]), int(n[q])) for q, g in enumerate(self.PROFILE_GROUPS)}
+        k = len(self.PROFILE_GROUPS)
+        ms = np.zeros(k)
+        n = np.zeros(k, dtype=np.int64)
+        check(_lib.load().csph_profile_read(self._h, _ptr(ms), _ptr(n), k), "csph_profile_read")
+        return {g: (float(ms[q]), int(n[q])) for q, g in enumerate(self.PROFILE_GROUPS) if n[q] or q < 5}
 
     # ------------------------------------------------------------------ scheme
     def set_scheme(self, limiter=_lib.LIM_MINMOD, flux=_lib.FLUX_SWEPT_AV):
