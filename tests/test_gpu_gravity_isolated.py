@@ -77,6 +77,27 @@ def test_isolated_one_step_fp32():
     g.close()
 
 
+@pytest.mark.parametrize("shape,bc", [((4096, 4, 4), None), ((2048, 4, 4), BC_OUT)],
+                         ids=["periodic4096", "isolated2048"])
+def test_radix2_lds_path_fp32(shape, bc):
+    # transform lengths above 2048 (FP32 only) take the radix-2 FFT in LDS
+    # instead of the register FFT: a periodic axis of 4096, an isolated axis of
+    # 2048 (padded to 4096)
+    need_gpu()
+    pr = _random(shape, seed=12, bc=bc or (P.PERIODIC,) * 6)
+    o = oracle_sim(pr)
+    o.step()
+    announce("radix2_lds_path_fp32", shape)
+    g = gpu_sim(pr, "f32")
+    g.step()
+    for f in ("psi", "psih"):
+        a, b = g.stage(f), o.field(f)
+        err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+        print(f"radix-2 path {shape}: {f} max error / max |psi| = {err:.2e}")
+        assert err <= 1e-6, f  # measured 1e-7
+    g.close()
+
+
 def test_cold_sphere_many_steps_fp64():
     need_gpu()
     pr = P.cold_sphere(16, R=0.3, G=1.0)
