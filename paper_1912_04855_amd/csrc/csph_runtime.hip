@@ -553,7 +553,8 @@ int periodic_faces(const csph_sim* s) {
   return np;
 }
 
-// allocate and fill the Poisson solve's buffers and tables (once per sim)
+// allocate and fill the Poisson solve's buffers and tables (once per sim); on
+// failure the caller releases what was allocated (grav_release)
 template <typename Real>
 csph_status grav_setup(csph_sim* s) {
   Grav<Real>& gr = grav_of<Real>(s);
@@ -618,9 +619,6 @@ csph_status grav_setup(csph_sim* s) {
     double* tmp = nullptr;
     if (hipMalloc((void**)&tmp, 2 * octant * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
-      (void)hipFree(s->gbuf);
-      s->gbuf = nullptr;
-      gr = Grav<Real>{};
       return fail(CSPH_ERR_NOMEM, "hipMalloc of the Green's function scratch failed");
     }
     const double* ctab[3];
@@ -628,22 +626,30 @@ csph_status grav_setup(csph_sim* s) {
     hipError_t e = Poisson<Real>::green(gr, s->g.h, tmp, ctab, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(tmp);
-    if (e != hipSuccess) {
-      (void)hipStreamSynchronize(s->stream);
-      (void)hipFree(s->gbuf);
-      s->gbuf = nullptr;
-      gr = Grav<Real>{};
-      return fail(CSPH_ERR_DEVICE, std::string("the Green's function: ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return fail(CSPH_ERR_DEVICE, std::string("the Green's function: ") + hipGetErrorString(e));
   }
   return CSPH_OK;
+}
+
+// the solve's device memory and tables released (after a failed set-up too)
+template <typename Real>
+void grav_release(csph_sim* s) {
+  (void)hipStreamSynchronize(s->stream);
+  if (s->gbuf) (void)hipFree(s->gbuf);
+  s->gbuf = nullptr;
+  s->grav_iso = false;
+  grav_of<Real>(s) = Grav<Real>{};
 }
 
 template <typename Real>
 csph_status grav_on(csph_sim* s, double G) {
   if (!s->gbuf) {
     csph_status st = grav_setup<Real>(s);
-    if (st) return st;
+    if (st) {
+      // a failure part-way leaves no half-built tables behind for the next call
+      grav_release<Real>(s);
+      return st;
+    }
   }
   Grav<Real>& gr = grav_of<Real>(s);
   Fields<Real>& F = fields_of<Real>(s);
@@ -682,11 +688,7 @@ csph_status grav_off(csph_sim* s) {
   if (!s->has_psi) HIP_TRY(hipMemsetAsync(F.psis, 0, s->L.field_bytes, s->stream));
   s->g.psi = s->has_psi ? 1 : 0;
   s->psi_dirty = true;
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  (void)hipFree(s->gbuf);
-  s->gbuf = nullptr;
-  s->grav_iso = false;
-  grav_of<Real>(s) = Grav<Real>{};
+  grav_release<Real>(s);
   return CSPH_OK;
 }
 
