@@ -584,7 +584,9 @@ int orc_set_potential(orc_sim* s, const double* psi) {
  *   lambda(k) = sum_d (2 cos(2 pi k_d / n_d) - 2) / h^2,
  * so psi_k = 4 pi G rho_k / lambda(k) for k != 0 and psi_0 = 0 (the mean density
  * has no potential on a periodic box).  The transforms are plain O(n^2) sums
- * along each axis. */
+ * along each axis.  A box with no periodic face (gas in vacuum) takes the
+ * free-space potential of its cells instead (free_space below); a box with
+ * some periodic faces and some not is refused. */
 
 #define ORC_PI 3.14159265358979323846
 
