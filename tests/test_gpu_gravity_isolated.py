@@ -115,6 +115,45 @@ def test_cold_sphere_many_steps_fp64():
     g.close()
 
 
+def _cycloid_density(t, G=1.0, rho=1.0):
+    """Density of a pressureless uniform sphere collapsing from rest: r = r0
+    cos^2 b with b + sin b cos b = (pi/2) t / t_ff, t_ff = sqrt(3 pi / (32 G
+    rho)), so rho(t) = rho / cos^6 b."""
+    tau = 0.5 * math.pi * t / math.sqrt(3 * math.pi / (32 * G * rho))
+    lo, hi = 0.0, 0.5 * math.pi
+    for _ in range(200):
+        b = 0.5 * (lo + hi)
+        if b + math.sin(b) * math.cos(b) < tau:
+            lo = b
+        else:
+            hi = b
+    return rho / math.cos(0.5 * (lo + hi)) ** 6
+
+
+def test_cold_sphere_collapse_at_scale_fp32():
+    # the free-fall collapse of a cold uniform sphere to half its free-fall time
+    # on a 128^3 isolated box: the centre's density follows the exact cycloid
+    # (homologous collapse, rho = 1.707 at t = t_ff / 2)
+    need_gpu()
+    n, G = 128, 1.0
+    pr = P.cold_sphere(n, R=0.3, G=G)
+    t_end = 0.5 * math.sqrt(3 * math.pi / (32 * G))
+    announce("cold_sphere_collapse_fp32", n)
+    g = gpu_sim(pr, "f32")
+    while g.time()[0] < t_end:
+        g.step(dt_max=min(2e-3, t_end - g.time()[0]))
+    assert g.time()[0] == pytest.approx(t_end, rel=1e-6)
+    rho = g.conserved()[0]
+    g.close()
+    c = n // 2
+    core = rho[c - 4:c + 4, c - 4:c + 4, c - 4:c + 4]
+    want = _cycloid_density(t_end, G)
+    print(f"cold sphere 128^3 at t_ff/2: centre density {core.mean():.4f} (spread "
+          f"{core.max() - core.min():.1e}), cycloid {want:.4f}")
+    assert abs(core.mean() - want) <= 0.005 * want  # measured 0.13%
+    assert core.max() - core.min() <= 0.003 * want  # still uniform (homologous): measured 0.06%
+
+
 @pytest.mark.parametrize("n,dtype", [(256, "f32"), (128, "f64")])
 def test_isolated_potential_at_size(n, dtype):
     # the benchmark's grid: the GPU's potential at sampled cells (corners, the
