@@ -480,7 +480,7 @@ def _oracle_batch_member(args):
 
 def cpu_box(instances=32, steps=4, master=0, batch_count=512, batch_steps=100):
     """The multi-instance comparator of the batched workload: one oracle process
-    per host core (at most 16, this host's share of a one-GPU machine) on the first
+    per host core (at most 16, the CPU share that comes with one GPU) on the first
     `instances` members of the batch, `steps` steps each; the aggregate rate is
     extrapolated to the whole batch (batch_count members, batch_steps steps)."""
     import multiprocessing as mp
