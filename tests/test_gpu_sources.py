@@ -186,12 +186,15 @@ def test_source_refusals():
     s.close()
 
 
+@pytest.mark.parametrize("box", ["periodic", "isolated"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_all_extensions_together(dtype):
-    # viscosity, self-gravity and sources and sinks on one periodic grid with an
-    # external potential, against the oracle
+def test_all_extensions_together(dtype, box):
+    # viscosity, self-gravity and sources and sinks on one grid with an external
+    # potential, against the oracle: a periodic box, and an isolated one (every
+    # face OUTFLOW, the free-space potential)
     need_gpu()
-    pr = P.random_state((16, 12, 8), seed=17, potential=True)
+    pr = P.random_state((16, 12, 8), seed=17, potential=True,
+                        bc=(P.OUTFLOW,) * 6 if box == "isolated" else None)
     pr.nu = 0.01
     pr.grav = 0.4
     pr.src = _rates((8, 12, 16), 18)
@@ -199,11 +202,11 @@ def test_all_extensions_together(dtype):
     o = oracle_sim(pr)
     for _ in range(30):
         o.step()
-    announce("all_extensions", dtype)
+    announce("all_extensions", dtype, box)
     g = gpu_sim(pr, dtype)
     assert g.advance(math.inf, 30) == 30
     err = rel_l1_vars(g.conserved(), o.conserved())
-    print(f"viscosity + gravity + sources {dtype}: relative L1 vs oracle after 30 steps = {err:.3e}")
+    print(f"viscosity + gravity + sources {dtype} {box}: relative L1 vs oracle after 30 steps = {err:.3e}")
     assert err <= (1e-11 if dtype == "f64" else 2e-5)
     assert g.time()[0] == pytest.approx(o.time()[0], rel=1e-12 if dtype == "f64" else 1e-5)
     g.close()
