@@ -150,7 +150,10 @@ csph_status csph_set_potential(csph_sim* sim, const double* host_psi);
 
 /* Boundary rule of one face: 0..5 = -x, +x, -y, +y, -z, +z.  PERIODIC must be set
  * on both faces of an axis before stepping.  inflow_prim = (rho, u, v, w, p) is
- * read only for CSPH_INFLOW (a Dirichlet state whose particles move by u dt). */
+ * read only for CSPH_INFLOW (a Dirichlet state whose particles move by u dt).
+ * CSPH_ERR_ARG for a bad face or kind, a batch member, or (while self-gravity is
+ * on) a kind that would change the box's class: PERIODIC on an isolated box, any
+ * other kind on a periodic one. */
 csph_status csph_set_boundary(csph_sim* sim, int32_t face, csph_bc kind,
                               const double inflow_prim[5]);
 
