@@ -396,6 +396,85 @@ __device__ __forceinline__ void stockham(Real* re, Real* im, int n, int W, const
   }
 }
 
+// The same passes with the line length, the tile width and each pass's stride
+// known at compile time, so that every LDS offset of a pass is a constant from
+// one base: the register FFT for the lengths the grids use most.  The sequence
+// of radices and the arithmetic are those of stockham(), step for step.
+template <int R, int kSg, int kN, int kW, int kNs>
+__device__ __forceinline__ void stockham_pass_ct(Real* re, Real* im, int w, int tl, bool active,
+                                                 const Real* __restrict__ tw) {
+  constexpr int kT = kN / kEl, kP = kW + 1, kU = kEl / R, kNR = kN / R;
+  Real vr[kU][R], vi[kU][R];
+  if (active) {
+    const int b0 = tl * kP + w;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vr[u][r] = re[b0 + (u * kT + r * kNR) * kP];
+        vi[u][r] = im[b0 + (u * kT + r * kNR) * kP];
+      }
+      if constexpr (kNs > 1) {
+        const int jm = (tl + u * kT) & (kNs - 1);
+        const int step = jm * (kN / (kNs * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int k = step * r;
+          const Real c = tw[2 * k], sn = (Real)kSg * tw[2 * k + 1];
+          const Real xr = vr[u][r], xi = vi[u][r];
+          vr[u][r] = c * xr - sn * xi;
+          vi[u][r] = c * xi + sn * xr;
+        }
+      }
+      dft_reg<R, kSg>(vr[u], vi[u]);
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = tl + u * kT;
+      const int jm = j & (kNs - 1);
+      const int sb = ((j - jm) * R + jm) * kP + w;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        re[sb + r * kNs * kP] = vr[u][r];
+        im[sb + r * kNs * kP] = vi[u][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int kSg, int kN, int kW, int kNs>
+__device__ __forceinline__ void stockham_ct_from(Real* re, Real* im, int w, int tl, bool active,
+                                                 const Real* __restrict__ tw) {
+  if constexpr (kNs < kN) {
+    constexpr int kRem = kN / kNs;
+    constexpr int R = kRem > kEl ? kEl : kRem;
+    stockham_pass_ct<R, kSg, kN, kW, kNs>(re, im, w, tl, active, tw);
+    stockham_ct_from<kSg, kN, kW, kNs * R>(re, im, w, tl, active, tw);
+  }
+}
+
+template <int kSg, int kN, int kW>
+__device__ __forceinline__ void stockham_ct(Real* re, Real* im, const Real* __restrict__ tw) {
+  const int t = threadIdx.x;
+  const int w = t & (kW - 1), tl = t / kW;
+  stockham_ct_from<kSg, kN, kW, 1>(re, im, w, tl, tl < kN / kEl, tw);
+}
+
+// the register FFT of the tile: a compile-time shape where one exists (the
+// widths lines() gives these lengths), else the general passes
+template <int kSg>
+__device__ __forceinline__ void stockham_any(Real* re, Real* im, int n, int W, const Real* __restrict__ tw) {
+  if (n == 512 && W == 4) stockham_ct<kSg, 512, 4>(re, im, tw);
+  else if (n == 256 && W == 8) stockham_ct<kSg, 256, 8>(re, im, tw);
+  else if (n == 128 && W == 16) stockham_ct<kSg, 128, 16>(re, im, tw);
+  else if (n == 1024 && W == 2) stockham_ct<kSg, 1024, 2>(re, im, tw);
+  else stockham<kSg>(re, im, n, W, tw);
+}
+
 template <int kPass>
 __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const Ctrl* __restrict__ ctrl,
                                                 Grav<Real> gr, int W) {
@@ -488,7 +567,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
   constexpr bool kFwd = kPass == kXFwd || kPass == kYFwd;
   if (fast) {
     if constexpr (kPass == kZ) {
-      stockham<-1>(re, im, n, W, tw);
+      stockham_any<-1>(re, im, n, W, tw);
       for (int idx = t; idx < tile; idx += NT) {
         int kz, w;
         dW(idx, kz, w);
@@ -497,9 +576,9 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
         im[kz * P + w] *= f;
       }
       __syncthreads();
-      stockham<1>(re, im, n, W, tw);
+      stockham_any<1>(re, im, n, W, tw);
     } else {
-      stockham<kFwd ? -1 : 1>(re, im, n, W, tw);
+      stockham_any<kFwd ? -1 : 1>(re, im, n, W, tw);
     }
   } else if constexpr (kPass == kZ) {
     // forward, times the Green's function 4 pi G / (lambda(k) N), inverse; slot
