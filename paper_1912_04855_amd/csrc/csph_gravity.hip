@@ -475,6 +475,12 @@ __device__ __forceinline__ void stockham_any(Real* re, Real* im, int n, int W, c
   else stockham<kSg>(re, im, n, W, tw);
 }
 
+// the tile shapes with a compile-time register FFT (stockham_any); their tiles
+// hold n W = NT kEl values, kEl per thread
+__device__ __forceinline__ bool ct_shape(int n, int W) {
+  return (n == 512 && W == 4) || (n == 256 && W == 8) || (n == 128 && W == 16) || (n == 1024 && W == 2);
+}
+
 template <int kPass>
 __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const Ctrl* __restrict__ ctrl,
                                                 Grav<Real> gr, int W) {
@@ -537,28 +543,67 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
       im[s * P + w] = vi;
     }
   } else if constexpr (kPass == kXInv) {
-    for (int idx = t; idx < tile; idx += NT) {
-      int w, e;
-      dn(idx, w, e);
-      Real2 v;
-      v.x = 0;
-      v.y = 0;
-      if (w < q.nl) v = cw[xline(w) + e];
-      const int s = rev ? bit_reverse(e, log2n) : e;
-      re[s * P + w] = v.x;
-      im[s * P + w] = v.y;
+    if (fast && ct_shape(n, W)) {
+      // kEl elements per thread: their loads in flight together, then to LDS
+      Real2 v[kEl];
+#pragma unroll
+      for (int r = 0; r < kEl; ++r) {
+        int w, e;
+        dn(t + r * NT, w, e);
+        v[r].x = 0;
+        v[r].y = 0;
+        if (w < q.nl) v[r] = cw[xline(w) + e];
+      }
+#pragma unroll
+      for (int r = 0; r < kEl; ++r) {
+        int w, e;
+        dn(t + r * NT, w, e);
+        re[e * P + w] = v[r].x;
+        im[e * P + w] = v[r].y;
+      }
+    } else {
+      for (int idx = t; idx < tile; idx += NT) {
+        int w, e;
+        dn(idx, w, e);
+        Real2 v;
+        v.x = 0;
+        v.y = 0;
+        if (w < q.nl) v = cw[xline(w) + e];
+        const int s = rev ? bit_reverse(e, log2n) : e;
+        re[s * P + w] = v.x;
+        im[s * P + w] = v.y;
+      }
     }
   } else {
-    for (int idx = t; idx < tile; idx += NT) {
-      int e, w;
-      dW(idx, e, w);
-      Real2 v;
-      v.x = 0;
-      v.y = 0;
-      if (w < q.nl && e < q.nin) v = cw[q.base + w + (long long)e * q.es];
-      const int s = rev ? bit_reverse(e, log2n) : e;
-      re[s * P + w] = v.x;
-      im[s * P + w] = v.y;
+    if (fast && ct_shape(n, W)) {
+      Real2 v[kEl];
+#pragma unroll
+      for (int r = 0; r < kEl; ++r) {
+        int e, w;
+        dW(t + r * NT, e, w);
+        v[r].x = 0;
+        v[r].y = 0;
+        if (w < q.nl && e < q.nin) v[r] = cw[q.base + w + (long long)e * q.es];
+      }
+#pragma unroll
+      for (int r = 0; r < kEl; ++r) {
+        int e, w;
+        dW(t + r * NT, e, w);
+        re[e * P + w] = v[r].x;
+        im[e * P + w] = v[r].y;
+      }
+    } else {
+      for (int idx = t; idx < tile; idx += NT) {
+        int e, w;
+        dW(idx, e, w);
+        Real2 v;
+        v.x = 0;
+        v.y = 0;
+        if (w < q.nl && e < q.nin) v = cw[q.base + w + (long long)e * q.es];
+        const int s = rev ? bit_reverse(e, log2n) : e;
+        re[s * P + w] = v.x;
+        im[s * P + w] = v.y;
+      }
     }
   }
   __syncthreads();
