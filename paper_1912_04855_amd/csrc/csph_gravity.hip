@@ -654,8 +654,10 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
   __syncthreads();
 
   // ------------------------------------------------------------------ store
-  if constexpr (kPass == kXFwd) {
-    for (int idx = t; idx < tile; idx += NT) {
+  // element idx of the tile to memory; the compile-time FFT shapes unroll the
+  // kEl elements of a thread so that their reads are issued together
+  auto store = [&](int idx) {
+    if constexpr (kPass == kXFwd) {
       int w, e;
       dn(idx, w, e);
       if (w < q.nl) {
@@ -664,10 +666,7 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
         v.y = im[e * P + w];
         cw[xline(w) + e] = v;
       }
-    }
-  } else if constexpr (kPass == kXInv) {
-    const Real* __restrict__ pe = gr.psi_ext;
-    for (int idx = t; idx < tile; idx += NT) {
+    } else if constexpr (kPass == kXInv) {
       int w, e;
       dn(idx, w, e);
       if (w < q.nl && e < q.nout) {
@@ -676,13 +675,11 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
         dny(l, kq, jj);
         const int kk = q.k + kq;
         const long long c = cell(g, e, jj, kk);
-        const Real ext = pe[c];
+        const Real ext = gr.psi_ext[c];
         F.psi[c] = ext + re[e * P + w];
         gr.psih[c] = ext + im[e * P + w];
       }
-    }
-  } else {
-    for (int idx = t; idx < tile; idx += NT) {
+    } else {
       int e, w;
       dW(idx, e, w);
       if (w < q.nl && e < q.nout) {
@@ -692,6 +689,12 @@ __global__ void __launch_bounds__(NT) k_poisson(Fields<Real> F, GridDev g, const
         cw[q.base + w + (long long)e * q.es] = v;
       }
     }
+  };
+  if (fast && ct_shape(n, W)) {
+#pragma unroll
+    for (int r = 0; r < kEl; ++r) store(t + r * NT);
+  } else {
+    for (int idx = t; idx < tile; idx += NT) store(idx);
   }
 }
 
